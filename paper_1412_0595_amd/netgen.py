@@ -1,0 +1,206 @@
+"""Seeded synthetic spiking networks shaped like the paper's layered models.
+
+This module only draws inputs: population sizes, Bernoulli CSR connectivity
+(Compressed Row Storage, Section 3: values along the pre-synaptic index, the
+post-synaptic index of each value, and the start of every pre-synaptic row),
+uniform weights, per-instance conductance scales, Poisson seeds and loss
+targets.  It holds none of the simulation arithmetic, so both the FP64 oracle
+and the HIP library consume exactly the same arrays.
+
+The layered shape follows the insect-olfaction model of Section 5.1 (input
+projection neurons -> Kenyon cells -> detection neurons, called A -> B -> C
+here), with Poisson input sources (the model's non-deterministic inputs,
+Section 4 "Discussion").  The batched configuration is the conductance-scaling
+sweep of Section 2 ("a series of simulations in the likely range of the
+scaling factors") drawn as many uneven instances.
+
+A network spec is a plain dict::
+
+    {"dt": 0.1, "substeps": 3,
+     "instances": [{"g_scale": s, "seed": k,
+                    "pops":  [{"name", "kind": "poisson"|"hh", "n", "rate_hz", "i_ext"}],
+                    "projs": [{"pre", "post", "row_ptr" int32[n_pre+1],
+                               "col_idx" int32[nnz], "g" float32[nnz],
+                               "e_rev", "tau", "stdp": None | {...}}]}]}
+
+Units: mV, ms, uS, nA, Hz.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Conductance scales of the layered model (uS).  The paper fixes none of them;
+# they are chosen by its own criterion (a moderate spiking level with no NaNs).
+G0_AB = 0.1      # A->B: g = U[0,1) * G0_AB / (n_A * p_AB)
+G1_BC = 0.05     # B->C: g = U[0,1) * G1_BC / (n_B * p_BC)
+G_INH_CC = 0.0005  # C->C at n_C = 100: g = U[0,1) * G_INH_CC * 100 / n_C
+
+E_EXC, TAU_AB, TAU_BC = 0.0, 1.0, 5.0
+E_INH, TAU_CC = -92.0, 2.5
+
+# STDP of the plastic B->C projection (amplitudes in units of g_max)
+STDP_A_PLUS, STDP_A_MINUS, STDP_TAU = 0.01, 0.012, 20.0
+
+
+def bernoulli_csr(rng, n_pre, n_post, p, *, no_self=False, chunk_elems=1 << 24):
+    """Bernoulli(p) connectivity for every (pre, post) pair, as CSR with
+    ascending column indices in each row.  ``no_self`` drops i == j."""
+    if n_pre == 0 or n_post == 0:
+        return np.zeros(n_pre + 1, np.int32), np.zeros(0, np.int32)
+    counts = np.zeros(n_pre, np.int64)
+    cols = []
+    rows_per = max(1, chunk_elems // max(1, n_post))
+    for r0 in range(0, n_pre, rows_per):
+        r1 = min(n_pre, r0 + rows_per)
+        if p >= 1.0:
+            m = np.ones((r1 - r0, n_post), bool)
+        else:
+            m = rng.random((r1 - r0, n_post), dtype=np.float32) < np.float32(p)
+        if no_self:
+            idx = np.arange(r0, r1)
+            ok = idx < n_post
+            m[np.nonzero(ok)[0], idx[ok]] = False
+        counts[r0:r1] = m.sum(axis=1)
+        cols.append(np.nonzero(m)[1].astype(np.int32))
+    row_ptr = np.zeros(n_pre + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("projection too large for int32 CSR")
+    return row_ptr.astype(np.int32), (np.concatenate(cols) if cols else np.zeros(0, np.int32))
+
+
+def uniform_weights(rng, nnz, scale):
+    """g = U[0,1) * scale, stored as fp32 (uS)."""
+    return (rng.random(nnz) * scale).astype(np.float32)
+
+
+def layered_instance(rng, n_a, n_b, n_c, *, rate_hz=20.0, p_ab=0.5, p_bc=1.0,
+                     g_scale=1.0, seed=0, stdp_bc=False, i_ext=0.0):
+    """One A(Poisson) -> B(HH) -> C(HH) network with C->C all-to-all inhibition."""
+    pops = [dict(name="A", kind="poisson", n=int(n_a), rate_hz=float(rate_hz), i_ext=0.0),
+            dict(name="B", kind="hh", n=int(n_b), rate_hz=0.0, i_ext=float(i_ext)),
+            dict(name="C", kind="hh", n=int(n_c), rate_hz=0.0, i_ext=float(i_ext))]
+    rp, ci = bernoulli_csr(rng, n_a, n_b, p_ab)
+    ab = dict(pre=0, post=1, row_ptr=rp, col_idx=ci,
+              g=uniform_weights(rng, ci.size, G0_AB / (n_a * p_ab)),
+              e_rev=E_EXC, tau=TAU_AB, stdp=None)
+    rp, ci = bernoulli_csr(rng, n_b, n_c, p_bc)
+    g1 = G1_BC / (n_b * p_bc)
+    bc = dict(pre=1, post=2, row_ptr=rp, col_idx=ci, g=uniform_weights(rng, ci.size, g1),
+              e_rev=E_EXC, tau=TAU_BC, stdp=None)
+    if stdp_bc:
+        bc["stdp"] = dict(a_plus=STDP_A_PLUS, a_minus=STDP_A_MINUS, tau=STDP_TAU, g_max=g1)
+    rp, ci = bernoulli_csr(rng, n_c, n_c, 1.0, no_self=True)
+    cc = dict(pre=2, post=2, row_ptr=rp, col_idx=ci,
+              g=uniform_weights(rng, ci.size, G_INH_CC * 100.0 / n_c),
+              e_rev=E_INH, tau=TAU_CC, stdp=None)
+    return dict(g_scale=float(g_scale), seed=int(seed), pops=pops, projs=[ab, bc, cc])
+
+
+def instance_seed(key, i):
+    """Poisson key of instance i: every instance draws its own stream."""
+    return (int(key) << 20) | int(i)
+
+
+def _loguniform_int(rng, lo, hi, size):
+    return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size))).astype(np.int64)
+
+
+def make_config(k, *, n_instances=None, scale=1.0):
+    """Workloads 1..5 (dt = 0.1 ms, 3 Euler substeps).  Seeds: base = 1000*k,
+    +1 connectivity, +2 Poisson key, +3 instance sizes and g_scale, +4 target.
+
+    1: A=100 @20 Hz, B=1000, C=100; A->B p=0.5, B->C and C->C all-to-all.
+    2: A=1000 @20 Hz, B=20000, C=1000; p_AB=0.2, p_BC=0.5.
+    3: A=2000 @30 Hz, B=100000, C=1000; p_AB=0.2, p_BC=0.5 with pair STDP.
+    4: 256 instances, A~LU[200,1000], B~LU[2000,20000], C~LU[100,1000],
+       g_scale~LU[0.1,10], p=0.2/0.5.
+    5: 64 x (A=500, B=5000, C=200), p=0.2/0.5, plus a seeded target
+       y~U[-64,-58] mV per output neuron (returned under "target").
+
+    ``n_instances`` trims workloads 4 and 5; ``scale`` shrinks every
+    population (rounded, >= 2) for reduced-size tests.
+    """
+    base = 1000 * k
+    rng_c = np.random.default_rng(base + 1)
+    seed_key = base + 2
+    sz = lambda n: max(2, int(round(n * scale)))
+    spec = dict(dt=0.1, substeps=3, instances=[])
+    if k == 1:
+        spec["instances"].append(layered_instance(rng_c, sz(100), sz(1000), sz(100), rate_hz=20.0,
+                                                  p_ab=0.5, p_bc=1.0, seed=seed_key))
+        spec["steps"] = 10000
+    elif k == 2:
+        spec["instances"].append(layered_instance(rng_c, sz(1000), sz(20000), sz(1000), rate_hz=20.0,
+                                                  p_ab=0.2, p_bc=0.5, seed=seed_key))
+        spec["steps"] = 10000
+    elif k == 3:
+        spec["instances"].append(layered_instance(rng_c, sz(2000), sz(100000), sz(1000), rate_hz=30.0,
+                                                  p_ab=0.2, p_bc=0.5, seed=seed_key, stdp_bc=True))
+        spec["steps"] = 5000
+    elif k == 4:
+        n = 256 if n_instances is None else int(n_instances)
+        rng_s = np.random.default_rng(base + 3)
+        a = _loguniform_int(rng_s, 200, 1000, 256)[:n]
+        b = _loguniform_int(rng_s, 2000, 20000, 256)[:n]
+        c = _loguniform_int(rng_s, 100, 1000, 256)[:n]
+        gs = np.exp(rng_s.uniform(math.log(0.1), math.log(10.0), 256))[:n]
+        for i in range(n):
+            spec["instances"].append(layered_instance(rng_c, sz(a[i]), sz(b[i]), sz(c[i]), rate_hz=20.0,
+                                                      p_ab=0.2, p_bc=0.5, g_scale=float(gs[i]),
+                                                      seed=instance_seed(seed_key, i)))
+        spec["steps"] = 5000
+    elif k == 5:
+        n = 64 if n_instances is None else int(n_instances)
+        for i in range(n):
+            spec["instances"].append(layered_instance(rng_c, sz(500), sz(5000), sz(200), rate_hz=20.0,
+                                                      p_ab=0.2, p_bc=0.5, seed=instance_seed(seed_key, i)))
+        rng_t = np.random.default_rng(base + 4)
+        spec["target"] = [rng_t.uniform(-64.0, -58.0, inst["pops"][2]["n"]) for inst in spec["instances"]]
+        spec["steps"] = 2000
+        spec["ckpt_every"] = 100
+    else:
+        raise ValueError(f"unknown workload {k}")
+    return spec
+
+
+def random_tiny(seed, *, n_pops=3, max_n=64, p=0.3, n_poisson=1, rate_hz=200.0, stdp=False,
+                integer_g=False, g_scale=1.0):
+    """Small random network for brute-force checks: arbitrary sizes, empty rows,
+    all-to-all rows, self-projections.  ``integer_g`` draws g in {0,..,7} so
+    that every sum is exact in any order."""
+    rng = np.random.default_rng(seed)
+    pops = []
+    for i in range(n_pops):
+        kind = "poisson" if i < n_poisson else "hh"
+        pops.append(dict(name=f"P{i}", kind=kind, n=int(rng.integers(1, max_n + 1)),
+                         rate_hz=rate_hz if kind == "poisson" else 0.0, i_ext=0.0))
+    projs = []
+    for post in range(n_poisson, n_pops):
+        for pre in range(n_pops):
+            if rng.random() < 0.6 or pre == post - 1:
+                pp = p if rng.random() < 0.7 else 1.0
+                rp, ci = bernoulli_csr(rng, pops[pre]["n"], pops[post]["n"], pp)
+                if integer_g:
+                    g = rng.integers(0, 8, ci.size).astype(np.float32)
+                else:
+                    g = uniform_weights(rng, ci.size, 0.02)
+                e_rev = 0.0 if rng.random() < 0.7 else -92.0
+                projs.append(dict(pre=pre, post=post, row_ptr=rp, col_idx=ci, g=g, e_rev=e_rev,
+                                  tau=float(rng.choice([1.0, 2.5, 5.0])), stdp=None))
+    if stdp:
+        for pr in projs:
+            if pops[pr["pre"]]["kind"] == "hh":
+                pr["stdp"] = dict(a_plus=STDP_A_PLUS, a_minus=STDP_A_MINUS, tau=STDP_TAU,
+                                  g_max=float(pr["g"].max() if pr["g"].size else 0.02) * 1.5 + 1e-6)
+                break
+    return dict(dt=0.1, substeps=3, instances=[dict(g_scale=float(g_scale), seed=int(seed) + 77,
+                                                    pops=pops, projs=projs)])
+
+
+def forced_spikes(rng, n, frac):
+    """Seeded synthetic spike set: a sorted random subset of round(frac*n) ids."""
+    k = int(round(frac * n))
+    return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)

@@ -1,0 +1,243 @@
+"""Pins of the oracle's synapses, Poisson sources, STDP and network step.
+
+Propagation is checked against the dense representation (Eq. 2 layout)
+computed by a matrix product; Poisson draws against the published Philox
+known-answer vectors and Binomial statistics; STDP against a brute-force
+double sum over spike pairs; decay against its closed form.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1412_0595_amd import netgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(proj, n_pre, n_post):
+    w = np.zeros((n_pre, n_post))
+    rp, ci, g = proj["row_ptr"], proj["col_idx"], proj["g"]
+    for i in range(n_pre):
+        w[i, ci[rp[i]:rp[i + 1]]] += g[rp[i]:rp[i + 1]].astype(np.float64)
+    return w
+
+
+def test_philox_known_answers(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert list(orc.philox(v[0:4], v[4:6])) == v[6:10]
+
+
+def test_poisson_threshold(orc):
+    L = orc.lib()
+    assert L.orc_poisson_threshold(20.0, 0.1) == math.floor(0.002 * 2 ** 32)
+    assert L.orc_poisson_threshold(30.0, 0.1) == math.floor(0.003 * 2 ** 32)
+    assert L.orc_poisson_threshold(0.0, 0.1) == 0
+    assert L.orc_poisson_threshold(1e6, 0.1) == 2 ** 32
+
+
+def test_poisson_binomial_statistics(orc):
+    """Each source's count over T steps is Binomial(T, p): the pooled mean and
+    variance match T p and T p (1-p); lag-1 correlation of the population
+    count vanishes."""
+    n, T, rate = 2000, 3000, 200.0
+    inst = dict(g_scale=1.0, seed=12345, pops=[dict(name="A", kind="poisson", n=n, rate_hz=rate, i_ext=0.0)],
+                projs=[])
+    net = orc.OracleNet(inst, log_events=True)
+    net.step(T)
+    c = net.counts(0).astype(np.float64)
+    p = rate * 0.1e-3
+    mu, var = T * p, T * p * (1 - p)
+    assert abs(c.mean() - mu) < 4 * math.sqrt(var / n)
+    # sample variance of n draws: sd ~ var*sqrt(2/(n-1)) (normal approx)
+    assert abs(c.var(ddof=1) - var) < 5 * var * math.sqrt(2.0 / (n - 1))
+    t, _, _ = net.events()
+    per_step = np.bincount(t, minlength=T).astype(np.float64)
+    r = np.corrcoef(per_step[:-1], per_step[1:])[0, 1]
+    assert abs(r) < 4 / math.sqrt(T)
+    # another key gives another stream
+    inst2 = dict(inst, seed=12346)
+    net2 = orc.OracleNet(inst2)
+    net2.step(T)
+    assert not np.array_equal(net2.counts(0), net.counts(0).astype(np.int32))
+
+
+def _one_hh_step_delivery(orc, inst, spikes):
+    """Set S(-1) by hand and run one step; return G of every projection."""
+    net = orc.OracleNet(inst)
+    for p, flags in spikes.items():
+        net.set_last_spikes(p, flags)
+    net.step(1)
+    return net
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_propagation_matches_dense_product(orc, seed):
+    """After one step, G_p = d_p * g_scale * (W_p^T s) with W_p the dense
+    matrix of projection p and s the spike vector of step -1.  Integer g makes
+    every sum exact, so the comparison is bitwise."""
+    spec = netgen.random_tiny(seed, integer_g=True, g_scale=1.0)
+    inst = spec["instances"][0]
+    rng = np.random.default_rng(seed)
+    spikes = {p: (rng.random(pp["n"]) < 0.4).astype(np.uint8) for p, pp in enumerate(inst["pops"])}
+    spikes[0][:] = 1 if seed % 2 else spikes[0]          # all-spiking and none-spiking cases
+    if seed == 4:
+        for p in spikes:
+            spikes[p][:] = 0
+    net = _one_hh_step_delivery(orc, inst, spikes)
+    for q, pr in enumerate(inst["projs"]):
+        npre, npost = inst["pops"][pr["pre"]]["n"], inst["pops"][pr["post"]]["n"]
+        W = dense(pr, npre, npost)
+        d = math.exp(-0.1 / pr["tau"])
+        expect = (W.T @ spikes[pr["pre"]].astype(np.float64)) * d
+        assert np.array_equal(net.G(q), expect), q
+
+
+def test_propagation_scaled_float_weights(orc):
+    spec = netgen.random_tiny(11, integer_g=False, g_scale=2.7)
+    inst = spec["instances"][0]
+    rng = np.random.default_rng(3)
+    spikes = {p: (rng.random(pp["n"]) < 0.5).astype(np.uint8) for p, pp in enumerate(inst["pops"])}
+    net = _one_hh_step_delivery(orc, inst, spikes)
+    for q, pr in enumerate(inst["projs"]):
+        npre, npost = inst["pops"][pr["pre"]]["n"], inst["pops"][pr["post"]]["n"]
+        W = dense(pr, npre, npost)
+        expect = 2.7 * (W.T @ spikes[pr["pre"]]) * math.exp(-0.1 / pr["tau"])
+        assert np.allclose(net.G(q), expect, rtol=1e-14, atol=1e-18)
+
+
+def test_conductance_decay_closed_form(orc):
+    """A single delivered spike leaves G(k) = s g exp(-dt/tau)^(k+1) behind."""
+    rp = np.array([0, 1], np.int32)
+    inst = dict(g_scale=1.5, seed=1,
+                pops=[dict(name="A", kind="poisson", n=1, rate_hz=0.0, i_ext=0.0),
+                      dict(name="B", kind="hh", n=1, rate_hz=0.0, i_ext=0.0)],
+                projs=[dict(pre=0, post=1, row_ptr=rp, col_idx=np.array([0], np.int32),
+                            g=np.array([0.25], np.float32), e_rev=0.0, tau=2.5, stdp=None)])
+    net = orc.OracleNet(inst)
+    net.set_last_spikes(0, np.array([1], np.uint8))
+    d = math.exp(-0.1 / 2.5)
+    for k in range(50):
+        net.step(1)
+        assert abs(net.G(0)[0] - 1.5 * 0.25 * d ** (k + 1)) < 1e-15
+    # excitatory input depolarised the neuron from rest, inhibitory would not
+    V = net.get(1, orc.V)[0]
+    assert V > orc.rest()[0]
+
+
+def test_inhibition_hyperpolarises(orc):
+    rp = np.array([0, 1], np.int32)
+    inst = dict(g_scale=1.0, seed=1,
+                pops=[dict(name="A", kind="poisson", n=1, rate_hz=0.0, i_ext=0.0),
+                      dict(name="B", kind="hh", n=1, rate_hz=0.0, i_ext=0.0)],
+                projs=[dict(pre=0, post=1, row_ptr=rp, col_idx=np.array([0], np.int32),
+                            g=np.array([0.05], np.float32), e_rev=-92.0, tau=2.5, stdp=None)])
+    net = orc.OracleNet(inst)
+    net.set_last_spikes(0, np.array([1], np.uint8))
+    net.step(5)
+    assert net.get(1, orc.V)[0] < orc.rest()[0] - 0.1
+
+
+def _pair_sum(pre_t, post_t, a_plus, a_minus, tau, dt, g_max, t_last):
+    """Sum over every (pre, post) spike pair with both times <= t_last of
+    +A+ gmax e^{-(tpost-tpre)dt/tau} (tpre <= tpost) and
+    -A- gmax e^{-(tpre-tpost)dt/tau} (tpost <= tpre)."""
+    tot = 0.0
+    for a in pre_t:
+        if a > t_last:
+            continue
+        for b in post_t:
+            if b > t_last:
+                continue
+            if a <= b:
+                tot += a_plus * g_max * math.exp(-(b - a) * dt / tau)
+            if b <= a:
+                tot -= a_minus * g_max * math.exp(-(a - b) * dt / tau)
+    return tot
+
+
+def test_stdp_equals_pair_sum(orc):
+    """With no clip binding, the trace rule's total change of every synapse
+    equals the explicit double sum over spike pairs (pairs at equal times
+    count in both directions).  Updates for spikes of the last step are not
+    applied yet (they act at the next step)."""
+    rng = np.random.default_rng(5)
+    n_a, n_b, n_c = 30, 12, 6
+    rp_ab, ci_ab = netgen.bernoulli_csr(rng, n_a, n_b, 0.5)
+    rp_bc, ci_bc = netgen.bernoulli_csr(rng, n_b, n_c, 0.7)
+    g_bc = (0.4 + 0.2 * rng.random(ci_bc.size)).astype(np.float32) * np.float32(0.05)
+    g_max = 0.05
+    st = dict(a_plus=0.002, a_minus=0.0024, tau=20.0, g_max=g_max)
+    inst = dict(g_scale=1.0, seed=99,
+                pops=[dict(name="A", kind="poisson", n=n_a, rate_hz=400.0, i_ext=0.0),
+                      dict(name="B", kind="hh", n=n_b, rate_hz=0.0, i_ext=0.0),
+                      dict(name="C", kind="hh", n=n_c, rate_hz=0.0, i_ext=0.0)],
+                projs=[dict(pre=0, post=1, row_ptr=rp_ab, col_idx=ci_ab,
+                            g=(rng.random(ci_ab.size) * 0.08).astype(np.float32), e_rev=0.0, tau=1.0, stdp=None),
+                       dict(pre=1, post=2, row_ptr=rp_bc, col_idx=ci_bc, g=g_bc, e_rev=0.0, tau=5.0, stdp=st)])
+    T = 1500
+    net = orc.OracleNet(inst, log_events=True)
+    net.step(T)
+    t, p, i = net.events()
+    assert (p == 1).sum() > 20 and (p == 2).sum() > 5
+    w = net.weights(1)
+    assert np.all(w > 0) and np.all(w < g_max)        # no clip bound
+    for r in range(n_b):
+        pre_t = t[(p == 1) & (i == r)]
+        for k in range(rp_bc[r], rp_bc[r + 1]):
+            j = ci_bc[k]
+            post_t = t[(p == 2) & (i == j)]
+            dw = _pair_sum(pre_t, post_t, st["a_plus"], st["a_minus"], 20.0, 0.1, g_max, T - 2)
+            assert abs((w[k] - float(g_bc[k])) - dw) < 1e-12, (r, j)
+
+
+def test_stdp_weights_stay_clipped(orc):
+    spec = netgen.make_config(1, scale=0.1)
+    inst = spec["instances"][0]
+    pr = inst["projs"][1]
+    pr["stdp"] = dict(a_plus=0.5, a_minus=0.6, tau=20.0, g_max=float(pr["g"].max()))
+    inst["g_scale"] = 3.0
+    net = orc.OracleNet(inst)
+    for _ in range(10):
+        net.step(200)
+        w = net.weights(1)
+        assert np.all(w >= 0.0) and np.all(w <= pr["stdp"]["g_max"])
+    assert np.any(w == 0.0) or np.any(w == pr["stdp"]["g_max"])
+
+
+def test_replay_of_own_raster_is_identical(orc):
+    """Feeding a population its own recorded spikes reproduces the run exactly."""
+    spec = netgen.make_config(1, scale=0.2)
+    inst = spec["instances"][0]
+    T = 600
+    a = orc.OracleNet(inst, log_events=True)
+    Va = a.trace(T, 2)
+    t, p, i = a.events()
+    n_pops = len(inst["pops"])
+    key = t.astype(np.int64) * n_pops + p
+    order = np.lexsort((i, key))
+    off = np.zeros(T * n_pops + 1, np.int64)
+    np.cumsum(np.bincount(key, minlength=T * n_pops), out=off[1:])
+    ids = i[order]
+    b = orc.OracleNet(inst)
+    b.set_replay(1, off, ids, T)
+    b.set_replay(2, off, ids, T)
+    Vb = b.trace(T, 2)
+    assert np.array_equal(Va, Vb)
+    assert np.array_equal(a.counts(1), b.counts(1))
+
+
+def test_layered_network_activity(orc):
+    """The small layered workload spikes at a moderate level without NaNs
+    (the calibration criterion of Section 2)."""
+    spec = netgen.make_config(1)
+    net = orc.OracleNet(spec["instances"][0])
+    net.step(3000)
+    assert net.nan_count == 0
+    for p in (1, 2):
+        hz = net.counts(p).mean() / 0.3
+        assert 2.0 < hz < 100.0
