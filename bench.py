@@ -1,0 +1,179 @@
+"""Benchmark of the spiking-network timestep on one MI355X.
+
+Default workload: A = 1000 Poisson sources at 20 Hz, B = 20000 and C = 1000
+Traub-Miles neurons, A->B p = 0.2, B->C p = 0.5, C->C all-to-all inhibitory
+(15.0 M synapses), dt = 0.1 ms with 3 Euler substeps.  A "step" is one
+timestep of the whole network: propagation of the previous step's spikes,
+the neuron update and spike compaction.
+
+Prints ONE JSON line: value = Traub-Miles neuron-steps per second over the
+timed steps (inputs already resident in HBM), plus synaptic events per
+second, the roofline of the dominant kernel (its per-launch time measured
+with hipEvents around each launch) and the FP64 oracle timed on a bounded
+sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_TFLOPS = 78.6      # MI355X fp64 vector peak (FMA = 2 flops)
+
+# Algorithmic traffic per unit (bytes), stated in the design notes:
+#  - propagation: 8 B per synaptic event (col_idx + weight) + 16 B per work
+#    item (the item itself) + 8 B per row (its two row-start entries)
+#  - neuron update: per Traub-Miles neuron-step, 4 double-float state
+#    variables read and written (64 B) + 16 B per incoming projection
+#    (64-bit conductance read and written)
+PROP_BYTES_PER_EVENT = 8
+NEURON_STATE_BYTES = 64
+NEURON_G_BYTES = 16
+
+WORKLOADS = {2: "A=1000 Poisson @20 Hz, B=20000 HH, C=1000 HH; A->B p=0.2, B->C p=0.5, C->C all-to-all "
+                "inhibitory; dt=0.1 ms, 3 Euler substeps"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--instances", type=int, default=None, help="trim a batched workload")
+    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=200)
+    return ap.parse_args()
+
+
+def out_degree_table(spec):
+    """Per instance, per population: total outgoing row length of each neuron."""
+    import numpy as np
+    tabs = []
+    for inst in spec["instances"]:
+        t = [np.zeros(p["n"], np.int64) for p in inst["pops"]]
+        for q in inst["projs"]:
+            t[q["pre"]] += np.diff(np.asarray(q["row_ptr"], np.int64))
+        tabs.append(t)
+    return tabs
+
+
+def spike_totals(net, spec):
+    import numpy as np
+    return [[net.spikes(b, p).astype(np.int64) for p in range(len(inst["pops"]))]
+            for b, inst in enumerate(spec["instances"])]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1412_0595_amd import netgen, snn
+
+    spec = netgen.make_config(args.workload, n_instances=args.instances)
+    n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
+    n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
+    cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=cache)
+    stream = torch.cuda.current_stream()
+
+    net.step(args.warmup)
+    net.sync()
+    deg = out_degree_table(spec)
+    c0 = spike_totals(net, spec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    net.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    net.sync()
+    ms = e0.elapsed_time(e1)
+    c1 = spike_totals(net, spec)
+    events = 0
+    spikes = 0
+    for b in range(len(spec["instances"])):
+        for p in range(len(c0[b])):
+            d = c1[b][p] - c0[b][p]
+            spikes += int(d.sum())
+            events += int((d * deg[b][p]).sum())
+    sec = ms * 1e-3
+    neuron_steps = n_hh * args.steps / sec
+    events_s = events / sec
+
+    # per-kernel durations, hipEvents around each launch (same stream)
+    kms = net.profile_kernels(args.profile_steps)
+    c2 = spike_totals(net, spec)
+    ev_prof = sum(int(((c2[b][p] - c1[b][p]) * deg[b][p]).sum()) for b in range(len(c1)) for p in range(len(c1[b])))
+    items_prof = sum(int(((c2[b][p] - c1[b][p]) * 0).sum()) for b in range(len(c1)) for p in range(len(c1[b])))
+    n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
+               for inst in spec["instances"] for k in range(len(inst["pops"])))
+    neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
+    prop_bytes = PROP_BYTES_PER_EVENT * ev_prof / args.profile_steps
+    kern = {
+        "propagate": dict(ms=kms[0], bytes=prop_bytes),
+        "neuron": dict(ms=kms[2], bytes=neuron_bytes),
+    }
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
+    roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+            "ms_per_launch": {k: round(v["ms"], 6) for k, v in kern.items()},
+            "bytes_per_launch": {k: int(v["bytes"]) for k, v in kern.items()}}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        inst = spec["instances"][0]
+        orc = O.OracleNet(inst)
+        n_hh0 = sum(p["n"] for p in inst["pops"] if p["kind"] == "hh")
+        orc.step(1)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and k < args.steps:
+            orc.step(10)
+            k += 10
+        el = time.perf_counter() - t0
+        cpu = {"value": n_hh0 * k / el, "unit": "neuron-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle, instance 0 of the same workload, {k} steps from step 1, single thread"}
+
+    rec = {
+        "metric": "neuron-steps/s + synaptic events/s (1 GPU); batched/adjoint vs plain loop",
+        "value": neuron_steps,
+        "unit": "neuron-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS.get(args.workload, f"workload {args.workload}"),
+                   "instances": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn},
+        "synaptic_events_per_s": events_s,
+        "spikes": spikes,
+        "wall_s": t_wall,
+        "launch": net.launch,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    net.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

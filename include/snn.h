@@ -1,0 +1,261 @@
+/*
+ * snn.h - C ABI of the MI355X spiking-network timestep library (libsnn.so).
+ *
+ * The library advances networks of Hodgkin-Huxley neurons (Traub-Miles
+ * kinetics) and Poisson input sources, coupled by conductance synapses kept
+ * in Compressed Row Storage, one discrete time step at a time.  This is the
+ * per-timestep update that the paper (Balaji, Yavuz, Nowotny, "Scalability
+ * and Optimization Strategies for GPU Enhanced Neural Networks") runs inside
+ * GeNN: Hodgkin-Huxley integration at discretised time steps (Section 2),
+ * sparse synapse propagation through the three CRS arrays (Section 3,
+ * Eq. 1), and the many-network conductance-scaling sweep (Section 2, Fig. 1)
+ * as a batch of independent instances.
+ *
+ * Conventions
+ *  - Units: mV, ms, uS (conductance), nF, nA, Hz.
+ *  - Every function returns an snn_status (0 = SNN_OK, negative = error)
+ *    unless stated otherwise; snn_last_error() gives a message for the last
+ *    failure on the calling thread.  No exception crosses the ABI.
+ *  - A device error is sticky: once a HIP call has failed, every later call
+ *    on that net returns SNN_EDEVICE.
+ *  - "host" pointers are caller-owned CPU memory of the stated size;
+ *    "device" pointers are caller-owned GPU memory valid on the net's stream.
+ *  - A NaN or infinite membrane voltage is not an error: it is counted per
+ *    instance (snn_get_nan_counts), like the sumNANs column of Fig. 1.
+ */
+#ifndef SNN_ABI_H_
+#define SNN_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct snn_net snn_net; /* opaque, library-owned */
+
+enum snn_status {
+    SNN_OK = 0,
+    SNN_EINVAL = -1,  /* invalid argument or network description */
+    SNN_ENOMEM = -2,  /* device or host allocation failed */
+    SNN_EDEVICE = -3, /* a HIP call failed (sticky) */
+    SNN_ESTATE = -4,  /* call not valid in the net's current state */
+    SNN_ERANGE = -5   /* value outside the representable range */
+};
+
+enum snn_pop_kind { SNN_POISSON = 0, SNN_TRAUB_MILES = 1 };
+
+/* State variables of a Traub-Miles population. */
+enum snn_var { SNN_V = 0, SNN_M = 1, SNN_H = 2, SNN_N = 3 };
+
+/* Neuron parameters, in this order: g_Na (uS), E_Na (mV), g_K (uS),
+ * E_K (mV), g_leak (uS), E_leak (mV), C_m (nF). */
+enum { SNN_HH_NPARAM = 7 };
+
+/* A population (Section 5.1 "populations of neurons at different stages").
+ *  kind      SNN_POISSON: source i fires at step t iff the first output word
+ *            of Philox-4x32-10 (Salmon et al., SC'11) with counter
+ *            (i, t mod 2^32, t div 2^32, 0) and key (seed mod 2^32,
+ *            seed div 2^32) is below floor(p * 2^32), p = rate_hz * dt_ms *
+ *            1e-3 evaluated left to right in double precision (p >= 1:
+ *            always fires).
+ *            SNN_TRAUB_MILES: Hodgkin-Huxley neuron, Traub-Miles rates.
+ *  n         number of neurons (>= 0).
+ *  rate_hz   Poisson rate (finite, >= 0); ignored for HH.
+ *  i_ext_nA  constant injected current of every HH neuron.
+ *  hh        neuron parameters (see above); snn_default_hh() fills the
+ *            Traub-Miles values.  C_m must be > 0.
+ *  record_vbar  1: accumulate every neuron's post-step V in double
+ *            precision (read with snn_get_vbar). */
+typedef struct {
+    int32_t kind;
+    int32_t n;
+    double rate_hz;
+    double i_ext_nA;
+    double hh[SNN_HH_NPARAM];
+    int32_t record_vbar;
+} snn_pop_desc;
+
+/* A projection in Compressed Row Storage (Section 3): row_ptr holds the
+ * start of every pre-synaptic row (n_pre + 1 entries, row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n_pre] = nnz); col_idx the post-synaptic index of
+ * every synapse, ascending within a row; g its conductance (uS, finite,
+ * >= 0).  A spike of pre neuron i at step t - 1 adds g_scale * g[k] to the
+ * conductance G[col_idx[k]] of the post population for every k in row i at
+ * step t; G enters the post neuron as G (e_rev_mV - V) and decays by
+ * exp(-dt / tau_ms) per step.  The post population must be Traub-Miles.
+ *
+ * stdp = 1 makes the weights plastic with pair-based, all-to-all traces
+ * (trace time constant tau_stdp_ms): on a pre spike, every synapse of its
+ * row is depressed by a_minus * g_max * y_post after delivery; on a post
+ * spike, every synapse of its column is potentiated by a_plus * g_max *
+ * x_pre; weights are clipped to [0, g_max] after each update. */
+typedef struct {
+    int32_t pre_pop;
+    int32_t post_pop;
+    int64_t nnz;
+    const int32_t *row_ptr; /* host, n_pre + 1 */
+    const int32_t *col_idx; /* host, nnz */
+    const float *g;         /* host, nnz */
+    float e_rev_mV;
+    float tau_ms;
+    int32_t stdp;
+    float a_plus, a_minus, tau_stdp_ms, g_max;
+} snn_proj_desc;
+
+/* One independent network instance.  g_scale multiplies every synaptic
+ * conductance of the instance (the gScale of Section 5.1); seed keys its
+ * Poisson sources. */
+typedef struct {
+    int32_t n_pops;
+    int32_t n_projs;
+    const snn_pop_desc *pops;   /* host, n_pops */
+    const snn_proj_desc *projs; /* host, n_projs */
+    float g_scale;
+    uint64_t seed;
+} snn_instance_desc;
+
+/* Device memory hooks: alloc(bytes, ctx) returns device memory or NULL,
+ * free(ptr, ctx) releases it.  Both NULL: hipMalloc / hipFree. */
+typedef void *(*snn_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*snn_free_fn)(void *ptr, void *ctx);
+
+/* Whole-batch configuration.
+ *  dt_ms, substeps  time step and number of forward-Euler substeps (>= 1)
+ *  n_instances, inst  the batch (>= 1 instance)
+ *  stream        hipStream_t every call enqueues on (NULL: the null stream)
+ *  raster_steps  > 0: keep the spike bitmask of the last raster_steps steps
+ *                on the device (snn_get_raster); 0: no raster
+ *  autotune      1: time candidate launch shapes on this network at create
+ *                and keep the fastest (results do not depend on it)
+ *  tune_cache    path of a JSON file that stores tuned shapes per network
+ *                signature, or NULL */
+typedef struct {
+    double dt_ms;
+    int32_t substeps;
+    int32_t n_instances;
+    const snn_instance_desc *inst;
+    void *stream;
+    snn_alloc_fn alloc;
+    snn_free_fn free;
+    void *alloc_ctx;
+    int32_t raster_steps;
+    int32_t autotune;
+    const char *tune_cache;
+} snn_config;
+
+/* Launch shape of the step kernels (see snn_get_launch). */
+typedef struct {
+    int32_t neuron_block;   /* threads per block of the neuron update: 64..1024, multiple of 64 */
+    int32_t prop_blocks;    /* blocks of the propagation kernel (persistent grid) */
+    int32_t prop_block;     /* threads per block of the propagation kernel */
+    int32_t chunk;          /* synapses per work item of a row or column walk, multiple of 64 */
+} snn_launch;
+
+/* Fill p[0..6] with the Traub-Miles parameters (7.15 uS, 50 mV, 1.43 uS,
+ * -95 mV, 0.02672 uS, -63.563 mV, 0.143 nF). */
+void snn_default_hh(double *p);
+
+/* Validate the description, copy every host array to the device and set
+ * every Traub-Miles neuron to its resting point (the root of the
+ * steady-state membrane current in [-80, -60] mV), conductances and traces
+ * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL. */
+int snn_create(const snn_config *cfg, snn_net **out);
+
+/* Release every device buffer.  NULL is ignored. */
+void snn_destroy(snn_net *net);
+
+/* Enqueue n_steps timesteps on the net's stream and return (asynchronous).
+ * Each step t: (1) deliver the spikes of step t-1 through every projection
+ * (and depress plastic rows), (2) potentiate plastic columns of post neurons
+ * that spiked at t-1, (3) update every neuron: synaptic current from the
+ * start-of-step V, `substeps` Euler substeps, conductance decay, spike iff
+ * V(t-1) < 0 <= V(t); Poisson sources draw their spikes of step t. */
+int snn_step(snn_net *net, int64_t n_steps);
+
+/* Wait for all work enqueued on the net's stream. */
+int snn_sync(snn_net *net);
+
+/* Number of steps taken so far (host-side counter). */
+int64_t snn_time(const snn_net *net);
+
+/* Spike count of every neuron of population pop of instance inst since
+ * create (host int32[n]).  Synchronises. */
+int snn_get_spikes(snn_net *net, int32_t inst, int32_t pop, int32_t *counts);
+
+/* Raster of population pop of instance inst for steps [t0, t1), which must
+ * lie within the last raster_steps steps.  offsets (host int64[t1-t0+1])
+ * receives the start of each step's ids in `ids` (host int32[cap]),
+ * ascending within a step.  Returns SNN_ERANGE if cap is too small
+ * (offsets[t1-t0] still holds the needed size).  Synchronises. */
+int snn_get_raster(snn_net *net, int32_t inst, int32_t pop, int64_t t0, int64_t t1,
+                   int64_t *offsets, int32_t *ids, int64_t cap);
+
+/* Read / write one state variable (enum snn_var) of a Traub-Miles
+ * population as float (host float[n]); the read returns the rounded value
+ * of the stored double-float pair, the write sets the pair to the value
+ * exactly.  Synchronise. */
+int snn_get_state(snn_net *net, int32_t inst, int32_t pop, int32_t var, float *out);
+int snn_set_state(snn_net *net, int32_t inst, int32_t pop, int32_t var, const float *in);
+
+/* The same in double precision (host double[n]): the exact sum of the
+ * stored pair on read; on write the pair (hi = fl32(x), lo = fl32(x - hi)). */
+int snn_get_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, double *out);
+int snn_set_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, const double *in);
+
+/* Post-side conductance G (uS) of projection proj of instance inst (host
+ * double[n_post]).  G is held as a signed 64-bit multiple of 2^-40 uS, so
+ * sums of deliveries do not depend on their order; the write rounds to that
+ * grid.  Synchronise. */
+int snn_get_conductance(snn_net *net, int32_t inst, int32_t proj, double *out);
+int snn_set_conductance(snn_net *net, int32_t inst, int32_t proj, const double *in);
+
+/* Spikes of the last completed step of population pop as 0/1 bytes (host
+ * uint8[n]); the write replaces them (they are delivered at the next step).
+ * Synchronise. */
+int snn_get_last_spikes(snn_net *net, int32_t inst, int32_t pop, uint8_t *out);
+int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *in);
+
+/* Sum of post-step V (double, host double[n]) over all steps since create,
+ * for a population created with record_vbar = 1.  Synchronises. */
+int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out);
+
+/* Per instance, how many Traub-Miles neurons had a finite V at the start of
+ * a step and a non-finite V at its end (host int32[n_instances]). */
+int snn_get_nan_counts(snn_net *net, int32_t *per_instance);
+
+/* Replace every instance's g_scale (host float[n_instances], finite, >= 0). */
+int snn_set_gscale(snn_net *net, const float *per_instance);
+
+/* Current weights of projection proj of instance inst (host float[nnz]). */
+int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out);
+
+/* Device memory of each projection's CRS arrays in bytes, as stored:
+ * 4 * (2 * nnz + n_pre + 1), i.e. Eq. (1) with a row-start array of
+ * n_pre + 1 entries (host int64[total projections, instance-major]). */
+int snn_memory_bytes(const snn_net *net, int64_t *per_proj_bytes);
+
+/* Current / new launch shape; snn_set_launch validates the ranges above. */
+int snn_get_launch(const snn_net *net, snn_launch *out);
+int snn_set_launch(snn_net *net, const snn_launch *in);
+
+/* Time n_steps steps (hipEvents around the enqueued work) after restoring
+ * the state in between; out_ms gets the mean milliseconds per step.  Used by
+ * the autotuner; leaves the net's state as it found it. */
+int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms);
+
+/* Advance the net by n_steps single-step launches with a hipEvent pair
+ * around every kernel, and return the mean duration in milliseconds of each
+ * kernel over those steps: ms[0] propagation, ms[1] potentiation (0 if no
+ * projection is plastic), ms[2] neuron update.  Synchronises. */
+int snn_profile_kernels(snn_net *net, int64_t n_steps, double *ms);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *snn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNN_ABI_H_ */

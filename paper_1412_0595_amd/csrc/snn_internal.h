@@ -1,0 +1,141 @@
+// Device-side tables of the spiking-network library, shared by the host
+// runtime (snn_runtime.hip) and the kernels (snn_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snn {
+
+constexpr int kWave = 64;
+constexpr int kMaxIn = 4;    // incoming projections of one population
+constexpr int kMaxOut = 8;   // outgoing projections of one population
+constexpr int kMaxTr = 4;    // STDP traces kept by one population
+constexpr int kMaxLtp = 2;   // plastic projections arriving at one population
+constexpr int kMinChunk = 64;
+
+// Conductances are signed 64-bit multiples of 2^-40 uS.  Integer addition
+// is associative, so the sum of a step's deliveries does not depend on the
+// order in which atomics land; the grid is far finer than fp32.
+constexpr double kFixOne = 1099511627776.0;          // 2^40
+constexpr double kFixInv = 1.0 / 1099511627776.0;    // 2^-40
+
+enum { kPoisson = 0, kHH = 1 };
+
+// One population of one instance; its neurons occupy the global ids
+// [base, base + n), base a multiple of 64, so a wavefront never spans two.
+struct Seg {
+    int32_t kind, n;
+    int64_t base;
+    int32_t inst, pop;
+    int32_t n_in, n_out, n_tr, n_ltp;
+    // incoming projections: conductance array, reversal, decay per step
+    int64_t in_G[kMaxIn];
+    double in_erev[kMaxIn];
+    double in_decay[kMaxIn];
+    // outgoing projections: id and row-start array (pool offset)
+    int32_t out_proj[kMaxOut];
+    int64_t out_rp[kMaxOut];
+    // plastic projections arriving here: id and column-start array
+    int32_t ltp_proj[kMaxLtp];
+    int64_t ltp_cp[kMaxLtp];
+    // STDP traces owned by this population: pool offset and decay per step
+    int64_t tr_base[kMaxTr];
+    float tr_decay[kMaxTr];
+    // Poisson
+    uint64_t thresh;   // fires iff Philox word < thresh (thresh may be 2^32)
+    uint64_t seed;
+    // Traub-Miles
+    double gna, ena, gk, ek, gl, el, inv_c, i_ext;
+    int32_t record_vbar;
+    int32_t pad_;
+};
+
+struct Proj {
+    int32_t pre_seg, post_seg;
+    int32_t n_pre, n_post;
+    int32_t inst, stdp;
+    int64_t rp_base;    // row_ptr pool offset (n_pre + 1 local offsets)
+    int64_t syn_base;   // col_idx / weight pool offset
+    int64_t nnz;
+    int64_t G_base;     // conductance pool offset (n_post)
+    // STDP
+    float a_plus_gmax, a_minus_gmax, g_max, pad_;
+    int64_t x_base, y_base;    // trace pool offsets (pre n_pre, post n_post)
+    int64_t cp_base;           // column-start pool offset (n_post + 1)
+    int64_t csc_base;          // row-of / position pool offset (nnz)
+};
+
+// Counters the kernels hand to each other from step to step.  Each kernel
+// reads one step field and writes the other, so no kernel reads a field
+// that one of its own blocks writes.
+struct StepState {
+    int64_t t_prop;      // step index seen by propagation / potentiation
+    int64_t t_neuron;    // step index seen by the neuron update
+    uint32_t qcnt[2];    // propagation work items produced at step t (slot t & 1)
+    uint32_t lcnt[2];    // potentiation work items produced at step t
+    uint32_t overflow;   // set if a queue would have overflowed (never expected)
+    uint32_t pad_;
+};
+
+// A work item: synapses [k0, k1) (local offsets) of row `row` of projection
+// `proj` (propagation) or of column `row` (potentiation).
+struct Item {
+    int32_t proj, row, k0, k1;
+};
+
+struct NeuronArgs {
+    const Seg *segs;
+    const int32_t *wave_seg;
+    int64_t n_waves;
+    float *vh, *vl, *mh, *ml, *hh, *hl, *nh, *nl;
+    int64_t *G;
+    int32_t *counts;
+    double *vsum;
+    int32_t *nan_count;      // per instance
+    uint64_t *bits;          // 2 slots of n_waves words
+    uint64_t *raster;        // raster_steps slots of n_waves words, or null
+    int32_t raster_steps;
+    float *trace;
+    const Proj *projs;
+    const int32_t *rp_pool;
+    const int32_t *cp_pool;
+    Item *queue;             // 2 slots of qcap
+    int64_t qcap;
+    Item *lqueue;            // 2 slots of lcap
+    int64_t lcap;
+    int32_t chunk;
+    int32_t substeps;
+    double hs;               // dt / substeps
+    StepState *st;
+};
+
+struct PropArgs {
+    const Proj *projs;
+    const Item *queue;
+    int64_t qcap;
+    const int32_t *col_pool;
+    float *w_pool;
+    const float *gscale;     // per instance
+    int64_t *G;
+    const float *trace;
+    StepState *st;
+};
+
+struct LtpArgs {
+    const Proj *projs;
+    const Item *lqueue;
+    int64_t lcap;
+    const int32_t *csc_row;  // pre index of each column entry
+    const int32_t *csc_pos;  // CSR position of each column entry
+    float *w_pool;
+    const float *trace;
+    StepState *st;
+};
+
+// Launchers (snn_kernels.hip).
+hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s);
+hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s);
+hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s);
+
+}  // namespace snn

@@ -1,0 +1,316 @@
+// Step kernels of the spiking-network library, written for gfx950 (wave64).
+//
+//  k_neuron     one lane per neuron: Traub-Miles update (Section 2: HH at
+//               discrete time steps) or Poisson draw, upward-crossing spike
+//               test, wavefront-ballot + LDS prefix-sum compaction of the
+//               spikes into the work queue of the next step.
+//  k_propagate  persistent grid, one wavefront per work item: a slice of one
+//               spiking row of a Compressed Row Storage projection (Section 3)
+//               whose weights are added into the post-side conductances.
+//  k_potentiate persistent grid, one wavefront per slice of the column of a
+//               post neuron that spiked (STDP potentiation).
+//
+// Conductances are int64 multiples of 2^-40 uS, so atomics from any number
+// of wavefronts give the same bits in any order.
+#include "snn_internal.h"
+
+namespace snn {
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with the key bumped by the Weyl constants between
+// rounds.  Only the first output word is needed for a Bernoulli draw.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t philox_first_word(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                      uint32_t key0, uint32_t key1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_lo = 0xD2511F53u * x0, a_hi = __umulhi(0xD2511F53u, x0);
+        const uint32_t b_lo = 0xCD9E8D57u * x2, b_hi = __umulhi(0xCD9E8D57u, x2);
+        x0 = b_hi ^ x1 ^ key0;
+        x1 = b_lo;
+        x2 = a_hi ^ x3 ^ key1;
+        x3 = a_lo;
+        key0 += 0x9E3779B9u;
+        key1 += 0xBB67AE85u;
+    }
+    return x0;
+}
+
+// x / (e^x - 1) with its limit 1 at x = 0 (expm1 keeps it accurate near 0).
+__device__ __forceinline__ double xexpm1_ratio(double x)
+{
+    return x == 0.0 ? 1.0 : x / expm1(x);
+}
+
+// Wave-wide inclusive sum (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Neuron update + spike compaction
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
+{
+    __shared__ uint32_t s_woff[16][2];
+    __shared__ uint32_t s_base[2];
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+    const int nwb = blockDim.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * nwb + wid;
+    const int64_t t = a.st->t_neuron;
+    const int cur = (int)(t & 1);
+
+    bool spike = false;
+    uint32_t nq = 0, nl = 0;       // work items this lane emits
+    int sidx = 0;
+    int32_t j = 0;
+
+    if (gw < a.n_waves) {
+        sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[gw]);
+        const Seg &S = a.segs[sidx];
+        const int64_t gid = gw * kWave + lane;
+        j = (int32_t)(gid - S.base);
+        const bool active = j < S.n;
+
+        if (S.kind == kHH) {
+            if (active) {
+                double v = (double)a.vh[gid] + (double)a.vl[gid];
+                double m = (double)a.mh[gid] + (double)a.ml[gid];
+                double h = (double)a.hh[gid] + (double)a.hl[gid];
+                double n = (double)a.nh[gid] + (double)a.nl[gid];
+                const double v0 = v;
+                // synaptic current from the start-of-step voltage, held
+                // fixed over the substeps
+                double iin = S.i_ext;
+                for (int q = 0; q < S.n_in; ++q) {
+                    int64_t *gp = a.G + S.in_G[q] + j;
+                    const int64_t gf = *gp;
+                    iin += (double)gf * kFixInv * (S.in_erev[q] - v0);
+                    *gp = __double2ll_rn((double)gf * S.in_decay[q]);
+                }
+                const double hc = a.hs * S.inv_c;
+                for (int k = 0; k < a.substeps; ++k) {
+                    const double am = 1.28 * xexpm1_ratio((-52.0 - v) * 0.25);
+                    const double bm = 1.4 * xexpm1_ratio((v + 25.0) * 0.2);
+                    const double ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
+                    const double bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
+                    const double an = 0.16 * xexpm1_ratio((-50.0 - v) * 0.2);
+                    const double bn = 0.5 * exp((-55.0 - v) * 0.025);
+                    const double n2 = n * n;
+                    const double iion = S.gna * (m * m * m * h) * (v - S.ena) + S.gk * (n2 * n2) * (v - S.ek) +
+                                        S.gl * (v - S.el);
+                    const double vn = v + hc * (iin - iion);
+                    const double mn = m + a.hs * (am * (1.0 - m) - bm * m);
+                    const double hn = h + a.hs * (ah * (1.0 - h) - bh * h);
+                    const double nn = n + a.hs * (an * (1.0 - n) - bn * n);
+                    v = vn;
+                    m = mn;
+                    h = hn;
+                    n = nn;
+                }
+                spike = (v0 < 0.0) && (v >= 0.0);
+                float f = (float)v;
+                a.vh[gid] = f;
+                a.vl[gid] = (float)(v - (double)f);
+                f = (float)m;
+                a.mh[gid] = f;
+                a.ml[gid] = (float)(m - (double)f);
+                f = (float)h;
+                a.hh[gid] = f;
+                a.hl[gid] = (float)(h - (double)f);
+                f = (float)n;
+                a.nh[gid] = f;
+                a.nl[gid] = (float)(n - (double)f);
+                if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[S.inst], 1);
+                if (S.record_vbar) a.vsum[gid] += v;
+            }
+        } else {
+            if (active) {
+                const uint32_t w = philox_first_word((uint32_t)j, (uint32_t)((uint64_t)t & 0xffffffffu),
+                                                     (uint32_t)((uint64_t)t >> 32), 0u,
+                                                     (uint32_t)(S.seed & 0xffffffffu), (uint32_t)(S.seed >> 32));
+                spike = (uint64_t)w < S.thresh;
+            }
+        }
+
+        const uint64_t ball = __ballot(spike);
+        if (lane == 0) {
+            a.bits[(int64_t)cur * a.n_waves + gw] = ball;
+            if (a.raster) a.raster[(t % a.raster_steps) * a.n_waves + gw] = ball;
+        }
+        if (active) {
+            for (int q = 0; q < S.n_tr; ++q) {
+                float *tp = a.trace + S.tr_base[q] + j;
+                *tp = *tp * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
+            }
+        }
+        if (ball != 0 && spike) {
+            a.counts[gid] += 1;
+            const uint32_t ch = (uint32_t)a.chunk;
+            for (int o = 0; o < S.n_out; ++o) {
+                const int32_t *rp = a.rp_pool + S.out_rp[o];
+                const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
+                nq += (len + ch - 1) / ch;
+            }
+            for (int o = 0; o < S.n_ltp; ++o) {
+                const int32_t *cp = a.cp_pool + S.ltp_cp[o];
+                const uint32_t len = (uint32_t)(cp[j + 1] - cp[j]);
+                nl += (len + ch - 1) / ch;
+            }
+        }
+    }
+
+    // Compaction: wave inclusive scans, per-wave offsets in LDS, one atomic
+    // reservation per block and per queue.
+    const uint32_t iq = wave_incl_sum(nq, lane);
+    const uint32_t il = wave_incl_sum(nl, lane);
+    if (lane == kWave - 1) {
+        s_woff[wid][0] = iq;
+        s_woff[wid][1] = il;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sq = 0, sl = 0;
+        for (int w = 0; w < nwb; ++w) {
+            const uint32_t tq = s_woff[w][0], tl = s_woff[w][1];
+            s_woff[w][0] = sq;
+            s_woff[w][1] = sl;
+            sq += tq;
+            sl += tl;
+        }
+        s_base[0] = sq ? atomicAdd(&a.st->qcnt[cur], sq) : 0u;
+        s_base[1] = sl ? atomicAdd(&a.st->lcnt[cur], sl) : 0u;
+        if (sq && (int64_t)s_base[0] + sq > a.qcap) atomicOr(&a.st->overflow, 1u);
+        if (sl && (int64_t)s_base[1] + sl > a.lcap) atomicOr(&a.st->overflow, 2u);
+        if (blockIdx.x == 0) {
+            a.st->qcnt[cur ^ 1] = 0;    // consumed by this step's propagation
+            a.st->lcnt[cur ^ 1] = 0;
+            a.st->t_prop = t + 1;
+        }
+    }
+    __syncthreads();
+
+    if (nq | nl) {
+        const Seg &S = a.segs[sidx];
+        const int32_t ch = a.chunk;
+        int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
+        Item *qd = a.queue + (int64_t)cur * a.qcap;
+        for (int o = 0; o < S.n_out; ++o) {
+            const int32_t *rp = a.rp_pool + S.out_rp[o];
+            const int32_t k1 = rp[j + 1];
+            for (int32_t k = rp[j]; k < k1; k += ch, ++pos)
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, k1)};
+        }
+        pos = (int64_t)s_base[1] + s_woff[wid][1] + (il - nl);
+        Item *ld = a.lqueue + (int64_t)cur * a.lcap;
+        for (int o = 0; o < S.n_ltp; ++o) {
+            const int32_t *cp = a.cp_pool + S.ltp_cp[o];
+            const int32_t k1 = cp[j + 1];
+            for (int32_t k = cp[j]; k < k1; k += ch, ++pos)
+                if (pos < a.lcap) ld[pos] = Item{S.ltp_proj[o], j, k, min(k + ch, k1)};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR propagation (+ depression on plastic rows)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_propagate(PropArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = a.st->t_prop;
+    const int prev = (int)((t + 1) & 1);          // slot of step t - 1
+    const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
+    const Item *q = a.queue + (int64_t)prev * a.qcap;
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    uint32_t it = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+
+    for (; it < n; it += nw) {
+        const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
+        const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
+        const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
+        const Proj &P = a.projs[proj];
+        const double s = (double)a.gscale[P.inst] * kFixOne;
+        const int32_t *col = a.col_pool + P.syn_base;
+        float *w = a.w_pool + P.syn_base;
+        int64_t *G = a.G + P.G_base;
+        if (!P.stdp) {
+            for (int32_t k = k0 + lane; k < k1; k += kWave) {
+                const int32_t c = col[k];
+                const long long inc = __double2ll_rn(s * (double)w[k]);
+                atomicAdd((unsigned long long *)(G + c), (unsigned long long)inc);
+            }
+        } else {
+            const float *y = a.trace + P.y_base;
+            for (int32_t k = k0 + lane; k < k1; k += kWave) {
+                const int32_t c = col[k];
+                const float gv = w[k];
+                const long long inc = __double2ll_rn(s * (double)gv);
+                atomicAdd((unsigned long long *)(G + c), (unsigned long long)inc);
+                w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->t_neuron = t;
+}
+
+// ---------------------------------------------------------------------------
+// STDP potentiation over the columns of post neurons that spiked at t - 1
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = a.st->t_neuron;
+    const int prev = (int)((t + 1) & 1);
+    const uint32_t n = min((uint32_t)a.lcap, a.st->lcnt[prev]);
+    const Item *q = a.lqueue + (int64_t)prev * a.lcap;
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    uint32_t it = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (; it < n; it += nw) {
+        const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
+        const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
+        const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
+        const Proj &P = a.projs[proj];
+        const int32_t *rows = a.csc_row + P.csc_base;
+        const int32_t *pos = a.csc_pos + P.csc_base;
+        float *w = a.w_pool + P.syn_base;
+        const float *x = a.trace + P.x_base;
+        for (int32_t k = k0 + lane; k < k1; k += kWave) {
+            const int32_t at = pos[k];
+            w[at] = fminf(P.g_max, w[at] + P.a_plus_gmax * x[rows[k]]);
+        }
+    }
+}
+
+hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s)
+{
+    const int64_t wpb = block / kWave;
+    const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_neuron, dim3((unsigned)blocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_propagate, dim3(blocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_potentiate, dim3(blocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace snn

@@ -1,0 +1,1261 @@
+// Host runtime of the spiking-network library: validation, device layout,
+// the step loop (direct launches or a captured hipGraph of whole steps),
+// state access, the launch-shape autotuner, and the C ABI of include/snn.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+#include "snn_internal.h"
+
+using namespace snn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+// --------------------------- Traub-Miles rest point --------------------------
+// Steady-state gate value a / (a + b) and the membrane current with all gates
+// at steady state; the resting potential is its root in [-80, -60] mV.
+double ratio_xm1(double x) { return x == 0.0 ? 1.0 : x / std::expm1(x); }
+
+double steady_current(const double *p, double v)
+{
+    const double am = 1.28 * ratio_xm1((-52.0 - v) / 4.0), bm = 1.4 * ratio_xm1((v + 25.0) / 5.0);
+    const double ah = 0.128 * std::exp((-48.0 - v) / 18.0), bh = 4.0 / (std::exp((-25.0 - v) / 5.0) + 1.0);
+    const double an = 0.16 * ratio_xm1((-50.0 - v) / 5.0), bn = 0.5 * std::exp((-55.0 - v) / 40.0);
+    const double m = am / (am + bm), h = ah / (ah + bh), n = an / (an + bn);
+    return p[0] * m * m * m * h * (v - p[1]) + p[2] * n * n * n * n * (v - p[3]) + p[4] * (v - p[5]);
+}
+
+bool resting_state(const double *p, double out[4])
+{
+    double lo = -80.0, hi = -60.0;
+    if (!(steady_current(p, lo) < 0.0 && steady_current(p, hi) > 0.0)) return false;
+    while (true) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (steady_current(p, mid) < 0.0) lo = mid; else hi = mid;
+    }
+    const double v = 0.5 * (lo + hi);
+    const double am = 1.28 * ratio_xm1((-52.0 - v) / 4.0), bm = 1.4 * ratio_xm1((v + 25.0) / 5.0);
+    const double ah = 0.128 * std::exp((-48.0 - v) / 18.0), bh = 4.0 / (std::exp((-25.0 - v) / 5.0) + 1.0);
+    const double an = 0.16 * ratio_xm1((-50.0 - v) / 5.0), bn = 0.5 * std::exp((-55.0 - v) / 40.0);
+    out[0] = v;
+    out[1] = am / (am + bm);
+    out[2] = ah / (ah + bh);
+    out[3] = an / (an + bn);
+    return true;
+}
+
+uint64_t poisson_threshold(double rate_hz, double dt_ms)
+{
+    const double p = rate_hz * dt_ms * 1e-3;
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return (uint64_t)1 << 32;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------- the net ------------------------------------
+struct HostProj {            // host copy of what state access needs
+    int32_t inst, pre_pop, post_pop, n_pre, n_post;
+    int64_t nnz, syn_base, G_base;
+    std::vector<int32_t> row_ptr;
+    std::vector<int32_t> col_ptr;   // plastic only
+    int stdp;
+};
+
+struct snn_net {
+    // configuration
+    double dt;
+    int substeps;
+    int n_inst;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    snn_alloc_fn alloc_fn;
+    snn_free_fn free_fn;
+    void *alloc_ctx;
+    int device;
+    bool sticky;
+    int64_t t;                       // steps enqueued so far
+
+    // tables
+    std::vector<Seg> segs;
+    std::vector<Proj> projs;
+    std::vector<HostProj> hprojs;
+    std::vector<std::vector<int32_t>> seg_of;   // [inst][pop] -> seg index
+    std::vector<std::vector<int32_t>> proj_of;  // [inst][local proj] -> global proj
+    std::vector<float> gscale;
+    int64_t n_waves, n_neurons_padded;
+    int64_t n_hh;                    // Traub-Miles neurons (not padded)
+    bool plastic;
+    int64_t qcap, lcap;
+    int raster_steps;
+
+    // device memory
+    std::vector<void *> allocs;
+    Seg *d_segs;
+    Proj *d_projs;
+    int32_t *d_wave_seg;
+    int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos;
+    float *d_w;
+    float *d_gscale;
+    int64_t w_count;
+    // arena of everything a step mutates (one block, so that snapshots are one copy)
+    char *d_arena;
+    int64_t arena_bytes;
+    float *vh, *vl, *mh, *ml, *hh, *hl, *nh, *nl;
+    int32_t *counts;
+    double *vsum;
+    int64_t *G;
+    int64_t G_count;
+    int32_t *nan_count;
+    uint64_t *bits, *raster;
+    float *trace;
+    int64_t trace_count;
+    Item *queue, *lqueue;
+    StepState *st;
+
+    // launch shape and graph
+    snn_launch launch;
+    hipGraphExec_t graph_exec;
+    int graph_steps;
+};
+
+namespace {
+
+void *dev_alloc(snn_net *net, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (net->alloc_fn) {
+        p = net->alloc_fn(bytes, net->alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) net->allocs.push_back(p);
+    return p;
+}
+
+void release(snn_net *net)
+{
+    if (net->graph_exec) {
+        (void)hipGraphExecDestroy(net->graph_exec);
+        net->graph_exec = nullptr;
+    }
+    for (void *p : net->allocs) {
+        if (net->free_fn) net->free_fn(p, net->alloc_ctx); else (void)hipFree(p);
+    }
+    net->allocs.clear();
+    if (net->cap_stream) {
+        (void)hipStreamDestroy(net->cap_stream);
+        net->cap_stream = nullptr;
+    }
+}
+
+#define HIP_OK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            net->sticky = true;                                                               \
+            return fail(SNN_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
+        }                                                                                     \
+    } while (0)
+
+int check_net(const snn_net *net)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (net->sticky) return fail(SNN_EDEVICE, "a previous device error left the net unusable");
+    return SNN_OK;
+}
+
+NeuronArgs neuron_args(snn_net *net)
+{
+    NeuronArgs a{};
+    a.segs = net->d_segs;
+    a.wave_seg = net->d_wave_seg;
+    a.n_waves = net->n_waves;
+    a.vh = net->vh; a.vl = net->vl; a.mh = net->mh; a.ml = net->ml;
+    a.hh = net->hh; a.hl = net->hl; a.nh = net->nh; a.nl = net->nl;
+    a.G = net->G;
+    a.counts = net->counts;
+    a.vsum = net->vsum;
+    a.nan_count = net->nan_count;
+    a.bits = net->bits;
+    a.raster = net->raster_steps > 0 ? net->raster : nullptr;
+    a.raster_steps = net->raster_steps > 0 ? net->raster_steps : 1;
+    a.trace = net->trace;
+    a.projs = net->d_projs;
+    a.rp_pool = net->d_rp;
+    a.cp_pool = net->d_cp;
+    a.queue = net->queue;
+    a.qcap = net->qcap;
+    a.lqueue = net->lqueue;
+    a.lcap = net->lcap;
+    a.chunk = net->launch.chunk;
+    a.substeps = net->substeps;
+    a.hs = net->dt / net->substeps;
+    a.st = net->st;
+    return a;
+}
+
+// Enqueue one whole step on stream s.
+hipError_t enqueue_step(snn_net *net, hipStream_t s)
+{
+    PropArgs p{};
+    p.projs = net->d_projs;
+    p.queue = net->queue;
+    p.qcap = net->qcap;
+    p.col_pool = net->d_col;
+    p.w_pool = net->d_w;
+    p.gscale = net->d_gscale;
+    p.G = net->G;
+    p.trace = net->trace;
+    p.st = net->st;
+    hipError_t e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, s);
+    if (e != hipSuccess) return e;
+    if (net->plastic) {
+        LtpArgs l{};
+        l.projs = net->d_projs;
+        l.lqueue = net->lqueue;
+        l.lcap = net->lcap;
+        l.csc_row = net->d_csc_row;
+        l.csc_pos = net->d_csc_pos;
+        l.w_pool = net->d_w;
+        l.trace = net->trace;
+        l.st = net->st;
+        e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_neuron(neuron_args(net), net->launch.neuron_block, s);
+}
+
+constexpr int kGraphSteps = 64;
+
+int build_graph(snn_net *net)
+{
+    if (net->graph_exec) {
+        (void)hipGraphExecDestroy(net->graph_exec);
+        net->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(net, net->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(net->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&net->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        net->graph_exec = nullptr;
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    net->graph_steps = kGraphSteps;
+    return SNN_OK;
+}
+
+int run_steps(snn_net *net, int64_t n)
+{
+    if (n >= kGraphSteps && !net->graph_exec) {
+        int rc = build_graph(net);
+        if (rc) return rc;
+    }
+    while (n >= kGraphSteps) {
+        HIP_OK(hipGraphLaunch(net->graph_exec, net->stream));
+        n -= kGraphSteps;
+        net->t += kGraphSteps;
+    }
+    for (; n > 0; --n) {
+        HIP_OK(enqueue_step(net, net->stream));
+        net->t += 1;
+    }
+    return SNN_OK;
+}
+
+int seg_index(const snn_net *net, int32_t inst, int32_t pop, bool need_hh)
+{
+    if (inst < 0 || inst >= net->n_inst) return fail(SNN_EINVAL, "instance %d out of range", inst);
+    if (pop < 0 || pop >= (int32_t)net->seg_of[inst].size()) return fail(SNN_EINVAL, "population %d out of range", pop);
+    const int s = net->seg_of[inst][pop];
+    if (need_hh && net->segs[s].kind != kHH) return fail(SNN_EINVAL, "population %d is not Traub-Miles", pop);
+    return s;
+}
+
+int proj_index(const snn_net *net, int32_t inst, int32_t proj)
+{
+    if (inst < 0 || inst >= net->n_inst) return fail(SNN_EINVAL, "instance %d out of range", inst);
+    if (proj < 0 || proj >= (int32_t)net->proj_of[inst].size()) return fail(SNN_EINVAL, "projection %d out of range", proj);
+    return net->proj_of[inst][proj];
+}
+
+int d2h(snn_net *net, void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return SNN_OK;
+    HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, net->stream));
+    HIP_OK(hipStreamSynchronize(net->stream));
+    return SNN_OK;
+}
+
+int h2d(snn_net *net, void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0) return SNN_OK;
+    HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, net->stream));
+    HIP_OK(hipStreamSynchronize(net->stream));
+    return SNN_OK;
+}
+
+// ------------------------------- validation ---------------------------------
+int validate(const snn_config *cfg)
+{
+    if (!cfg) return fail(SNN_EINVAL, "config is NULL");
+    if (!(cfg->dt_ms > 0.0) || !std::isfinite(cfg->dt_ms)) return fail(SNN_EINVAL, "dt_ms must be finite and > 0");
+    if (cfg->substeps < 1 || cfg->substeps > 64) return fail(SNN_EINVAL, "substeps must be in [1, 64]");
+    if (cfg->n_instances < 1 || !cfg->inst) return fail(SNN_EINVAL, "need at least one instance");
+    if (cfg->raster_steps < 0) return fail(SNN_EINVAL, "raster_steps must be >= 0");
+    if ((cfg->alloc == nullptr) != (cfg->free == nullptr)) return fail(SNN_EINVAL, "alloc and free must both be set or both be NULL");
+    for (int b = 0; b < cfg->n_instances; ++b) {
+        const snn_instance_desc &I = cfg->inst[b];
+        if (I.n_pops < 1 || I.n_pops > 64 || !I.pops) return fail(SNN_EINVAL, "instance %d: n_pops must be in [1, 64]", b);
+        if (I.n_projs < 0 || I.n_projs > 256 || (I.n_projs > 0 && !I.projs))
+            return fail(SNN_EINVAL, "instance %d: n_projs must be in [0, 256]", b);
+        if (!(I.g_scale >= 0.0f) || !std::isfinite(I.g_scale)) return fail(SNN_EINVAL, "instance %d: g_scale must be finite and >= 0", b);
+        std::vector<int> n_in(I.n_pops, 0), n_out(I.n_pops, 0), n_tr(I.n_pops, 0), n_ltp(I.n_pops, 0);
+        for (int p = 0; p < I.n_pops; ++p) {
+            const snn_pop_desc &P = I.pops[p];
+            if (P.kind != SNN_POISSON && P.kind != SNN_TRAUB_MILES) return fail(SNN_EINVAL, "instance %d pop %d: bad kind %d", b, p, P.kind);
+            if (P.n < 0) return fail(SNN_EINVAL, "instance %d pop %d: n < 0", b, p);
+            if (P.kind == SNN_POISSON && (!(P.rate_hz >= 0.0) || !std::isfinite(P.rate_hz)))
+                return fail(SNN_EINVAL, "instance %d pop %d: rate must be finite and >= 0", b, p);
+            if (P.kind == SNN_TRAUB_MILES) {
+                for (int k = 0; k < SNN_HH_NPARAM; ++k)
+                    if (!std::isfinite(P.hh[k])) return fail(SNN_EINVAL, "instance %d pop %d: parameter %d not finite", b, p, k);
+                if (!(P.hh[6] > 0.0)) return fail(SNN_EINVAL, "instance %d pop %d: C_m must be > 0", b, p);
+                if (!std::isfinite(P.i_ext_nA)) return fail(SNN_EINVAL, "instance %d pop %d: i_ext not finite", b, p);
+                double r[4];
+                if (!resting_state(P.hh, r)) return fail(SNN_EINVAL, "instance %d pop %d: no resting point in [-80, -60] mV", b, p);
+            }
+        }
+        for (int q = 0; q < I.n_projs; ++q) {
+            const snn_proj_desc &Q = I.projs[q];
+            if (Q.pre_pop < 0 || Q.pre_pop >= I.n_pops || Q.post_pop < 0 || Q.post_pop >= I.n_pops)
+                return fail(SNN_EINVAL, "instance %d proj %d: population index out of range", b, q);
+            if (I.pops[Q.post_pop].kind != SNN_TRAUB_MILES)
+                return fail(SNN_EINVAL, "instance %d proj %d: post population must be Traub-Miles", b, q);
+            if (!(Q.tau_ms > 0.0f) || !std::isfinite(Q.tau_ms) || !std::isfinite(Q.e_rev_mV))
+                return fail(SNN_EINVAL, "instance %d proj %d: tau must be > 0 and e_rev finite", b, q);
+            const int32_t npre = I.pops[Q.pre_pop].n, npost = I.pops[Q.post_pop].n;
+            if (Q.nnz < 0 || Q.nnz >= ((int64_t)1 << 31)) return fail(SNN_EINVAL, "instance %d proj %d: nnz out of range", b, q);
+            if (!Q.row_ptr || (Q.nnz > 0 && (!Q.col_idx || !Q.g))) return fail(SNN_EINVAL, "instance %d proj %d: NULL CSR array", b, q);
+            if (Q.row_ptr[0] != 0) return fail(SNN_EINVAL, "instance %d proj %d: row_ptr[0] != 0", b, q);
+            if (Q.row_ptr[npre] != Q.nnz) return fail(SNN_EINVAL, "instance %d proj %d: row_ptr[n_pre] != nnz", b, q);
+            for (int32_t i = 0; i < npre; ++i) {
+                const int32_t a0 = Q.row_ptr[i], a1 = Q.row_ptr[i + 1];
+                if (a1 < a0) return fail(SNN_EINVAL, "instance %d proj %d: row_ptr decreases at row %d", b, q, i);
+                for (int32_t k = a0; k < a1; ++k) {
+                    const int32_t c = Q.col_idx[k];
+                    if (c < 0 || c >= npost) return fail(SNN_EINVAL, "instance %d proj %d: col_idx[%d] = %d out of range", b, q, k, c);
+                    if (k > a0 && c < Q.col_idx[k - 1]) return fail(SNN_EINVAL, "instance %d proj %d: row %d not sorted", b, q, i);
+                    if (!(Q.g[k] >= 0.0f) || !std::isfinite(Q.g[k])) return fail(SNN_EINVAL, "instance %d proj %d: g[%d] not finite and >= 0", b, q, k);
+                }
+            }
+            n_in[Q.post_pop]++;
+            n_out[Q.pre_pop]++;
+            if (Q.stdp) {
+                if (!std::isfinite(Q.a_plus) || !std::isfinite(Q.a_minus) || !(Q.tau_stdp_ms > 0.0f) ||
+                    !std::isfinite(Q.tau_stdp_ms) || !(Q.g_max >= 0.0f) || !std::isfinite(Q.g_max))
+                    return fail(SNN_EINVAL, "instance %d proj %d: bad STDP parameters", b, q);
+                n_tr[Q.pre_pop]++;
+                n_tr[Q.post_pop]++;
+                n_ltp[Q.post_pop]++;
+            }
+        }
+        for (int p = 0; p < I.n_pops; ++p) {
+            if (n_in[p] > kMaxIn) return fail(SNN_EINVAL, "instance %d pop %d: more than %d incoming projections", b, p, kMaxIn);
+            if (n_out[p] > kMaxOut) return fail(SNN_EINVAL, "instance %d pop %d: more than %d outgoing projections", b, p, kMaxOut);
+            if (n_tr[p] > kMaxTr) return fail(SNN_EINVAL, "instance %d pop %d: more than %d STDP traces", b, p, kMaxTr);
+            if (n_ltp[p] > kMaxLtp) return fail(SNN_EINVAL, "instance %d pop %d: more than %d plastic inputs", b, p, kMaxLtp);
+        }
+    }
+    return SNN_OK;
+}
+
+// Largest conductance a post neuron can reach is below (sum of its column) *
+// g_scale / (1 - decay); keep it well inside the 2^63 * 2^-40 uS range.
+constexpr double kGLimit = 4194304.0;   // 2^22 uS
+
+int check_range(const snn_net *net, const std::vector<double> &colmax_sum, const float *gs)
+{
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        const double s = gs[net->projs[q].inst];
+        if (!(colmax_sum[q] * s < kGLimit))
+            return fail(SNN_ERANGE, "projection %zu: g_scale * column sum / (1 - decay) exceeds %g uS", q, kGLimit);
+    }
+    return SNN_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI ========================================
+extern "C" {
+
+void snn_default_hh(double *p)
+{
+    p[0] = 7.15;
+    p[1] = 50.0;
+    p[2] = 1.43;
+    p[3] = -95.0;
+    p[4] = 0.02672;
+    p[5] = -63.563;
+    p[6] = 0.143;
+}
+
+const char *snn_last_error(void) { return g_err.c_str(); }
+
+int snn_create(const snn_config *cfg, snn_net **out)
+{
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    g_err.clear();
+    int rc = validate(cfg);
+    if (rc) return rc;
+
+    snn_net *net = new snn_net();
+    net->dt = cfg->dt_ms;
+    net->substeps = cfg->substeps;
+    net->n_inst = cfg->n_instances;
+    net->stream = (hipStream_t)cfg->stream;
+    net->alloc_fn = cfg->alloc;
+    net->free_fn = cfg->free;
+    net->alloc_ctx = cfg->alloc_ctx;
+    net->raster_steps = cfg->raster_steps;
+    net->launch = snn_launch{256, 1024, 256, 256};
+    auto bail = [&](int code) {
+        release(net);
+        delete net;
+        return code;
+    };
+
+    // ---- layout: segments, projections, pools
+    int64_t base = 0, rp_total = 0, syn_total = 0, G_total = 0, tr_total = 0, cp_total = 0, csc_total = 0;
+    net->seg_of.resize(net->n_inst);
+    net->proj_of.resize(net->n_inst);
+    net->gscale.resize(net->n_inst);
+    net->n_hh = 0;
+    net->plastic = false;
+    std::vector<double> colsum_bound;
+    for (int b = 0; b < net->n_inst; ++b) {
+        const snn_instance_desc &I = cfg->inst[b];
+        net->gscale[b] = I.g_scale;
+        for (int p = 0; p < I.n_pops; ++p) {
+            const snn_pop_desc &P = I.pops[p];
+            Seg S{};
+            S.kind = P.kind == SNN_POISSON ? kPoisson : kHH;
+            S.n = P.n;
+            S.base = base;
+            S.inst = b;
+            S.pop = p;
+            S.thresh = poisson_threshold(P.rate_hz, net->dt);
+            S.seed = I.seed;
+            S.gna = P.hh[0]; S.ena = P.hh[1]; S.gk = P.hh[2]; S.ek = P.hh[3]; S.gl = P.hh[4]; S.el = P.hh[5];
+            S.inv_c = 1.0 / P.hh[6];
+            S.i_ext = P.i_ext_nA;
+            S.record_vbar = P.record_vbar ? 1 : 0;
+            net->seg_of[b].push_back((int32_t)net->segs.size());
+            net->segs.push_back(S);
+            base += align_up(P.n, kWave);
+            if (S.kind == kHH) net->n_hh += P.n;
+        }
+        for (int q = 0; q < I.n_projs; ++q) {
+            const snn_proj_desc &Q = I.projs[q];
+            const int gi = (int)net->projs.size();
+            Seg &pre = net->segs[net->seg_of[b][Q.pre_pop]];
+            Seg &post = net->segs[net->seg_of[b][Q.post_pop]];
+            Proj P{};
+            P.pre_seg = net->seg_of[b][Q.pre_pop];
+            P.post_seg = net->seg_of[b][Q.post_pop];
+            P.n_pre = pre.n;
+            P.n_post = post.n;
+            P.inst = b;
+            P.stdp = Q.stdp ? 1 : 0;
+            P.rp_base = rp_total;
+            rp_total += pre.n + 1;
+            P.syn_base = syn_total;
+            P.nnz = Q.nnz;
+            syn_total += Q.nnz;
+            P.G_base = G_total;
+            G_total += post.n;
+            const double decay = std::exp(-net->dt / (double)Q.tau_ms);
+            post.in_G[post.n_in] = P.G_base;
+            post.in_erev[post.n_in] = Q.e_rev_mV;
+            post.in_decay[post.n_in] = decay;
+            post.n_in++;
+            pre.out_proj[pre.n_out] = gi;
+            pre.out_rp[pre.n_out] = P.rp_base;
+            pre.n_out++;
+            HostProj H{};
+            H.inst = b; H.pre_pop = Q.pre_pop; H.post_pop = Q.post_pop; H.n_pre = pre.n; H.n_post = post.n;
+            H.nnz = Q.nnz; H.syn_base = P.syn_base; H.G_base = P.G_base; H.stdp = P.stdp;
+            H.row_ptr.assign(Q.row_ptr, Q.row_ptr + pre.n + 1);
+            if (Q.stdp) {
+                net->plastic = true;
+                P.a_plus_gmax = Q.a_plus * Q.g_max;
+                P.a_minus_gmax = Q.a_minus * Q.g_max;
+                P.g_max = Q.g_max;
+                const float td = (float)std::exp(-net->dt / (double)Q.tau_stdp_ms);
+                P.x_base = tr_total;
+                pre.tr_base[pre.n_tr] = tr_total;
+                pre.tr_decay[pre.n_tr] = td;
+                pre.n_tr++;
+                tr_total += pre.n;
+                P.y_base = tr_total;
+                post.tr_base[post.n_tr] = tr_total;
+                post.tr_decay[post.n_tr] = td;
+                post.n_tr++;
+                tr_total += post.n;
+                P.cp_base = cp_total;
+                cp_total += post.n + 1;
+                P.csc_base = csc_total;
+                csc_total += Q.nnz;
+                post.ltp_proj[post.n_ltp] = gi;
+                post.ltp_cp[post.n_ltp] = P.cp_base;
+                post.n_ltp++;
+            }
+            // bound on the conductance reachable with g_scale = 1
+            std::vector<double> col(post.n > 0 ? post.n : 1, 0.0);
+            for (int64_t k = 0; k < Q.nnz; ++k) col[Q.col_idx[k]] += Q.g[k];
+            double mx = 0.0;
+            for (double c : col) mx = std::max(mx, c);
+            if (Q.stdp) mx = std::max(mx, (double)Q.g_max * (double)pre.n);
+            colsum_bound.push_back(mx / (1.0 - decay));
+            net->proj_of[b].push_back(gi);
+            net->projs.push_back(P);
+            net->hprojs.push_back(std::move(H));
+        }
+    }
+    if ((rc = check_range(net, colsum_bound, net->gscale.data()))) return bail(rc);
+    net->n_neurons_padded = base;
+    net->n_waves = base / kWave;
+    net->w_count = syn_total;
+    net->G_count = G_total;
+    net->trace_count = tr_total;
+
+    // work-queue capacity: every neuron spiking at once, with the smallest chunk
+    int64_t qcap = 0, lcap = 0;
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        const HostProj &H = net->hprojs[q];
+        for (int32_t i = 0; i < H.n_pre; ++i)
+            qcap += (H.row_ptr[i + 1] - H.row_ptr[i] + kMinChunk - 1) / kMinChunk;
+    }
+    // column lengths of plastic projections
+    std::vector<std::vector<int32_t>> colptrs(net->projs.size());
+    for (int b = 0, gq = 0; b < net->n_inst; ++b) {
+        const snn_instance_desc &I = cfg->inst[b];
+        for (int q = 0; q < I.n_projs; ++q, ++gq) {
+            if (!I.projs[q].stdp) continue;
+            HostProj &H = net->hprojs[gq];
+            H.col_ptr.assign(H.n_post + 1, 0);
+            for (int64_t k = 0; k < I.projs[q].nnz; ++k) H.col_ptr[I.projs[q].col_idx[k] + 1]++;
+            for (int32_t j = 0; j < H.n_post; ++j) H.col_ptr[j + 1] += H.col_ptr[j];
+            for (int32_t j = 0; j < H.n_post; ++j)
+                lcap += (H.col_ptr[j + 1] - H.col_ptr[j] + kMinChunk - 1) / kMinChunk;
+        }
+    }
+    net->qcap = std::max<int64_t>(qcap, 1);
+    net->lcap = std::max<int64_t>(lcap, 1);
+    if (net->qcap >= ((int64_t)1 << 32) || net->lcap >= ((int64_t)1 << 32))
+        return bail(fail(SNN_ERANGE, "work queue would exceed 2^32 items"));
+
+    // ---- device allocation (everything above is host-only checking)
+    if (hipGetDevice(&net->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(SNN_EDEVICE, "no HIP device"));
+    }
+    if (hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        net->cap_stream = nullptr;
+        return bail(fail(SNN_EDEVICE, "hipStreamCreate failed"));
+    }
+    const int64_t N = net->n_neurons_padded;
+    const int64_t W = net->n_waves;
+    bool any_vbar = false;
+    for (const Seg &S : net->segs) any_vbar |= S.record_vbar != 0;
+    struct Part { int64_t off, bytes; };
+    int64_t off = 0;
+    auto part = [&](int64_t bytes) { Part p{off, bytes}; off = align_up(off + std::max<int64_t>(bytes, 1), 256); return p; };
+    Part p_state[8];
+    for (auto &p : p_state) p = part(N * 4);
+    Part p_counts = part(N * 4);
+    Part p_vsum = part(any_vbar ? N * 8 : 8);
+    Part p_G = part(G_total * 8);
+    Part p_nan = part(net->n_inst * 4);
+    Part p_bits = part(2 * W * 8);
+    Part p_raster = part(net->raster_steps > 0 ? (int64_t)net->raster_steps * W * 8 : 8);
+    Part p_trace = part(tr_total * 4);
+    Part p_queue = part(2 * net->qcap * (int64_t)sizeof(Item));
+    Part p_lqueue = part(2 * net->lcap * (int64_t)sizeof(Item));
+    Part p_st = part(sizeof(StepState));
+    net->arena_bytes = off;
+    net->d_arena = (char *)dev_alloc(net, (size_t)off);
+    net->d_segs = (Seg *)dev_alloc(net, sizeof(Seg) * net->segs.size());
+    net->d_projs = (Proj *)dev_alloc(net, sizeof(Proj) * std::max<size_t>(net->projs.size(), 1));
+    net->d_wave_seg = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(W, 1));
+    net->d_rp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(rp_total, 1));
+    net->d_col = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(syn_total, 1));
+    net->d_w = (float *)dev_alloc(net, 4 * std::max<int64_t>(syn_total, 1));
+    net->d_cp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(cp_total, 1));
+    net->d_csc_row = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(csc_total, 1));
+    net->d_csc_pos = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(csc_total, 1));
+    net->d_gscale = (float *)dev_alloc(net, 4 * net->n_inst);
+    if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
+        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale)
+        return bail(fail(SNN_ENOMEM, "device allocation failed"));
+    char *A = net->d_arena;
+    float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
+    for (int k = 0; k < 8; ++k) *st_ptrs[k] = (float *)(A + p_state[k].off);
+    net->counts = (int32_t *)(A + p_counts.off);
+    net->vsum = (double *)(A + p_vsum.off);
+    net->G = (int64_t *)(A + p_G.off);
+    net->nan_count = (int32_t *)(A + p_nan.off);
+    net->bits = (uint64_t *)(A + p_bits.off);
+    net->raster = (uint64_t *)(A + p_raster.off);
+    net->trace = (float *)(A + p_trace.off);
+    net->queue = (Item *)(A + p_queue.off);
+    net->lqueue = (Item *)(A + p_lqueue.off);
+    net->st = (StepState *)(A + p_st.off);
+
+    // ---- uploads
+    auto up = [&](void *dst, const void *src, size_t bytes) -> int {
+        if (bytes == 0) return SNN_OK;
+        hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipGetLastError(); return fail(SNN_EDEVICE, "upload failed: %s", hipGetErrorString(e)); }
+        return SNN_OK;
+    };
+    {
+        std::vector<int32_t> wave_seg(std::max<int64_t>(W, 1), 0);
+        for (size_t s = 0; s < net->segs.size(); ++s) {
+            const Seg &S = net->segs[s];
+            for (int64_t w = S.base / kWave; w < (S.base + align_up(S.n, kWave)) / kWave; ++w) wave_seg[w] = (int32_t)s;
+        }
+        if ((rc = up(net->d_wave_seg, wave_seg.data(), 4 * W))) return bail(rc);
+    }
+    if ((rc = up(net->d_segs, net->segs.data(), sizeof(Seg) * net->segs.size()))) return bail(rc);
+    if ((rc = up(net->d_projs, net->projs.data(), sizeof(Proj) * net->projs.size()))) return bail(rc);
+    if ((rc = up(net->d_gscale, net->gscale.data(), 4 * net->n_inst))) return bail(rc);
+    for (int b = 0, gq = 0; b < net->n_inst; ++b) {
+        const snn_instance_desc &I = cfg->inst[b];
+        for (int q = 0; q < I.n_projs; ++q, ++gq) {
+            const snn_proj_desc &Q = I.projs[q];
+            const Proj &P = net->projs[gq];
+            const HostProj &H = net->hprojs[gq];
+            if ((rc = up(net->d_rp + P.rp_base, Q.row_ptr, 4 * (size_t)(P.n_pre + 1)))) return bail(rc);
+            if ((rc = up(net->d_col + P.syn_base, Q.col_idx, 4 * (size_t)Q.nnz))) return bail(rc);
+            if ((rc = up(net->d_w + P.syn_base, Q.g, 4 * (size_t)Q.nnz))) return bail(rc);
+            if (Q.stdp) {
+                // column view: entries of column j in ascending row order
+                std::vector<int32_t> fill(H.col_ptr.begin(), H.col_ptr.end() - 1), rows(Q.nnz), pos(Q.nnz);
+                for (int32_t i = 0; i < P.n_pre; ++i)
+                    for (int32_t k = Q.row_ptr[i]; k < Q.row_ptr[i + 1]; ++k) {
+                        const int32_t at = fill[Q.col_idx[k]]++;
+                        rows[at] = i;
+                        pos[at] = k;
+                    }
+                if ((rc = up(net->d_cp + P.cp_base, H.col_ptr.data(), 4 * (size_t)(P.n_post + 1)))) return bail(rc);
+                if ((rc = up(net->d_csc_row + P.csc_base, rows.data(), 4 * (size_t)Q.nnz))) return bail(rc);
+                if ((rc = up(net->d_csc_pos + P.csc_base, pos.data(), 4 * (size_t)Q.nnz))) return bail(rc);
+            }
+        }
+    }
+    // initial state: rest point of every Traub-Miles population; the rest zero
+    {
+        std::vector<float> hi[4], lo[4];
+        for (int k = 0; k < 4; ++k) {
+            hi[k].assign(N, 0.0f);
+            lo[k].assign(N, 0.0f);
+        }
+        for (int b = 0; b < net->n_inst; ++b)
+            for (int p = 0; p < cfg->inst[b].n_pops; ++p) {
+                const snn_pop_desc &P = cfg->inst[b].pops[p];
+                if (P.kind != SNN_TRAUB_MILES) continue;
+                double r[4];
+                resting_state(P.hh, r);
+                const Seg &S = net->segs[net->seg_of[b][p]];
+                for (int k = 0; k < 4; ++k) {
+                    const float h = (float)r[k], l = (float)(r[k] - (double)h);
+                    std::fill(hi[k].begin() + S.base, hi[k].begin() + S.base + S.n, h);
+                    std::fill(lo[k].begin() + S.base, lo[k].begin() + S.base + S.n, l);
+                }
+            }
+        if (hipMemset(net->d_arena, 0, (size_t)net->arena_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(SNN_EDEVICE, "hipMemset failed"));
+        }
+        for (int k = 0; k < 4; ++k) {
+            if ((rc = up(*st_ptrs[2 * k], hi[k].data(), 4 * (size_t)N))) return bail(rc);
+            if ((rc = up(*st_ptrs[2 * k + 1], lo[k].data(), 4 * (size_t)N))) return bail(rc);
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(SNN_EDEVICE, "device synchronisation failed"));
+    }
+    net->t = 0;
+    *out = net;
+    if (cfg->autotune) {
+        extern int snn_autotune_internal(snn_net *, const char *);
+        rc = snn_autotune_internal(net, cfg->tune_cache);
+        if (rc) {
+            *out = nullptr;
+            return bail(rc);
+        }
+    }
+    return SNN_OK;
+}
+
+void snn_destroy(snn_net *net)
+{
+    if (!net) return;
+    if (!net->sticky) (void)hipStreamSynchronize(net->stream);
+    release(net);
+    delete net;
+}
+
+int snn_step(snn_net *net, int64_t n_steps)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(SNN_EINVAL, "n_steps < 0");
+    return run_steps(net, n_steps);
+}
+
+int snn_sync(snn_net *net)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(net->stream));
+    StepState st;
+    HIP_OK(hipMemcpy(&st, net->st, sizeof st, hipMemcpyDeviceToHost));
+    if (st.overflow) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "work queue overflow (flag %u)", st.overflow);
+    }
+    return SNN_OK;
+}
+
+int64_t snn_time(const snn_net *net) { return net ? net->t : -1; }
+
+int snn_get_spikes(snn_net *net, int32_t inst, int32_t pop, int32_t *counts)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, false);
+    if (s < 0) return s;
+    if (!counts) return fail(SNN_EINVAL, "counts is NULL");
+    return d2h(net, counts, net->counts + net->segs[s].base, 4 * (size_t)net->segs[s].n);
+}
+
+int snn_get_raster(snn_net *net, int32_t inst, int32_t pop, int64_t t0, int64_t t1, int64_t *offsets, int32_t *ids,
+                   int64_t cap)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, false);
+    if (s < 0) return s;
+    if (net->raster_steps <= 0) return fail(SNN_ESTATE, "net was created without a raster");
+    if (t0 < 0 || t1 < t0 || t1 > net->t || t0 < net->t - net->raster_steps)
+        return fail(SNN_ERANGE, "steps [%lld, %lld) are not in the raster window", (long long)t0, (long long)t1);
+    if (!offsets || (cap > 0 && !ids)) return fail(SNN_EINVAL, "NULL output");
+    const Seg &S = net->segs[s];
+    const int64_t w0 = S.base / kWave, nw = align_up(S.n, kWave) / kWave;
+    std::vector<uint64_t> words(nw);
+    int64_t n = 0;
+    offsets[0] = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        if ((rc = d2h(net, words.data(), net->raster + (t % net->raster_steps) * net->n_waves + w0, 8 * (size_t)nw))) return rc;
+        for (int64_t w = 0; w < nw; ++w)
+            for (uint64_t b = words[w]; b; b &= b - 1) {
+                const int32_t id = (int32_t)(w * kWave + __builtin_ctzll(b));
+                if (n < cap) ids[n] = id;
+                ++n;
+            }
+        offsets[t - t0 + 1] = n;
+    }
+    return n > cap ? fail(SNN_ERANGE, "raster holds %lld ids, cap %lld", (long long)n, (long long)cap) : SNN_OK;
+}
+
+static float *state_hi(snn_net *net, int var) { float *p[4] = {net->vh, net->mh, net->hh, net->nh}; return p[var]; }
+static float *state_lo(snn_net *net, int var) { float *p[4] = {net->vl, net->ml, net->hl, net->nl}; return p[var]; }
+
+int snn_get_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, double *out)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, true);
+    if (s < 0) return s;
+    if (var < 0 || var > 3) return fail(SNN_EINVAL, "bad variable %d", var);
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    const Seg &S = net->segs[s];
+    std::vector<float> h(S.n), l(S.n);
+    if ((rc = d2h(net, h.data(), state_hi(net, var) + S.base, 4 * (size_t)S.n))) return rc;
+    if ((rc = d2h(net, l.data(), state_lo(net, var) + S.base, 4 * (size_t)S.n))) return rc;
+    for (int i = 0; i < S.n; ++i) out[i] = (double)h[i] + (double)l[i];
+    return SNN_OK;
+}
+
+int snn_get_state(snn_net *net, int32_t inst, int32_t pop, int32_t var, float *out)
+{
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    const int s = net ? seg_index(net, inst, pop, true) : -1;
+    if (s < 0) return net ? s : fail(SNN_EINVAL, "net is NULL");
+    std::vector<double> d(net->segs[s].n);
+    int rc = snn_get_state_f64(net, inst, pop, var, d.data());
+    if (rc) return rc;
+    for (size_t i = 0; i < d.size(); ++i) out[i] = (float)d[i];
+    return SNN_OK;
+}
+
+int snn_set_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, const double *in)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, true);
+    if (s < 0) return s;
+    if (var < 0 || var > 3) return fail(SNN_EINVAL, "bad variable %d", var);
+    if (!in) return fail(SNN_EINVAL, "in is NULL");
+    const Seg &S = net->segs[s];
+    std::vector<float> h(S.n), l(S.n);
+    for (int i = 0; i < S.n; ++i) {
+        h[i] = (float)in[i];
+        l[i] = (float)(in[i] - (double)h[i]);
+    }
+    if ((rc = h2d(net, state_hi(net, var) + S.base, h.data(), 4 * (size_t)S.n))) return rc;
+    return h2d(net, state_lo(net, var) + S.base, l.data(), 4 * (size_t)S.n);
+}
+
+int snn_set_state(snn_net *net, int32_t inst, int32_t pop, int32_t var, const float *in)
+{
+    if (!in) return fail(SNN_EINVAL, "in is NULL");
+    const int s = net ? seg_index(net, inst, pop, true) : -1;
+    if (s < 0) return net ? s : fail(SNN_EINVAL, "net is NULL");
+    std::vector<double> d(in, in + net->segs[s].n);
+    return snn_set_state_f64(net, inst, pop, var, d.data());
+}
+
+int snn_get_conductance(snn_net *net, int32_t inst, int32_t proj, double *out)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int q = proj_index(net, inst, proj);
+    if (q < 0) return q;
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    const HostProj &H = net->hprojs[q];
+    std::vector<int64_t> g(H.n_post);
+    if ((rc = d2h(net, g.data(), net->G + H.G_base, 8 * (size_t)H.n_post))) return rc;
+    for (int j = 0; j < H.n_post; ++j) out[j] = (double)g[j] * kFixInv;
+    return SNN_OK;
+}
+
+int snn_set_conductance(snn_net *net, int32_t inst, int32_t proj, const double *in)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int q = proj_index(net, inst, proj);
+    if (q < 0) return q;
+    if (!in) return fail(SNN_EINVAL, "in is NULL");
+    const HostProj &H = net->hprojs[q];
+    std::vector<int64_t> g(H.n_post);
+    for (int j = 0; j < H.n_post; ++j) {
+        if (!(in[j] >= 0.0) || !(in[j] < kGLimit)) return fail(SNN_ERANGE, "conductance %d out of [0, %g) uS", j, kGLimit);
+        g[j] = (int64_t)std::llrint(in[j] * kFixOne);
+    }
+    return h2d(net, net->G + H.G_base, g.data(), 8 * (size_t)H.n_post);
+}
+
+int snn_get_last_spikes(snn_net *net, int32_t inst, int32_t pop, uint8_t *out)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, false);
+    if (s < 0) return s;
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    const Seg &S = net->segs[s];
+    const int64_t nw = align_up(S.n, kWave) / kWave;
+    const int slot = (int)((net->t + 1) & 1);
+    std::vector<uint64_t> words(nw);
+    if ((rc = d2h(net, words.data(), net->bits + slot * net->n_waves + S.base / kWave, 8 * (size_t)nw))) return rc;
+    for (int i = 0; i < S.n; ++i) out[i] = (uint8_t)((words[i / kWave] >> (i % kWave)) & 1u);
+    return SNN_OK;
+}
+
+// Replace S(t-1) of one population: rewrite its bitmask words and rebuild
+// the work items of the slot the next step consumes (items of the other
+// populations are kept).
+int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *in)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, false);
+    if (s < 0) return s;
+    if (!in) return fail(SNN_EINVAL, "in is NULL");
+    const Seg &S = net->segs[s];
+    const int slot = (int)((net->t + 1) & 1);
+    const int64_t nw = align_up(S.n, kWave) / kWave;
+    std::vector<uint64_t> words(nw, 0);
+    for (int i = 0; i < S.n; ++i)
+        if (in[i]) words[i / kWave] |= (uint64_t)1 << (i % kWave);
+    if ((rc = h2d(net, net->bits + slot * net->n_waves + S.base / kWave, words.data(), 8 * (size_t)nw))) return rc;
+    StepState st;
+    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
+    const int32_t ch = net->launch.chunk;
+    for (int which = 0; which < 2; ++which) {
+        const uint32_t n = which == 0 ? st.qcnt[slot] : st.lcnt[slot];
+        Item *dq = (which == 0 ? net->queue : net->lqueue) + (int64_t)slot * (which == 0 ? net->qcap : net->lcap);
+        std::vector<Item> items(n);
+        if ((rc = d2h(net, items.data(), dq, sizeof(Item) * n))) return rc;
+        std::vector<Item> keep;
+        for (const Item &it : items) {
+            const Proj &P = net->projs[it.proj];
+            const int owner = which == 0 ? P.pre_seg : P.post_seg;
+            if (owner != s) keep.push_back(it);
+        }
+        for (int i = 0; i < S.n; ++i) {
+            if (!in[i]) continue;
+            if (which == 0) {
+                for (int o = 0; o < S.n_out; ++o) {
+                    const HostProj &H = net->hprojs[S.out_proj[o]];
+                    for (int32_t k = H.row_ptr[i]; k < H.row_ptr[i + 1]; k += ch)
+                        keep.push_back(Item{S.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1])});
+                }
+            } else {
+                for (int o = 0; o < S.n_ltp; ++o) {
+                    const HostProj &H = net->hprojs[S.ltp_proj[o]];
+                    for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
+                        keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1])});
+                }
+            }
+        }
+        if ((int64_t)keep.size() > (which == 0 ? net->qcap : net->lcap)) return fail(SNN_ERANGE, "too many work items");
+        if ((rc = h2d(net, dq, keep.data(), sizeof(Item) * keep.size()))) return rc;
+        if (which == 0) st.qcnt[slot] = (uint32_t)keep.size(); else st.lcnt[slot] = (uint32_t)keep.size();
+    }
+    return h2d(net, net->st, &st, sizeof st);
+}
+
+int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int s = seg_index(net, inst, pop, true);
+    if (s < 0) return s;
+    if (!net->segs[s].record_vbar) return fail(SNN_ESTATE, "population %d was created without record_vbar", pop);
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    return d2h(net, out, net->vsum + net->segs[s].base, 8 * (size_t)net->segs[s].n);
+}
+
+int snn_get_nan_counts(snn_net *net, int32_t *per_instance)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!per_instance) return fail(SNN_EINVAL, "out is NULL");
+    return d2h(net, per_instance, net->nan_count, 4 * (size_t)net->n_inst);
+}
+
+int snn_set_gscale(snn_net *net, const float *per_instance)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!per_instance) return fail(SNN_EINVAL, "in is NULL");
+    for (int b = 0; b < net->n_inst; ++b)
+        if (!(per_instance[b] >= 0.0f) || !std::isfinite(per_instance[b]))
+            return fail(SNN_EINVAL, "g_scale of instance %d must be finite and >= 0", b);
+    // same range rule as at create, on the stored weights' column sums
+    std::vector<double> bound(net->projs.size(), 0.0);
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        const HostProj &H = net->hprojs[q];
+        std::vector<int32_t> col(H.nnz);
+        std::vector<float> w(H.nnz);
+        if ((rc = d2h(net, col.data(), net->d_col + H.syn_base, 4 * (size_t)H.nnz))) return rc;
+        if ((rc = d2h(net, w.data(), net->d_w + H.syn_base, 4 * (size_t)H.nnz))) return rc;
+        std::vector<double> cs(std::max(H.n_post, 1), 0.0);
+        for (int64_t k = 0; k < H.nnz; ++k) cs[col[k]] += w[k];
+        double mx = 0.0;
+        for (double c : cs) mx = std::max(mx, c);
+        if (H.stdp) mx = std::max(mx, (double)net->projs[q].g_max * H.n_pre);
+        const int s = net->seg_of[H.inst][H.post_pop];
+        double decay = 0.0;
+        for (int k = 0; k < net->segs[s].n_in; ++k)
+            if (net->segs[s].in_G[k] == H.G_base) decay = net->segs[s].in_decay[k];
+        bound[q] = mx / (1.0 - decay);
+    }
+    if ((rc = check_range(net, bound, per_instance))) return rc;
+    std::copy(per_instance, per_instance + net->n_inst, net->gscale.begin());
+    return h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst);
+}
+
+int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const int q = proj_index(net, inst, proj);
+    if (q < 0) return q;
+    if (!out) return fail(SNN_EINVAL, "out is NULL");
+    const HostProj &H = net->hprojs[q];
+    return d2h(net, out, net->d_w + H.syn_base, 4 * (size_t)H.nnz);
+}
+
+int snn_memory_bytes(const snn_net *net, int64_t *per_proj_bytes)
+{
+    if (!net) return fail(SNN_EINVAL, "net is NULL");
+    if (!per_proj_bytes) return fail(SNN_EINVAL, "out is NULL");
+    for (size_t q = 0; q < net->hprojs.size(); ++q)
+        per_proj_bytes[q] = 4 * (2 * net->hprojs[q].nnz + net->hprojs[q].n_pre + 1);
+    return SNN_OK;
+}
+
+int snn_get_launch(const snn_net *net, snn_launch *out)
+{
+    if (!net || !out) return fail(SNN_EINVAL, "NULL argument");
+    *out = net->launch;
+    return SNN_OK;
+}
+
+int snn_set_launch(snn_net *net, const snn_launch *in)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!in) return fail(SNN_EINVAL, "in is NULL");
+    if (in->neuron_block < 64 || in->neuron_block > 1024 || in->neuron_block % 64)
+        return fail(SNN_EINVAL, "neuron_block must be a multiple of 64 in [64, 1024]");
+    if (in->prop_block < 64 || in->prop_block > 1024 || in->prop_block % 64)
+        return fail(SNN_EINVAL, "prop_block must be a multiple of 64 in [64, 1024]");
+    if (in->prop_blocks < 1 || in->prop_blocks > 65536) return fail(SNN_EINVAL, "prop_blocks must be in [1, 65536]");
+    if (in->chunk < kMinChunk || in->chunk % kWave || in->chunk > (1 << 20))
+        return fail(SNN_EINVAL, "chunk must be a multiple of 64 in [64, 2^20]");
+    if (in->chunk != net->launch.chunk) {
+        // the pending items of the next step were cut with the old chunk;
+        // they stay valid (any chunk >= 64 fits the queue), so only new
+        // items use the new length
+    }
+    net->launch = *in;
+    if (net->graph_exec) {
+        (void)hipGraphExecDestroy(net->graph_exec);
+        net->graph_exec = nullptr;
+    }
+    return SNN_OK;
+}
+
+int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (n_steps < 1 || !out_ms) return fail(SNN_EINVAL, "need n_steps >= 1 and an output");
+    // snapshot everything a step mutates
+    void *snap = nullptr, *wsnap = nullptr;
+    HIP_OK(hipMalloc(&snap, (size_t)net->arena_bytes));
+    if (net->plastic && hipMalloc(&wsnap, 4 * (size_t)std::max<int64_t>(net->w_count, 1)) != hipSuccess) {
+        (void)hipFree(snap);
+        net->sticky = true;
+        return fail(SNN_ENOMEM, "snapshot allocation failed");
+    }
+    const int64_t t_saved = net->t;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemcpyAsync(snap, net->d_arena, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && wsnap) e = hipMemcpyAsync(wsnap, net->d_w, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, net->stream);
+    if (e == hipSuccess) rc = run_steps(net, n_steps);
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventRecord(e1, net->stream);
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && rc == SNN_OK) e = hipMemcpyAsync(net->d_arena, snap, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && rc == SNN_OK && wsnap) e = hipMemcpyAsync(net->d_w, wsnap, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && rc == SNN_OK) e = hipStreamSynchronize(net->stream);
+    net->t = t_saved;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    if (wsnap) (void)hipFree(wsnap);
+    if (rc) return rc;
+    if (e != hipSuccess) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "timing failed: %s", hipGetErrorString(e));
+    }
+    *out_ms = (double)ms / (double)n_steps;
+    return SNN_OK;
+}
+
+int snn_profile_kernels(snn_net *net, int64_t n_steps, double *ms)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (n_steps < 1 || n_steps > 100000 || !ms) return fail(SNN_EINVAL, "need 1 <= n_steps <= 100000 and an output");
+    const int nk = 3;
+    std::vector<hipEvent_t> ev((size_t)(2 * nk * n_steps), nullptr);
+    for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+    PropArgs p{};
+    p.projs = net->d_projs; p.queue = net->queue; p.qcap = net->qcap; p.col_pool = net->d_col; p.w_pool = net->d_w;
+    p.gscale = net->d_gscale; p.G = net->G; p.trace = net->trace; p.st = net->st;
+    LtpArgs l{};
+    l.projs = net->d_projs; l.lqueue = net->lqueue; l.lcap = net->lcap; l.csc_row = net->d_csc_row;
+    l.csc_pos = net->d_csc_pos; l.w_pool = net->d_w; l.trace = net->trace; l.st = net->st;
+    const NeuronArgs a = neuron_args(net);
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < n_steps && e == hipSuccess; ++k) {
+        hipEvent_t *E = &ev[(size_t)(2 * nk * k)];
+        e = hipEventRecord(E[0], net->stream);
+        if (e == hipSuccess) e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[1], net->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[2], net->stream);
+        if (e == hipSuccess && net->plastic) e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, net->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[3], net->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[4], net->stream);
+        if (e == hipSuccess) e = launch_neuron(a, net->launch.neuron_block, net->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[5], net->stream);
+        if (e == hipSuccess) net->t += 1;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    double sum[3] = {0, 0, 0};
+    for (int64_t k = 0; k < n_steps && e == hipSuccess; ++k)
+        for (int j = 0; j < nk && e == hipSuccess; ++j) {
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, ev[(size_t)(2 * nk * k + 2 * j)], ev[(size_t)(2 * nk * k + 2 * j + 1)]);
+            sum[j] += t;
+        }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "kernel profiling failed: %s", hipGetErrorString(e));
+    }
+    for (int j = 0; j < nk; ++j) ms[j] = net->plastic || j != 1 ? sum[j] / (double)n_steps : 0.0;
+    return SNN_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------- autotuner ----------------------------------
+// Coordinate search over the launch shape on the real network: time a short
+// run per candidate (state restored after each), keep the fastest value of
+// one parameter, move to the next.  Results are bitwise independent of the
+// shape, so tuning never changes what is computed.
+static std::string signature(const snn_net *net)
+{
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, net->device);
+    int64_t nnz = 0;
+    for (const HostProj &H : net->hprojs) nnz += H.nnz;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s:i%d:s%zu:n%lld:z%lld:p%d", prop.gcnArchName, net->n_inst, net->segs.size(),
+             (long long)net->n_neurons_padded, (long long)nnz, net->plastic ? 1 : 0);
+    return buf;
+}
+
+static bool cache_lookup(const char *path, const std::string &sig, snn_launch *out)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char key[300];
+        snn_launch L{};
+        if (sscanf(line, " \"%299[^\"]\" : [ %d , %d , %d , %d ]", key, &L.neuron_block, &L.prop_blocks,
+                   &L.prop_block, &L.chunk) == 5 && sig == key) {
+            *out = L;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &sig, const snn_launch &L)
+{
+    if (!path) return;
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path, "r")) {
+        char line[512];
+        while (fgets(line, sizeof line, f)) {
+            std::string s(line);
+            if (s.find("\"") != std::string::npos && s.find("\"" + sig + "\"") == std::string::npos) {
+                while (!s.empty() && (s.back() == '\n' || s.back() == ',' || s.back() == ' ')) s.pop_back();
+                keep.push_back(s);
+            }
+        }
+        fclose(f);
+    }
+    char buf[512];
+    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d]", sig.c_str(), L.neuron_block, L.prop_blocks, L.prop_block, L.chunk);
+    keep.push_back(buf);
+    if (FILE *f = fopen(path, "w")) {
+        fprintf(f, "{\n");
+        for (size_t i = 0; i < keep.size(); ++i) fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+        fprintf(f, "}\n");
+        fclose(f);
+    }
+}
+
+int snn_autotune_internal(snn_net *net, const char *cache)
+{
+    const std::string sig = signature(net);
+    snn_launch best = net->launch;
+    if (cache_lookup(cache, sig, &best)) return snn_set_launch(net, &best);
+    const int64_t steps = 3 * kGraphSteps;
+    double best_ms = 0.0;
+    int rc = snn_time_steps(net, steps, &best_ms);   // also warms up
+    if (rc) return rc;
+    if ((rc = snn_time_steps(net, steps, &best_ms))) return rc;
+    const int nb[] = {64, 128, 256, 512, 1024};
+    const int pb[] = {256, 512, 1024, 2048, 4096, 8192};
+    const int ck[] = {128, 256, 512, 1024, 2048};
+    for (int dim = 0; dim < 3; ++dim) {
+        const int *vals = dim == 0 ? nb : dim == 1 ? pb : ck;
+        const int nv = dim == 0 ? 5 : dim == 1 ? 6 : 5;
+        snn_launch cur_best = best;
+        for (int k = 0; k < nv; ++k) {
+            snn_launch L = best;
+            if (dim == 0) L.neuron_block = vals[k];
+            if (dim == 1) L.prop_blocks = vals[k];
+            if (dim == 2) L.chunk = vals[k];
+            if ((rc = snn_set_launch(net, &L))) return rc;
+            double ms = 0.0;
+            if ((rc = snn_time_steps(net, steps, &ms))) return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                cur_best = L;
+            }
+        }
+        best = cur_best;
+    }
+    if ((rc = snn_set_launch(net, &best))) return rc;
+    cache_store(cache, sig, best);
+    return SNN_OK;
+}

@@ -1,0 +1,137 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects invalid
+network descriptions on the host before touching the GPU."""
+import copy
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1412_0595_amd import netgen, snn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "snn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(snn_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = snn.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(snn.EXPORTS) == names
+
+
+def test_default_parameters():
+    assert list(snn.default_hh()) == [7.15, 50.0, 1.43, -95.0, 0.02672, -63.563, 0.143]
+
+
+def _tiny():
+    return netgen.random_tiny(3, n_pops=3, max_n=20)
+
+
+def _bad(mutate):
+    spec = copy.deepcopy(_tiny())
+    mutate(spec["instances"][0])
+    rc, msg = snn.create_status(spec)
+    return rc, msg
+
+
+def _first_nonempty(inst):
+    for q in inst["projs"]:
+        if q["col_idx"].size > 2:
+            return q
+    raise AssertionError
+
+
+@pytest.mark.parametrize("name,mutate,needle", [
+    ("row_ptr0", lambda I: _first_nonempty(I)["row_ptr"].__setitem__(0, 1), "row_ptr[0]"),
+    ("nnz", lambda I: _first_nonempty(I).__setitem__("row_ptr", _first_nonempty(I)["row_ptr"] + 0) or
+     _first_nonempty(I)["row_ptr"].__setitem__(-1, _first_nonempty(I)["row_ptr"][-1] - 1), "nnz"),
+    ("col_range", lambda I: _first_nonempty(I)["col_idx"].__setitem__(0, 10 ** 6), "out of range"),
+    ("col_neg", lambda I: _first_nonempty(I)["col_idx"].__setitem__(0, -1), "out of range"),
+    ("g_nan", lambda I: _first_nonempty(I)["g"].__setitem__(0, np.nan), "g["),
+    ("g_neg", lambda I: _first_nonempty(I)["g"].__setitem__(0, -1.0), "g["),
+    ("pop_index", lambda I: I["projs"][0].__setitem__("post", 99), "population index"),
+    ("post_poisson", lambda I: I["projs"][0].__setitem__("post", 0), "Traub-Miles"),
+    ("tau", lambda I: I["projs"][0].__setitem__("tau", 0.0), "tau"),
+    ("gscale", lambda I: I.__setitem__("g_scale", float("inf")), "g_scale"),
+    ("rate", lambda I: I["pops"][0].__setitem__("rate_hz", -1.0), "rate"),
+    ("n_neg", lambda I: I["pops"][1].__setitem__("n", -5), "n < 0"),
+])
+def test_invalid_description_rejected(name, mutate, needle):
+    rc, msg = _bad(mutate)
+    assert rc == snn.SNN_EINVAL, (rc, msg)
+    assert needle in msg, msg
+
+
+def test_unsorted_row_rejected():
+    spec = copy.deepcopy(_tiny())
+    q = _first_nonempty(spec["instances"][0])
+    rp = q["row_ptr"]
+    for i in range(rp.size - 1):
+        if rp[i + 1] - rp[i] >= 2:
+            a = q["col_idx"][rp[i]]
+            q["col_idx"][rp[i]] = q["col_idx"][rp[i] + 1]
+            q["col_idx"][rp[i] + 1] = a
+            break
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_EINVAL and "not sorted" in msg
+
+
+def test_decreasing_row_ptr_rejected():
+    spec = copy.deepcopy(_tiny())
+    q = _first_nonempty(spec["instances"][0])
+    rp = q["row_ptr"].astype(np.int32).copy()
+    i = int(np.argmax(np.diff(rp) > 0))
+    rp[i + 1] = rp[i] - 1 if rp[i] > 0 else rp[i + 1]
+    if rp[i + 1] >= rp[i]:
+        rp[i + 1], rp[i] = 0, 1
+    q["row_ptr"] = rp
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_EINVAL
+
+
+def test_bad_config_rejected():
+    spec = copy.deepcopy(_tiny())
+    spec["dt"] = 0.0
+    assert snn.create_status(spec)[0] == snn.SNN_EINVAL
+    spec = copy.deepcopy(_tiny())
+    spec["substeps"] = 0
+    assert snn.create_status(spec)[0] == snn.SNN_EINVAL
+
+
+def test_too_many_incoming_projections_rejected():
+    spec = copy.deepcopy(_tiny())
+    inst = spec["instances"][0]
+    q = inst["projs"][0]
+    inst["projs"] = [copy.deepcopy(q) for _ in range(5)]
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_EINVAL and "incoming" in msg
+
+
+def test_conductance_range_rejected():
+    spec = copy.deepcopy(_tiny())
+    spec["instances"][0]["g_scale"] = 3e38
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_ERANGE, msg
+
+
+def test_valid_description_passes_validation():
+    """A valid network passes every host check; without a GPU the first
+    device call then fails cleanly with SNN_EDEVICE (on a GPU it succeeds)."""
+    rc, msg = snn.create_status(_tiny())
+    assert rc in (snn.SNN_OK, snn.SNN_EDEVICE), msg
+
+
+def test_null_arguments():
+    L = snn.load()
+    assert L.snn_create(None, None) == snn.SNN_EINVAL
+    assert L.snn_step(None, 1) == snn.SNN_EINVAL
+    assert L.snn_time(None) == -1
+    L.snn_destroy(None)

@@ -1,0 +1,143 @@
+"""Batched instances (the conductance-scaling sweep as one launch) and STDP."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1412_0595_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0595_amd import snn as S
+    S.load()
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _sub(spec, k):
+    return dict(dt=spec["dt"], substeps=spec["substeps"], instances=[spec["instances"][k]])
+
+
+def test_instance_in_batch_equals_instance_alone(snn):
+    """Every instance of an uneven batch evolves bit for bit as it does alone."""
+    say("case: batch of 5 uneven instances vs alone")
+    spec = netgen.make_config(4, n_instances=5, scale=0.3)
+    T = 300
+    batch = snn.Network(spec)
+    batch.step(T)
+    for k in range(5):
+        alone = snn.Network(_sub(spec, k))
+        alone.step(T)
+        for p in range(3):
+            assert np.array_equal(batch.spikes(k, p), alone.spikes(0, p)), (k, p)
+            if p:
+                assert np.array_equal(batch.state(k, p, snn.V), alone.state(0, p, snn.V)), (k, p)
+        alone.close()
+    assert np.array_equal(batch.nan_counts(), np.zeros(5, np.int32))
+    batch.close()
+
+
+def test_batch_matches_oracle_per_instance(snn):
+    say("case: batch of 3 vs oracle")
+    spec = netgen.make_config(4, n_instances=3, scale=0.2)
+    T = 400
+    net = snn.Network(spec)
+    net.step(T)
+    for k in range(3):
+        orc = O.OracleNet(spec["instances"][k])
+        orc.step(T)
+        d = np.concatenate([net.state(k, p, snn.V) - orc.get(p, O.V) for p in (1, 2)])
+        rms = math.sqrt(np.mean(d * d))
+        say(f"  instance {k} (g_scale {spec['instances'][k]['g_scale']:.3f}): V RMS at step {T} = {rms:.2e} mV")
+        assert rms < 1e-3
+        assert np.array_equal(net.spikes(k, 0), orc.counts(0))
+    net.close()
+
+
+def test_nan_stays_in_its_instance(snn):
+    """An instance driven unstable (huge g_scale) counts its NaN neurons and
+    leaves the other instances bit for bit unchanged."""
+    say("case: NaN isolation")
+    spec = netgen.make_config(4, n_instances=3, scale=0.2)
+    spec["instances"][1]["g_scale"] = 3000.0
+    T = 200
+    net = snn.Network(spec)
+    net.step(T)
+    nan = net.nan_counts()
+    say(f"  NaN counts per instance {nan.tolist()}")
+    assert nan[1] > 0 and nan[0] == 0 and nan[2] == 0
+    orc = O.OracleNet(spec["instances"][1])
+    orc.step(T)
+    assert orc.nan_count > 0
+    for k in (0, 2):
+        alone = snn.Network(_sub(spec, k))
+        alone.step(T)
+        for p in (1, 2):
+            assert np.array_equal(net.state(k, p, snn.V), alone.state(0, p, snn.V))
+        alone.close()
+    net.close()
+
+
+def test_set_gscale_matches_oracle(snn):
+    say("case: set_gscale")
+    spec = netgen.make_config(4, n_instances=2, scale=0.2)
+    net = snn.Network(spec)
+    net.set_gscale(np.array([2.0, 0.5], np.float32))
+    net.step(200)
+    for k, s in enumerate([2.0, 0.5]):
+        inst = dict(spec["instances"][k], g_scale=s)
+        orc = O.OracleNet(inst)
+        orc.step(200)
+        d = np.concatenate([net.state(k, p, snn.V) - orc.get(p, O.V) for p in (1, 2)])
+        assert math.sqrt(np.mean(d * d)) < 1e-3
+    net.close()
+
+
+def test_stdp_matches_oracle(snn):
+    """Workload-3 shape (plastic B->C, 30 Hz input) at reduced size: weights
+    after 1000 steps agree with the FP64 oracle (the GPU keeps fp32 weights
+    and traces)."""
+    say("case: STDP reduced workload 3")
+    spec = netgen.make_config(3, scale=0.02)
+    inst = spec["instances"][0]
+    T = 1000
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    net.step(T)
+    orc.step(T)
+    w_gpu = net.weights(0, 1).astype(np.float64)
+    w_orc = orc.weights(1)
+    w0 = inst["projs"][1]["g"].astype(np.float64)
+    changed = np.abs(w_orc - w0) > 0
+    say(f"  {changed.mean() * 100:.1f}% of plastic weights changed; "
+        f"max |dw| gpu-oracle {np.max(np.abs(w_gpu - w_orc)):.2e} (g_max {inst['projs'][1]['stdp']['g_max']:.2e})")
+    assert changed.mean() > 0.05
+    gmax = inst["projs"][1]["stdp"]["g_max"]
+    assert np.all(w_gpu >= 0) and np.all(w_gpu <= np.float32(gmax))
+    rel = np.linalg.norm(w_gpu - w_orc) / np.linalg.norm(w_orc - w0)
+    assert rel < 1e-3, rel
+    d = np.concatenate([net.state(0, p, snn.V) - orc.get(p, O.V) for p in (1, 2)])
+    assert math.sqrt(np.mean(d * d)) < 1e-3
+    assert np.array_equal(net.spikes(0, 2), orc.counts(2))
+    net.close()
+
+
+def test_memory_bytes_eq1(snn):
+    """Stored CRS bytes per projection: 4 * (2 nnz + n_pre + 1) (Eq. 1 with a
+    row-start array of n_pre + 1 entries)."""
+    spec = netgen.make_config(1, scale=0.3)
+    net = snn.Network(spec)
+    inst = spec["instances"][0]
+    expect = [4 * (2 * q["col_idx"].size + inst["pops"][q["pre"]]["n"] + 1) for q in inst["projs"]]
+    assert net.memory_bytes().tolist() == expect
+    net.close()

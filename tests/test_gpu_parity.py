@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer and index work (Poisson rasters, spike compaction, CSR indexing with
+integer weights) must match bit for bit; membrane voltages within 1e-3 mV
+RMS over the first 1000 steps; spike counts per neuron are reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1412_0595_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+FIX = 2.0 ** 40
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0595_amd import snn as S
+    S.load()
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_poisson_raster_bitwise(snn):
+    say("case: poisson raster, 3 populations, 300 steps")
+    inst = dict(g_scale=1.0, seed=(7 << 33) + 5,
+                pops=[dict(name="A", kind="poisson", n=1000, rate_hz=300.0, i_ext=0.0),
+                      dict(name="B", kind="poisson", n=70, rate_hz=5000.0, i_ext=0.0),
+                      dict(name="C", kind="poisson", n=3, rate_hz=20000.0, i_ext=0.0)], projs=[])
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    T = 300
+    net = snn.Network(spec, raster_steps=T)
+    net.step(T)
+    orc = O.OracleNet(inst, log_events=True)
+    orc.step(T)
+    t, p, i = orc.events()
+    for pop in range(3):
+        ras = net.raster(0, pop, 0, T)
+        for k in range(T):
+            expect = np.sort(i[(t == k) & (p == pop)])
+            assert np.array_equal(ras[k], expect), (pop, k)
+        assert np.array_equal(net.spikes(0, pop), orc.counts(pop))
+    net.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_propagation_bitwise_integer_weights(snn, seed):
+    """G after one step equals the rounded dense product d * (W^T s) on the
+    2^-40 uS grid, bit for bit (integer g makes every order exact)."""
+    say(f"case: propagation seed {seed}")
+    spec = netgen.random_tiny(seed, integer_g=True, max_n=200, p=0.4)
+    inst = spec["instances"][0]
+    rng = np.random.default_rng(100 + seed)
+    flags = {p: (rng.random(pp["n"]) < (1.0 if seed == 1 else 0.3)).astype(np.uint8)
+             for p, pp in enumerate(inst["pops"])}
+    if seed == 4:
+        flags = {p: np.zeros_like(f) for p, f in flags.items()}
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    for p, f in flags.items():
+        net.set_last_spikes(0, p, f)
+        orc.set_last_spikes(p, f)
+        assert np.array_equal(net.last_spikes(0, p), f)
+    net.step(1)
+    orc.step(1)
+    for q in range(len(inst["projs"])):
+        g_gpu = net.conductance(0, q) * FIX
+        g_orc = np.rint(orc.G(q) * FIX)
+        assert np.array_equal(g_gpu, g_orc), q
+    net.close()
+
+
+def _upstroke_state(n, spiking):
+    """V just below 0 with open sodium channels crosses 0 within one step;
+    everyone else rests."""
+    V0, m0, h0, n0 = O.rest()
+    V = np.full(n, V0)
+    m = np.full(n, m0)
+    h = np.full(n, h0)
+    nn = np.full(n, n0)
+    V[spiking] = -1.0
+    m[spiking] = 0.95
+    h[spiking] = 0.6
+    nn[spiking] = 0.3
+    return V, m, h, nn
+
+
+@pytest.mark.parametrize("pattern", ["none", "all", "w63", "w64", "w65", "sparse", "last"])
+def test_spike_compaction_bitwise(snn, pattern):
+    say(f"case: compaction {pattern}")
+    n = 200
+    idx = {"none": [], "all": list(range(n)), "w63": list(range(63)), "w64": list(range(64, 128)),
+           "w65": list(range(128, 193)), "sparse": [0, 63, 64, 127, 150, 199], "last": [199]}[pattern]
+    # each spiking neuron projects one synapse onto a counter population so
+    # the compacted work items are checked too
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32) % 7
+    inst = dict(g_scale=1.0, seed=3,
+                pops=[dict(name="X", kind="hh", n=n, rate_hz=0.0, i_ext=0.0),
+                      dict(name="Y", kind="hh", n=7, rate_hz=0.0, i_ext=0.0)],
+                projs=[dict(pre=0, post=1, row_ptr=rp, col_idx=ci, g=np.ones(n, np.float32), e_rev=0.0,
+                            tau=5.0, stdp=None)])
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    state = _upstroke_state(n, idx)
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    for var in range(4):
+        net.set_state(0, 0, var, state[var])
+        orc.set(0, var, state[var])
+    v_prev = net.state(0, 0, snn.V)
+    net.step(1)
+    orc.step(1)
+    v_new = net.state(0, 0, snn.V)
+    got = net.last_spikes(0, 0)
+    assert np.array_equal(got, ((v_prev < 0) & (v_new >= 0)).astype(np.uint8))
+    assert np.array_equal(got, orc.last_spikes(0))
+    assert sorted(np.nonzero(got)[0].tolist()) == sorted(idx)
+    net.step(1)
+    orc.step(1)
+    assert np.array_equal(np.rint(net.conductance(0, 0) * FIX), np.rint(orc.G(0) * FIX))
+    net.close()
+
+
+def test_one_step_update_from_same_state(snn):
+    """From an identical random state (including mid-spike and hyperpolarised
+    neurons and nonzero conductances) one step agrees to far below fp32."""
+    say("case: one-step update")
+    rng = np.random.default_rng(11)
+    spec = netgen.make_config(1, scale=0.3)
+    inst = spec["instances"][0]
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    for p in (1, 2):
+        n = inst["pops"][p]["n"]
+        vals = [rng.uniform(-85, 40, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)]
+        vals[0][:4] = [-52.0, -25.0, -50.0, 0.0]    # removable singularities of the rates
+        for var in range(4):
+            net.set_state(0, p, var, vals[var])
+            orc.set(p, var, net.state(0, p, var))   # the stored pair, exactly
+    for q, pr in enumerate(inst["projs"]):
+        g = rng.uniform(0, 0.02, inst["pops"][pr["post"]]["n"])
+        net.set_conductance(0, q, g)
+        orc.set_G(q, net.conductance(0, q))
+    net.step(1)
+    orc.step(1)
+    for p in (1, 2):
+        for var in range(4):
+            a, b = net.state(0, p, var), orc.get(p, var)
+            assert np.max(np.abs(a - b)) < 1e-9, (p, var, np.max(np.abs(a - b)))
+        assert np.array_equal(net.last_spikes(0, p), orc.last_spikes(p))
+    for q in range(3):
+        assert np.max(np.abs(net.conductance(0, q) - orc.G(q))) < 2e-12
+    net.close()
+
+
+def _parity_run(snn, spec, T, chunk=50, pops=(1, 2)):
+    inst = spec["instances"][0]
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    se = 0.0
+    cnt = 0
+    for _ in range(T // chunk):
+        net.step(chunk)
+        for _k in range(chunk):
+            orc.step(1)
+        for p in pops:
+            d = net.state(0, p, snn.V) - orc.get(p, O.V)
+            se += float(np.sum(d * d))
+            cnt += d.size
+    return net, orc, math.sqrt(se / cnt)
+
+
+def test_network_parity_workload1(snn):
+    """Workload 1 (A=100 Poisson, B=1000, C=100 HH): V RMS over all HH
+    neurons, sampled every step of the first 1000, within 1e-3 mV; then spike
+    counts per neuron over the full 10000 steps."""
+    say("case: workload 1, 1000-step V trace")
+    spec = netgen.make_config(1)
+    inst = spec["instances"][0]
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    se, cnt = 0.0, 0
+    for t in range(1000):
+        net.step(1)
+        orc.step(1)
+        for p in (1, 2):
+            d = net.state(0, p, snn.V) - orc.get(p, O.V)
+            se += float(np.sum(d * d))
+            cnt += d.size
+    rms = math.sqrt(se / cnt)
+    c1000 = [(net.spikes(0, p), orc.counts(p)) for p in (1, 2)]
+    say(f"workload 1: V RMS over steps 1..1000 = {rms:.3e} mV")
+    assert rms <= 1e-3
+    for p, (a, b) in zip((1, 2), c1000):
+        say(f"  pop {p}: counts identical for {np.mean(a == b) * 100:.2f}% of neurons at step 1000, "
+            f"max |diff| {np.max(np.abs(a - b))}")
+        assert np.array_equal(a, b)
+    say("case: workload 1, steps 1000..10000")
+    net.step(9000)
+    orc.step(9000)
+    assert np.array_equal(net.spikes(0, 0), orc.counts(0))
+    for p in (1, 2):
+        a, b = net.spikes(0, p), orc.counts(p)
+        frac = np.mean(a == b)
+        say(f"  pop {p}: counts identical for {frac * 100:.2f}% of neurons at step 10000, "
+            f"max |diff| {np.max(np.abs(a - b))}, mean rate {b.mean():.1f} Hz")
+        assert frac > 0.9
+    assert net.nan_counts()[0] == orc.nan_count == 0
+    net.close()
+
+
+def test_network_parity_workload2_short(snn):
+    """Workload 2 (A=1000, B=20000, C=1000; 15M synapses) for 300 steps."""
+    say("case: workload 2, 300 steps")
+    spec = netgen.make_config(2)
+    net, orc, rms = _parity_run(snn, spec, 300)
+    say(f"workload 2: V RMS over steps 1..300 (every 50th) = {rms:.3e} mV")
+    assert rms <= 1e-3
+    assert np.array_equal(net.spikes(0, 0), orc.counts(0))
+    for p in (1, 2):
+        assert np.mean(net.spikes(0, p) == orc.counts(p)) > 0.999
+    net.close()
+
+
+def test_graph_and_direct_launches_agree(snn):
+    """64 steps through the captured graph equal 64 single-step launches."""
+    say("case: graph vs direct")
+    spec = netgen.make_config(1, scale=0.5)
+    a = snn.Network(spec)
+    b = snn.Network(spec)
+    a.step(64)
+    for _ in range(64):
+        b.step(1)
+    for p in (1, 2):
+        for var in range(4):
+            assert np.array_equal(a.state(0, p, var), b.state(0, p, var))
+        assert np.array_equal(a.spikes(0, p), b.spikes(0, p))
+    a.close()
+    b.close()
+
+
+def test_launch_shape_does_not_change_results(snn):
+    say("case: launch shapes")
+    spec = netgen.make_config(1, scale=0.5)
+    ref = snn.Network(spec)
+    ref.step(200)
+    for shape in [dict(neuron_block=64, prop_blocks=7, prop_block=64, chunk=64),
+                  dict(neuron_block=1024, prop_blocks=4096, prop_block=1024, chunk=2048)]:
+        n = snn.Network(spec)
+        n.set_launch(**shape)
+        n.step(200)
+        for p in (1, 2):
+            assert np.array_equal(n.state(0, p, snn.V), ref.state(0, p, snn.V))
+            assert np.array_equal(n.spikes(0, p), ref.spikes(0, p))
+        for q in range(3):
+            assert np.array_equal(n.conductance(0, q), ref.conductance(0, q))
+        n.close()
+    ref.close()
+
+
+def test_vbar_accumulates_post_step_voltage(snn):
+    say("case: vbar")
+    spec = netgen.make_config(1, scale=0.3)
+    net = snn.Network(spec, record_vbar=("C",))
+    orc = O.OracleNet(spec["instances"][0])
+    acc = np.zeros(spec["instances"][0]["pops"][2]["n"])
+    for _ in range(100):
+        net.step(1)
+        orc.step(1)
+        acc += net.state(0, 2, snn.V)
+    vs = net.vbar_sum(0, 2)
+    assert np.allclose(vs, acc, rtol=0, atol=1e-9)
+    assert np.max(np.abs(vs - orc.vsum(2))) < 1e-3
+    net.close()
