@@ -25,12 +25,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X fp64 vector peak (FMA = 2 flops)
 
 # Algorithmic traffic per unit (bytes), stated in the design notes:
-#  - propagation: 8 B per synaptic event (col_idx + weight) + 16 B per work
-#    item (the item itself) + 8 B per row (its two row-start entries)
+#  - propagation: 8 B per synaptic event (col_idx + weight) + 16 B per
+#    spiking row (its work item and its two row-start entries)
 #  - neuron update: per Traub-Miles neuron-step, 4 double-float state
 #    variables read and written (64 B) + 16 B per incoming projection
 #    (64-bit conductance read and written)
 PROP_BYTES_PER_EVENT = 8
+PROP_BYTES_PER_ROW = 16
 NEURON_STATE_BYTES = 64
 NEURON_G_BYTES = 16
 
@@ -48,7 +49,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=500)
     return ap.parse_args()
 
 
@@ -113,19 +114,28 @@ def main():
     neuron_steps = n_hh * args.steps / sec
     events_s = events / sec
 
-    # per-kernel durations, hipEvents around each launch (same stream)
-    kms = net.profile_kernels(args.profile_steps)
-    c2 = spike_totals(net, spec)
-    ev_prof = sum(int(((c2[b][p] - c1[b][p]) * deg[b][p]).sum()) for b in range(len(c1)) for p in range(len(c1[b])))
-    items_prof = sum(int(((c2[b][p] - c1[b][p]) * 0).sum()) for b in range(len(c1)) for p in range(len(c1[b])))
+    # Per-kernel launch duration: one hipEvent pair around `profile_steps`
+    # back-to-back launches of that kernel alone on the final state (state
+    # restored afterwards).  The propagation launches all walk the pending
+    # spikes of the last step; the neuron launches update every neuron.
+    pend_events = 0
+    pend_rows = 0
+    for b in range(len(spec["instances"])):
+        for p in range(len(spec["instances"][b]["pops"])):
+            f = net.last_spikes(b, p).astype(bool)
+            pend_events += int(deg[b][p][f].sum())
+            pend_rows += int(f.sum()) * sum(1 for q in spec["instances"][b]["projs"] if q["pre"] == p)
+    k_prop = net.time_kernel(0, args.profile_steps)
+    k_neur = net.time_kernel(2, args.profile_steps)
     n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
                for inst in spec["instances"] for k in range(len(inst["pops"])))
     neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
-    prop_bytes = PROP_BYTES_PER_EVENT * ev_prof / args.profile_steps
+    prop_bytes = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
     kern = {
-        "propagate": dict(ms=kms[0], bytes=prop_bytes),
-        "neuron": dict(ms=kms[2], bytes=neuron_bytes),
+        "propagate": dict(ms=k_prop, bytes=prop_bytes),
+        "neuron": dict(ms=k_neur, bytes=neuron_bytes),
     }
+    # dominant = larger share of the timed step
     dom = max(kern, key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
     roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,

@@ -245,11 +245,13 @@ int snn_set_launch(snn_net *net, const snn_launch *in);
  * the autotuner; leaves the net's state as it found it. */
 int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms);
 
-/* Advance the net by n_steps single-step launches with a hipEvent pair
- * around every kernel, and return the mean duration in milliseconds of each
- * kernel over those steps: ms[0] propagation, ms[1] potentiation (0 if no
- * projection is plastic), ms[2] neuron update.  Synchronises. */
-int snn_profile_kernels(snn_net *net, int64_t n_steps, double *ms);
+/* Mean milliseconds per launch of one step kernel (which: 0 propagation,
+ * 1 potentiation, 2 neuron update), timed with one hipEvent pair around
+ * `launches` back-to-back launches of that kernel alone on the net's
+ * current state; the state is restored afterwards.  Propagation and
+ * potentiation consume the same pending work items at every launch.
+ * Synchronises. */
+int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_per_launch);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *snn_last_error(void);

@@ -221,8 +221,7 @@ NeuronArgs neuron_args(snn_net *net)
     return a;
 }
 
-// Enqueue one whole step on stream s.
-hipError_t enqueue_step(snn_net *net, hipStream_t s)
+PropArgs prop_args(snn_net *net)
 {
     PropArgs p{};
     p.projs = net->d_projs;
@@ -234,19 +233,30 @@ hipError_t enqueue_step(snn_net *net, hipStream_t s)
     p.G = net->G;
     p.trace = net->trace;
     p.st = net->st;
-    hipError_t e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, s);
+    return p;
+}
+
+LtpArgs ltp_args(snn_net *net)
+{
+    LtpArgs l{};
+    l.projs = net->d_projs;
+    l.lqueue = net->lqueue;
+    l.lcap = net->lcap;
+    l.csc_row = net->d_csc_row;
+    l.csc_pos = net->d_csc_pos;
+    l.w_pool = net->d_w;
+    l.trace = net->trace;
+    l.st = net->st;
+    return l;
+}
+
+// Enqueue one whole step on stream s.
+hipError_t enqueue_step(snn_net *net, hipStream_t s)
+{
+    hipError_t e = launch_propagate(prop_args(net), net->launch.prop_blocks, net->launch.prop_block, s);
     if (e != hipSuccess) return e;
     if (net->plastic) {
-        LtpArgs l{};
-        l.projs = net->d_projs;
-        l.lqueue = net->lqueue;
-        l.lcap = net->lcap;
-        l.csc_row = net->d_csc_row;
-        l.csc_pos = net->d_csc_pos;
-        l.w_pool = net->d_w;
-        l.trace = net->trace;
-        l.st = net->st;
-        e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, s);
+        e = launch_potentiate(ltp_args(net), net->launch.prop_blocks, net->launch.prop_block, s);
         if (e != hipSuccess) return e;
     }
     return launch_neuron(neuron_args(net), net->launch.neuron_block, s);
@@ -421,6 +431,48 @@ int check_range(const snn_net *net, const std::vector<double> &colmax_sum, const
 }
 
 }  // namespace
+
+// Run `body` between a hipEvent pair on a snapshot of everything a step
+// mutates, then restore the snapshot; *ms gets the elapsed milliseconds.
+template <class F>
+static int timed_on_snapshot(snn_net *net, F body, double *ms_out)
+{
+    void *snap = nullptr, *wsnap = nullptr;
+    HIP_OK(hipMalloc(&snap, (size_t)net->arena_bytes));
+    if (net->plastic && hipMalloc(&wsnap, 4 * (size_t)std::max<int64_t>(net->w_count, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(snap);
+        return fail(SNN_ENOMEM, "snapshot allocation failed");
+    }
+    const int64_t t_saved = net->t;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SNN_OK;
+    hipError_t e = hipMemcpyAsync(snap, net->d_arena, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && wsnap) e = hipMemcpyAsync(wsnap, net->d_w, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, net->stream);
+    if (e == hipSuccess) rc = body();
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventRecord(e1, net->stream);
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && rc == SNN_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && rc == SNN_OK) e = hipMemcpyAsync(net->d_arena, snap, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && rc == SNN_OK && wsnap) e = hipMemcpyAsync(net->d_w, wsnap, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
+    if (e == hipSuccess && rc == SNN_OK) e = hipStreamSynchronize(net->stream);
+    net->t = t_saved;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    if (wsnap) (void)hipFree(wsnap);
+    if (rc) return rc;
+    if (e != hipSuccess) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "timing failed: %s", hipGetErrorString(e));
+    }
+    *ms_out = (double)ms;
+    return SNN_OK;
+}
 
 // ============================== C ABI ========================================
 extern "C" {
@@ -1075,86 +1127,40 @@ int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms)
     int rc = check_net(net);
     if (rc) return rc;
     if (n_steps < 1 || !out_ms) return fail(SNN_EINVAL, "need n_steps >= 1 and an output");
-    // snapshot everything a step mutates
-    void *snap = nullptr, *wsnap = nullptr;
-    HIP_OK(hipMalloc(&snap, (size_t)net->arena_bytes));
-    if (net->plastic && hipMalloc(&wsnap, 4 * (size_t)std::max<int64_t>(net->w_count, 1)) != hipSuccess) {
-        (void)hipFree(snap);
-        net->sticky = true;
-        return fail(SNN_ENOMEM, "snapshot allocation failed");
-    }
-    const int64_t t_saved = net->t;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMemcpyAsync(snap, net->d_arena, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
-    if (e == hipSuccess && wsnap) e = hipMemcpyAsync(wsnap, net->d_w, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = hipEventRecord(e0, net->stream);
-    if (e == hipSuccess) rc = run_steps(net, n_steps);
-    if (e == hipSuccess && rc == SNN_OK) e = hipEventRecord(e1, net->stream);
-    if (e == hipSuccess && rc == SNN_OK) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess && rc == SNN_OK) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && rc == SNN_OK) e = hipMemcpyAsync(net->d_arena, snap, (size_t)net->arena_bytes, hipMemcpyDeviceToDevice, net->stream);
-    if (e == hipSuccess && rc == SNN_OK && wsnap) e = hipMemcpyAsync(net->d_w, wsnap, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream);
-    if (e == hipSuccess && rc == SNN_OK) e = hipStreamSynchronize(net->stream);
-    net->t = t_saved;
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(snap);
-    if (wsnap) (void)hipFree(wsnap);
+    // capture the graph before the clock starts: host capture time is not step time
+    if (n_steps >= kGraphSteps && !net->graph_exec && (rc = build_graph(net))) return rc;
+    double ms = 0.0;
+    rc = timed_on_snapshot(net, [&]() { return run_steps(net, n_steps); }, &ms);
     if (rc) return rc;
-    if (e != hipSuccess) {
-        net->sticky = true;
-        return fail(SNN_EDEVICE, "timing failed: %s", hipGetErrorString(e));
-    }
-    *out_ms = (double)ms / (double)n_steps;
+    *out_ms = ms / (double)n_steps;
     return SNN_OK;
 }
 
-int snn_profile_kernels(snn_net *net, int64_t n_steps, double *ms)
+int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_per_launch)
 {
     int rc = check_net(net);
     if (rc) return rc;
-    if (n_steps < 1 || n_steps > 100000 || !ms) return fail(SNN_EINVAL, "need 1 <= n_steps <= 100000 and an output");
-    const int nk = 3;
-    std::vector<hipEvent_t> ev((size_t)(2 * nk * n_steps), nullptr);
-    for (auto &e : ev) HIP_OK(hipEventCreate(&e));
-    PropArgs p{};
-    p.projs = net->d_projs; p.queue = net->queue; p.qcap = net->qcap; p.col_pool = net->d_col; p.w_pool = net->d_w;
-    p.gscale = net->d_gscale; p.G = net->G; p.trace = net->trace; p.st = net->st;
-    LtpArgs l{};
-    l.projs = net->d_projs; l.lqueue = net->lqueue; l.lcap = net->lcap; l.csc_row = net->d_csc_row;
-    l.csc_pos = net->d_csc_pos; l.w_pool = net->d_w; l.trace = net->trace; l.st = net->st;
-    const NeuronArgs a = neuron_args(net);
-    hipError_t e = hipSuccess;
-    for (int64_t k = 0; k < n_steps && e == hipSuccess; ++k) {
-        hipEvent_t *E = &ev[(size_t)(2 * nk * k)];
-        e = hipEventRecord(E[0], net->stream);
-        if (e == hipSuccess) e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream);
-        if (e == hipSuccess) e = hipEventRecord(E[1], net->stream);
-        if (e == hipSuccess) e = hipEventRecord(E[2], net->stream);
-        if (e == hipSuccess && net->plastic) e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, net->stream);
-        if (e == hipSuccess) e = hipEventRecord(E[3], net->stream);
-        if (e == hipSuccess) e = hipEventRecord(E[4], net->stream);
-        if (e == hipSuccess) e = launch_neuron(a, net->launch.neuron_block, net->stream);
-        if (e == hipSuccess) e = hipEventRecord(E[5], net->stream);
-        if (e == hipSuccess) net->t += 1;
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
-    double sum[3] = {0, 0, 0};
-    for (int64_t k = 0; k < n_steps && e == hipSuccess; ++k)
-        for (int j = 0; j < nk && e == hipSuccess; ++j) {
-            float t = 0.0f;
-            e = hipEventElapsedTime(&t, ev[(size_t)(2 * nk * k + 2 * j)], ev[(size_t)(2 * nk * k + 2 * j + 1)]);
-            sum[j] += t;
+    if (which < 0 || which > 2) return fail(SNN_EINVAL, "which must be 0, 1 or 2");
+    if (which == 1 && !net->plastic) return fail(SNN_ESTATE, "no plastic projection");
+    if (launches < 1 || launches > 1000000 || !ms_per_launch) return fail(SNN_EINVAL, "need 1 <= launches <= 1e6 and an output");
+    PropArgs p = prop_args(net);
+    LtpArgs l = ltp_args(net);
+    NeuronArgs a = neuron_args(net);
+    double ms = 0.0;
+    rc = timed_on_snapshot(net, [&]() -> int {
+        for (int64_t k = 0; k < launches; ++k) {
+            hipError_t e = which == 0 ? launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream)
+                         : which == 1 ? launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, net->stream)
+                                      : launch_neuron(a, net->launch.neuron_block, net->stream);
+            if (e != hipSuccess) {
+                net->sticky = true;
+                return fail(SNN_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+            }
         }
-    for (auto &x : ev) (void)hipEventDestroy(x);
-    if (e != hipSuccess) {
-        net->sticky = true;
-        return fail(SNN_EDEVICE, "kernel profiling failed: %s", hipGetErrorString(e));
-    }
-    for (int j = 0; j < nk; ++j) ms[j] = net->plastic || j != 1 ? sum[j] / (double)n_steps : 0.0;
+        return SNN_OK;
+    }, &ms);
+    if (rc) return rc;
+    *ms_per_launch = ms / (double)launches;
     return SNN_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "snn_get_spikes", "snn_get_raster", "snn_get_state", "snn_set_state", "snn_get_state_f64",
     "snn_set_state_f64", "snn_get_conductance", "snn_set_conductance", "snn_get_last_spikes",
     "snn_set_last_spikes", "snn_get_vbar", "snn_get_nan_counts", "snn_set_gscale", "snn_get_weights",
-    "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_profile_kernels",
+    "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel",
     "snn_last_error",
 ]
 
@@ -106,7 +106,7 @@ def load():
         "snn_get_launch": (C.c_int, [vp, vp]),
         "snn_set_launch": (C.c_int, [vp, vp]),
         "snn_time_steps": (C.c_int, [vp, i64, vp]),
-        "snn_profile_kernels": (C.c_int, [vp, i64, vp]),
+        "snn_time_kernel": (C.c_int, [vp, i32, i64, vp]),
         "snn_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -259,12 +259,12 @@ class Network:
         _check(load().snn_time_steps(self.h, int(n), C.byref(out)))
         return out.value
 
-    def profile_kernels(self, n):
-        """Mean ms per launch of (propagate, potentiate, neuron) over n
-        single-step launches bracketed by hipEvents; advances the net."""
-        out = np.zeros(3)
-        _check(load().snn_profile_kernels(self.h, int(n), _p(out)))
-        return out
+    def time_kernel(self, which, launches):
+        """Mean ms per launch of one kernel (0 propagate, 1 potentiate,
+        2 neuron) over back-to-back launches on a snapshot of the state."""
+        out = C.c_double()
+        _check(load().snn_time_kernel(self.h, int(which), int(launches), C.byref(out)))
+        return out.value
 
     # ----------------------------------------------------------------- state
     def _n(self, inst, pop):
