@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "snn_oracle.c"), os.path.join(HERE, "snn_adjoint.c")]
+DEPS = SRC + [os.path.join(HERE, "snn_oracle.h")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 POISSON, HH = 0, 1
@@ -24,7 +25,7 @@ V, M, H, N = 0, 1, 2, 3
 def build(force=True):
     """Compile the oracle with gcc (portable flags, no fast-math)."""
     srcs = [s for s in SRC if os.path.exists(s)]
-    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(s) for s in srcs):
+    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(s) for s in DEPS):
         return LIB
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
@@ -78,6 +79,9 @@ def lib():
             "orc_take_events": (i64, [vp, vp, vp, vp, i64]),
             "orc_set_replay": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, i64]),
             "orc_destroy": (None, [vp]),
+            "orc_dphi": (d, [d]),
+            "orc_substep_vjp": (None, [vp, d, vp, vp, vp, vp]),
+            "orc_adjoint": (C.c_int, [vp, i64, C.c_int, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             if not hasattr(L, name):
@@ -106,6 +110,35 @@ def rest(hh=None):
     if rc != 0:
         raise ValueError("no resting point in [-80, -60] mV")
     return tuple(float(x[0]) for x in o)
+
+
+def substep_vjp(hh, hs, x, lam_out):
+    """(lam_in[4], lam_I) of one Euler substep at state x = (V, m, h, n)."""
+    hh = np.ascontiguousarray(hh, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    lo = np.ascontiguousarray(lam_out, np.float64)
+    li = np.zeros(4)
+    lI = np.zeros(1)
+    lib().orc_substep_vjp(_p(hh), float(hs), _p(x), _p(lo), _p(li), _p(lI))
+    return li, float(lI[0])
+
+
+def substep(hh, hs, i_in, x):
+    hh = np.ascontiguousarray(hh, np.float64)
+    v = [np.array([float(a)]) for a in x]
+    lib().orc_substep(_p(hh), float(hs), float(i_in), *[_p(a) for a in v])
+    return np.array([a[0] for a in v])
+
+
+def raster_arrays(events, n_pops, T):
+    """(offsets, ids) of an event log for orc_set_replay: ids ascending per
+    (step, population)."""
+    t, p, i = events
+    key = t.astype(np.int64) * n_pops + p
+    order = np.lexsort((i, key))
+    off = np.zeros(T * n_pops + 1, np.int64)
+    np.cumsum(np.bincount(key, minlength=T * n_pops)[:T * n_pops], out=off[1:])
+    return off, i[order].astype(np.int32)
 
 
 def philox(ctr, key):
@@ -237,6 +270,22 @@ class OracleNet:
         t, p, i = (np.zeros(n, np.int32) for _ in range(3))
         lib().orc_take_events(self.h, _p(t), _p(p), _p(i), n)
         return t, p, i
+
+    def adjoint(self, T, loss_pop, dLdVbar):
+        """Run T steps from the initial state and the reverse pass: returns
+        (vbar, [dL/dg per projection], dL/dg_scale)."""
+        n = int(self.pops[loss_pop]["n"])
+        dv = np.ascontiguousarray(dLdVbar, np.float64)
+        assert dv.size == n
+        grads = [np.zeros(max(1, int(np.asarray(q["col_idx"]).size))) for q in self.inst["projs"]]
+        ptrs = (C.c_void_p * max(1, len(grads)))(*[g.ctypes.data for g in grads])
+        dls = np.zeros(1)
+        vbar = np.zeros(n)
+        rc = lib().orc_adjoint(self.h, int(T), int(loss_pop), _p(dv), C.cast(ptrs, C.c_void_p), _p(dls), _p(vbar))
+        if rc != 0:
+            raise ValueError("adjoint: bad arguments or plastic network")
+        grads = [g[:int(np.asarray(q["col_idx"]).size)] for g, q in zip(grads, self.inst["projs"])]
+        return vbar, grads, float(dls[0])
 
     def set_replay(self, pop, off, ids, T):
         """Population pop takes its spikes from a raster; off has T*n_pops+1 entries."""

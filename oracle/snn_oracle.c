@@ -34,8 +34,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_POISSON = 0, ORC_HH = 1 };
-enum { HH_GNA = 0, HH_ENA, HH_GK, HH_EK, HH_GL, HH_EL, HH_CM, HH_NPARAM };
+#include "snn_oracle.h"
+
 
 /* ------------------------------------------------------------------ */
 /* Traub-Miles kinetics.  V in mV, rates in 1/ms.                      */
@@ -163,58 +163,6 @@ int orc_poisson_fires(uint64_t seed, int64_t t, int32_t i, uint64_t thresh)
     orc_philox4x32_10(ctr, key, out);
     return (uint64_t)out[0] < thresh;
 }
-
-/* ------------------------------------------------------------------ */
-/* Network                                                            */
-/* ------------------------------------------------------------------ */
-#define ORC_MAX_POPS 16
-#define ORC_MAX_PROJS 32
-
-typedef struct {
-    int kind, n;
-    double rate_hz, i_ext, hh[HH_NPARAM];
-    uint64_t thresh;
-    double *V, *m, *h, *nn;      /* HH state */
-    unsigned char *spk_prev;     /* spikes of the previous step */
-    unsigned char *spk_now;      /* spikes of the current step */
-    int32_t *count;              /* spikes per neuron since init */
-    double *vsum;                /* sum of post-step V since init */
-    int replay;                  /* 1: spikes come from the replay raster */
-} opop;
-
-typedef struct {
-    int pre, post;
-    int64_t nnz;
-    int32_t *row_ptr, *col_idx;
-    double *g;                   /* fp32 input widened exactly */
-    double e_rev, tau;
-    double *G;                   /* post-side conductance, n_post */
-    int stdp;
-    double a_plus, a_minus, tau_stdp, g_max;
-    double *x, *y;               /* pre and post traces */
-    int32_t *col_ptr, *row_of, *perm;  /* column view for potentiation */
-} oproj;
-
-typedef struct orc_net {
-    double dt;
-    int substeps;
-    double g_scale;
-    uint64_t seed;
-    int n_pops, n_projs;
-    opop pops[ORC_MAX_POPS];
-    oproj projs[ORC_MAX_PROJS];
-    int64_t t;                   /* index of the next step */
-    int64_t nan_count;           /* HH neurons whose V turned non-finite */
-    int ready;
-    /* event log: (t, pop, id) of every spike, when enabled */
-    int log_events;
-    int64_t ev_n, ev_cap;
-    int32_t *ev_t, *ev_pop, *ev_id;
-    /* replay raster for populations marked replay: per step, per pop, ids */
-    const int64_t *rp_off;       /* [(t * n_pops + pop)] -> start in rp_ids; size T*n_pops+1 */
-    const int32_t *rp_ids;
-    int64_t rp_T;
-} orc_net;
 
 orc_net *orc_create(double dt, int substeps, double g_scale, uint64_t seed)
 {
@@ -346,15 +294,13 @@ static void log_event(orc_net *net, int64_t t, int pop, int id)
     net->ev_n++;
 }
 
-/* One timestep t = net->t. */
-static void orc_step1(orc_net *net)
+/* Phase 1 of step t: deliver the spikes of step t-1 through every
+ * projection; on a plastic projection, then depress each delivered synapse
+ * by the post trace of step t-1 (delivery uses the weight before the
+ * update). */
+void orc_phase_deliver(orc_net *net)
 {
-    const int64_t t = net->t;
     const double s = net->g_scale;
-
-    /* 1. Deliver the spikes of step t-1 through every projection; then, on a
-     *    plastic projection, depress each delivered synapse by the post
-     *    trace of step t-1 (delivery uses the weight before the update). */
     for (int q = 0; q < net->n_projs; ++q) {
         oproj *Q = &net->projs[q];
         const opop *pre = &net->pops[Q->pre];
@@ -369,9 +315,12 @@ static void orc_step1(orc_net *net)
                 }
         }
     }
+}
 
-    /* 2. Potentiation: every synapse onto a post neuron that spiked at t-1
-     *    grows by the pre trace of step t-1. */
+/* Phase 2: potentiation, every synapse onto a post neuron that spiked at
+ * t-1 grows by the pre trace of step t-1. */
+void orc_phase_potentiate(orc_net *net)
+{
     for (int q = 0; q < net->n_projs; ++q) {
         oproj *Q = &net->projs[q];
         if (!Q->stdp) continue;
@@ -385,9 +334,14 @@ static void orc_step1(orc_net *net)
             }
         }
     }
+}
 
-    /* 3. HH populations: synaptic current from the start-of-step V, Euler
-     *    substeps, conductance decay, upward crossing of 0 mV. */
+/* Phase 3: HH populations (synaptic current from the start-of-step V, Euler
+ * substeps, upward crossing of 0 mV), conductance decay, Poisson sources of
+ * step t, replayed populations. */
+void orc_phase_neurons(orc_net *net)
+{
+    const int64_t t = net->t;
     const double hs = net->dt / net->substeps;
     for (int p = 0; p < net->n_pops; ++p) {
         opop *P = &net->pops[p];
@@ -412,16 +366,12 @@ static void orc_step1(orc_net *net)
         double d = exp(-net->dt / Q->tau);
         for (int j = 0; j < net->pops[Q->post].n; ++j) Q->G[j] *= d;
     }
-
-    /* 4. Poisson sources of step t. */
     for (int p = 0; p < net->n_pops; ++p) {
         opop *P = &net->pops[p];
         if (P->kind != ORC_POISSON) continue;
         for (int i = 0; i < P->n; ++i)
             P->spk_now[i] = (unsigned char)orc_poisson_fires(net->seed, t, i, P->thresh);
     }
-
-    /* Replay: populations marked replay take their spikes from the raster. */
     if (net->rp_off) {
         for (int p = 0; p < net->n_pops; ++p) {
             opop *P = &net->pops[p];
@@ -433,8 +383,12 @@ static void orc_step1(orc_net *net)
             }
         }
     }
+}
 
-    /* 5. Counts, event log, STDP traces, then S(t) becomes S(t-1). */
+/* Phase 4: counts, event log, STDP traces; S(t) becomes S(t-1). */
+void orc_phase_finish(orc_net *net)
+{
+    const int64_t t = net->t;
     for (int p = 0; p < net->n_pops; ++p) {
         opop *P = &net->pops[p];
         for (int i = 0; i < P->n; ++i)
@@ -458,6 +412,15 @@ static void orc_step1(orc_net *net)
         P->spk_now = tmp;
     }
     net->t = t + 1;
+}
+
+/* One timestep t = net->t: the four phases in order. */
+static void orc_step1(orc_net *net)
+{
+    orc_phase_deliver(net);
+    orc_phase_potentiate(net);
+    orc_phase_neurons(net);
+    orc_phase_finish(net);
 }
 
 int orc_step(orc_net *net, int64_t n_steps)
