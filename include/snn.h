@@ -185,7 +185,8 @@ int64_t snn_time(const snn_net *net);
 int snn_get_spikes(snn_net *net, int32_t inst, int32_t pop, int32_t *counts);
 
 /* Raster of population pop of instance inst for steps [t0, t1), which must
- * lie within the last raster_steps steps.  offsets (host int64[t1-t0+1])
+ * lie within the last raster_steps steps, or, after snn_forward_record and
+ * until the next reset, within the recorded steps.  offsets (host int64[t1-t0+1])
  * receives the start of each step's ids in `ids` (host int32[cap]),
  * ascending within a step.  Returns SNN_ERANGE if cap is too small
  * (offsets[t1-t0] still holds the needed size).  Synchronises. */
@@ -252,6 +253,52 @@ int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms);
  * potentiation consume the same pending work items at every launch.
  * Synchronises. */
 int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_per_launch);
+
+/* Restore the state created by snn_create: every Traub-Miles neuron at its
+ * resting point, conductances, traces, counts, Vbar sums, NaN counts and
+ * spikes at zero, step counter 0.  Weights (including STDP changes) and
+ * g_scale are kept.  Enqueued on the net's stream. */
+int snn_reset(snn_net *net);
+
+/* Total number of synapses of the batch (the length of the weight pool),
+ * or -1 for NULL.  The pool holds the weights of every projection in
+ * instance-major, projection order, each in CRS order; snn_weight_offset
+ * gives where (inst, proj) starts. */
+int64_t snn_weight_count(const snn_net *net);
+int snn_weight_offset(const snn_net *net, int32_t inst, int32_t proj, int64_t *offset);
+
+/* Copy the whole weight pool to / from caller-owned device memory
+ * (float[snn_weight_count]) on the net's stream.  The write checks on the
+ * device that every weight is finite and >= 0 (SNN_EINVAL otherwise,
+ * nothing copied) and synchronises for that check. */
+int snn_get_weights_device(snn_net *net, float *dst_dev);
+int snn_set_weights_device(snn_net *net, const float *src_dev);
+
+/* Forward pass recorded for the adjoint (the "differentiation" extension:
+ * gradients of a loss on the time-averaged voltage Vbar of population pop
+ * with respect to every weight and every g_scale).  Resets the net
+ * (snn_reset), runs n_steps steps keeping the spike bitmask of every step
+ * and a checkpoint of the neuron state every ckpt_every steps, and writes
+ * Vbar_j = (1/n_steps) sum_t V_j(t) of population pop of every instance to
+ * vbar_dev (device double[sum over instances of n_pop], instance-major).
+ * Requires: population pop created with record_vbar = 1 in every instance,
+ * at most 1024 neurons per instance, substeps <= 8, no plastic projection.
+ * Device memory: 8 B per neuron-wave word per step (raster) + (32 B per
+ * neuron + 8 B per conductance) per checkpoint. */
+int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_every, double *vbar_dev);
+
+/* Reverse pass of the last snn_forward_record, exact for the discrete
+ * forward map with the recorded spike raster held fixed.  dL_dvbar_dev
+ * (device double, same layout as vbar_dev) is the loss gradient; the call
+ * writes dL/dg for every synapse into dL_dg_dev (device float[weight
+ * count], weight-pool order; projections that do not reach pop get 0) and
+ * dL/dg_scale into dL_dgscale_dev (device double[n_instances], accumulated
+ * in double).  Each segment between checkpoints is recomputed from its
+ * checkpoint; *mismatch (may be NULL; then the call stays asynchronous)
+ * receives the number of state values at which a recomputed segment end
+ * differs from the next stored checkpoint (0 expected). */
+int snn_backward(snn_net *net, const double *dL_dvbar_dev, float *dL_dg_dev, double *dL_dgscale_dev,
+                 int64_t *mismatch);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *snn_last_error(void);

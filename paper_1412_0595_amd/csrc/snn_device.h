@@ -1,0 +1,117 @@
+// Device functions shared by the step kernels and the adjoint kernels, so
+// that a recomputed step performs exactly the arithmetic of the forward step.
+#pragma once
+
+#include "snn_internal.h"
+
+namespace snn {
+
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with the key bumped by the Weyl constants between
+// rounds.  Only the first output word is needed for a Bernoulli draw.
+__device__ __forceinline__ uint32_t philox_first_word(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                      uint32_t key0, uint32_t key1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_lo = 0xD2511F53u * x0, a_hi = __umulhi(0xD2511F53u, x0);
+        const uint32_t b_lo = 0xCD9E8D57u * x2, b_hi = __umulhi(0xCD9E8D57u, x2);
+        x0 = b_hi ^ x1 ^ key0;
+        x1 = b_lo;
+        x2 = a_hi ^ x3 ^ key1;
+        x3 = a_lo;
+        key0 += 0x9E3779B9u;
+        key1 += 0xBB67AE85u;
+    }
+    return x0;
+}
+
+// x / (e^x - 1) with its limit 1 at x = 0 (expm1 keeps it accurate near 0).
+__device__ __forceinline__ double xexpm1_ratio(double x)
+{
+    return x == 0.0 ? 1.0 : x / expm1(x);
+}
+
+// Wave-wide inclusive sum (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Fixed-point increment of one delivered synapse: g_scale * g on the
+// 2^-40 uS grid (s_fix = g_scale * 2^40; the product of two fp32 values is
+// exact in double, so the only rounding is the final one).
+__device__ __forceinline__ long long fix_increment(double s_fix, float w)
+{
+    return __double2ll_rn(s_fix * (double)w);
+}
+
+__device__ __forceinline__ int64_t fix_decay(int64_t g, double d)
+{
+    return __double2ll_rn((double)g * d);
+}
+
+// Synaptic + external current of a neuron with start-of-step voltage v0 and
+// delivered conductances g[0..n_in).
+__device__ __forceinline__ double syn_current(const Seg &S, const int64_t *g, double v0)
+{
+    double iin = S.i_ext;
+#pragma unroll
+    for (int q = 0; q < kMaxIn; ++q)
+        if (q < S.n_in) iin += (double)g[q] * kFixInv * (S.in_erev[q] - v0);
+    return iin;
+}
+
+// Traub-Miles right-hand side at (v, m, h, n): rates and the four
+// derivatives; iin is the injected current held over the step.
+struct HHRates {
+    double am, bm, ah, bh, an, bn;
+};
+
+__device__ __forceinline__ HHRates hh_rates(double v)
+{
+    HHRates r;
+    r.am = 1.28 * xexpm1_ratio((-52.0 - v) * 0.25);
+    r.bm = 1.4 * xexpm1_ratio((v + 25.0) * 0.2);
+    r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
+    r.bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
+    r.an = 0.16 * xexpm1_ratio((-50.0 - v) * 0.2);
+    r.bn = 0.5 * exp((-55.0 - v) * 0.025);
+    return r;
+}
+
+// One forward-Euler substep, every right-hand side from the substep-start state.
+__device__ __forceinline__ void hh_substep(const Seg &S, double hs, double hc, double iin, double &v, double &m,
+                                           double &h, double &n)
+{
+    const HHRates r = hh_rates(v);
+    const double n2 = n * n;
+    const double iion = S.gna * (m * m * m * h) * (v - S.ena) + S.gk * (n2 * n2) * (v - S.ek) + S.gl * (v - S.el);
+    const double vn = v + hc * (iin - iion);
+    const double mn = m + hs * (r.am * (1.0 - m) - r.bm * m);
+    const double hn = h + hs * (r.ah * (1.0 - h) - r.bh * h);
+    const double nn = n + hs * (r.an * (1.0 - n) - r.bn * n);
+    v = vn;
+    m = mn;
+    h = hn;
+    n = nn;
+}
+
+// A double held as an fp32 pair (hi = fl32(x), lo = fl32(x - hi)).
+__device__ __forceinline__ double pair_load(const float *hi, const float *lo, int64_t i)
+{
+    return (double)hi[i] + (double)lo[i];
+}
+
+__device__ __forceinline__ void pair_split(double x, float &hi, float &lo)
+{
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+}
+
+}  // namespace snn

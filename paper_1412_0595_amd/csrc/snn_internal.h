@@ -29,7 +29,8 @@ struct Seg {
     int64_t base;
     int32_t inst, pop;
     int32_t n_in, n_out, n_tr, n_ltp;
-    // incoming projections: conductance array, reversal, decay per step
+    // incoming projections: id, conductance array, reversal, decay per step
+    int32_t in_proj[kMaxIn];
     int64_t in_G[kMaxIn];
     double in_erev[kMaxIn];
     double in_decay[kMaxIn];
@@ -133,9 +134,60 @@ struct LtpArgs {
     StepState *st;
 };
 
+// Reverse-time adjoint of one population's time-averaged voltage with the
+// spike raster held fixed (snn_adjoint.hip).  Loss neurons are numbered
+// compactly, instance-major: instance b owns [loss_base[b], loss_base[b+1]).
+constexpr int kAdjMaxSub = 8;       // substeps the reverse pass keeps in registers
+constexpr int kAdjMaxLoss = 1024;   // loss neurons per instance (one block each)
+
+struct AdjArgs {
+    const Seg *segs;
+    const Proj *projs;
+    int32_t n_inst;
+    const int32_t *loss_seg;     // per instance
+    const int64_t *loss_base;    // per instance + 1
+    const int32_t *loss_owner;   // per loss neuron: its instance
+    int64_t n_loss;
+    int32_t n_in_max;
+    const uint64_t *raster;      // [T][n_waves] spike bitmask of the recorded steps
+    int64_t n_waves;
+    int64_t T;
+    int64_t n_pad;               // padded neuron count (stride of the state arrays)
+    const float *ckpt_state;     // checkpoint of this segment: 8 state arrays
+    const int64_t *ckpt_G;       // and the conductance pool
+    const float *next_state;     // checkpoint of the next segment (self-check) or null
+    const int64_t *next_G;
+    uint32_t *mismatch;
+    int64_t t_a;                 // first step of the segment
+    int32_t K;                   // steps in the segment
+    const int32_t *rp_pool;
+    const int32_t *col_pool;
+    const float *w_pool;
+    const float *gscale;
+    double *tape_x;              // [K][4][n_loss]   state at the start of each step
+    double *tape_g;              // [K][n_in_max][n_loss]  delivered conductance (uS)
+    double *lam;                 // [4 + n_in_max][n_loss]  adjoint carried across segments
+    double *lg;                  // [K][n_in_max][n_loss]   adjoint of the delivered conductance
+    const double *dvbar;         // [n_loss]  dL / dVbar
+    int32_t substeps;
+    double hs;
+    const int4 *gitems;          // gather work: (instance, input slot, pre segment, bitmask word)
+    int64_t n_gitems;
+    float *dg;                   // [total synapses] dL / dg, weight-pool order
+    double *ds;                  // [n_inst] dL / dg_scale
+};
+
+hipError_t launch_adj_recompute(const AdjArgs &a, int block, hipStream_t s);
+hipError_t launch_adj_reverse(const AdjArgs &a, hipStream_t s);
+hipError_t launch_adj_gather(const AdjArgs &a, hipStream_t s);
+hipError_t launch_gather_vbar(const Seg *segs, const int32_t *loss_seg, const int64_t *loss_base,
+                              const int32_t *loss_owner, int64_t n_loss, const double *vsum, double inv_T,
+                              double *vbar, hipStream_t s);
+
 // Launchers (snn_kernels.hip).
 hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s);
 hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s);
 hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s);
+hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s);
 
 }  // namespace snn

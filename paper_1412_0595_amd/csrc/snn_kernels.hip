@@ -12,48 +12,11 @@
 //
 // Conductances are int64 multiples of 2^-40 uS, so atomics from any number
 // of wavefronts give the same bits in any order.
-#include "snn_internal.h"
+#include <algorithm>
+
+#include "snn_device.h"
 
 namespace snn {
-
-// ---------------------------------------------------------------------------
-// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with the key bumped by the Weyl constants between
-// rounds.  Only the first output word is needed for a Bernoulli draw.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t philox_first_word(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                                      uint32_t key0, uint32_t key1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t a_lo = 0xD2511F53u * x0, a_hi = __umulhi(0xD2511F53u, x0);
-        const uint32_t b_lo = 0xCD9E8D57u * x2, b_hi = __umulhi(0xCD9E8D57u, x2);
-        x0 = b_hi ^ x1 ^ key0;
-        x1 = b_lo;
-        x2 = a_hi ^ x3 ^ key1;
-        x3 = a_lo;
-        key0 += 0x9E3779B9u;
-        key1 += 0xBB67AE85u;
-    }
-    return x0;
-}
-
-// x / (e^x - 1) with its limit 1 at x = 0 (expm1 keeps it accurate near 0).
-__device__ __forceinline__ double xexpm1_ratio(double x)
-{
-    return x == 0.0 ? 1.0 : x / expm1(x);
-}
-
-// Wave-wide inclusive sum (64 lanes).
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
 
 // ---------------------------------------------------------------------------
 // Neuron update + spike compaction
@@ -84,53 +47,28 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 
         if (S.kind == kHH) {
             if (active) {
-                double v = (double)a.vh[gid] + (double)a.vl[gid];
-                double m = (double)a.mh[gid] + (double)a.ml[gid];
-                double h = (double)a.hh[gid] + (double)a.hl[gid];
-                double n = (double)a.nh[gid] + (double)a.nl[gid];
+                double v = pair_load(a.vh, a.vl, gid);
+                double m = pair_load(a.mh, a.ml, gid);
+                double h = pair_load(a.hh, a.hl, gid);
+                double n = pair_load(a.nh, a.nl, gid);
                 const double v0 = v;
                 // synaptic current from the start-of-step voltage, held
-                // fixed over the substeps
-                double iin = S.i_ext;
-                for (int q = 0; q < S.n_in; ++q) {
-                    int64_t *gp = a.G + S.in_G[q] + j;
-                    const int64_t gf = *gp;
-                    iin += (double)gf * kFixInv * (S.in_erev[q] - v0);
-                    *gp = __double2ll_rn((double)gf * S.in_decay[q]);
-                }
+                // fixed over the substeps; then the conductances decay
+                int64_t g[kMaxIn];
+#pragma unroll
+                for (int q = 0; q < kMaxIn; ++q)
+                    if (q < S.n_in) g[q] = a.G[S.in_G[q] + j];
+                const double iin = syn_current(S, g, v0);
+#pragma unroll
+                for (int q = 0; q < kMaxIn; ++q)
+                    if (q < S.n_in) a.G[S.in_G[q] + j] = fix_decay(g[q], S.in_decay[q]);
                 const double hc = a.hs * S.inv_c;
-                for (int k = 0; k < a.substeps; ++k) {
-                    const double am = 1.28 * xexpm1_ratio((-52.0 - v) * 0.25);
-                    const double bm = 1.4 * xexpm1_ratio((v + 25.0) * 0.2);
-                    const double ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
-                    const double bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
-                    const double an = 0.16 * xexpm1_ratio((-50.0 - v) * 0.2);
-                    const double bn = 0.5 * exp((-55.0 - v) * 0.025);
-                    const double n2 = n * n;
-                    const double iion = S.gna * (m * m * m * h) * (v - S.ena) + S.gk * (n2 * n2) * (v - S.ek) +
-                                        S.gl * (v - S.el);
-                    const double vn = v + hc * (iin - iion);
-                    const double mn = m + a.hs * (am * (1.0 - m) - bm * m);
-                    const double hn = h + a.hs * (ah * (1.0 - h) - bh * h);
-                    const double nn = n + a.hs * (an * (1.0 - n) - bn * n);
-                    v = vn;
-                    m = mn;
-                    h = hn;
-                    n = nn;
-                }
+                for (int k = 0; k < a.substeps; ++k) hh_substep(S, a.hs, hc, iin, v, m, h, n);
                 spike = (v0 < 0.0) && (v >= 0.0);
-                float f = (float)v;
-                a.vh[gid] = f;
-                a.vl[gid] = (float)(v - (double)f);
-                f = (float)m;
-                a.mh[gid] = f;
-                a.ml[gid] = (float)(m - (double)f);
-                f = (float)h;
-                a.hh[gid] = f;
-                a.hl[gid] = (float)(h - (double)f);
-                f = (float)n;
-                a.nh[gid] = f;
-                a.nl[gid] = (float)(n - (double)f);
+                pair_split(v, a.vh[gid], a.vl[gid]);
+                pair_split(m, a.mh[gid], a.ml[gid]);
+                pair_split(h, a.hh[gid], a.hl[gid]);
+                pair_split(n, a.nh[gid], a.nl[gid]);
                 if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[S.inst], 1);
                 if (S.record_vbar) a.vsum[gid] += v;
             }
@@ -247,16 +185,14 @@ __global__ __launch_bounds__(1024) void k_propagate(PropArgs a)
         if (!P.stdp) {
             for (int32_t k = k0 + lane; k < k1; k += kWave) {
                 const int32_t c = col[k];
-                const long long inc = __double2ll_rn(s * (double)w[k]);
-                atomicAdd((unsigned long long *)(G + c), (unsigned long long)inc);
+                atomicAdd((unsigned long long *)(G + c), (unsigned long long)fix_increment(s, w[k]));
             }
         } else {
             const float *y = a.trace + P.y_base;
             for (int32_t k = k0 + lane; k < k1; k += kWave) {
                 const int32_t c = col[k];
                 const float gv = w[k];
-                const long long inc = __double2ll_rn(s * (double)gv);
-                atomicAdd((unsigned long long *)(G + c), (unsigned long long)inc);
+                atomicAdd((unsigned long long *)(G + c), (unsigned long long)fix_increment(s, gv));
                 w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
             }
         }
@@ -290,6 +226,23 @@ __global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
             w[at] = fminf(P.g_max, w[at] + P.a_plus_gmax * x[rows[k]]);
         }
     }
+}
+
+// Flag (bit 0) any weight that is not finite or is negative.
+__global__ void k_check_weights(const float *w, int64_t n, uint32_t *flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = w[i];
+        if (!(x >= 0.0f) || !isfinite(x)) atomicOr(flag, 1u);
+    }
+}
+
+hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, n, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s)

@@ -137,6 +137,30 @@ struct snn_net {
     Item *queue, *lqueue;
     StepState *st;
 
+    // initial state block (8 state arrays), for snn_reset
+    float *d_init_state;
+
+    // adjoint recording (snn_forward_record / snn_backward)
+    bool recorded;
+    bool rec_timeline;     // the recording describes steps [0, rec_T) of the current run
+    int32_t rec_pop;
+    int64_t rec_T;
+    int32_t rec_K;
+    int64_t rec_nseg;
+    uint64_t *d_rec_raster;
+    float *d_ckpt_state;
+    int64_t *d_ckpt_G;
+    int32_t *d_loss_seg;
+    int64_t *d_loss_base;
+    int32_t *d_loss_owner;
+    int64_t n_loss;
+    int32_t n_in_max;
+    int32_t loss_block;
+    int4 *d_gitems;
+    int64_t n_gitems;
+    double *d_tape_x, *d_tape_g, *d_lg, *d_lam;
+    uint32_t *d_flag;
+
     // launch shape and graph
     snn_launch launch;
     hipGraphExec_t graph_exec;
@@ -157,6 +181,17 @@ void *dev_alloc(snn_net *net, size_t bytes)
     }
     if (p) net->allocs.push_back(p);
     return p;
+}
+
+void dev_free(snn_net *net, void *p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < net->allocs.size(); ++i)
+        if (net->allocs[i] == p) {
+            if (net->free_fn) net->free_fn(p, net->alloc_ctx); else (void)hipFree(p);
+            net->allocs.erase(net->allocs.begin() + (long)i);
+            return;
+        }
 }
 
 void release(snn_net *net)
@@ -564,6 +599,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
             P.G_base = G_total;
             G_total += post.n;
             const double decay = std::exp(-net->dt / (double)Q.tau_ms);
+            post.in_proj[post.n_in] = gi;
             post.in_G[post.n_in] = P.G_base;
             post.in_erev[post.n_in] = Q.e_rev_mV;
             post.in_decay[post.n_in] = decay;
@@ -773,6 +809,13 @@ int snn_create(const snn_config *cfg, snn_net **out)
             if ((rc = up(*st_ptrs[2 * k + 1], lo[k].data(), 4 * (size_t)N))) return bail(rc);
         }
     }
+    net->d_init_state = (float *)dev_alloc(net, 4 * 8 * (size_t)N);
+    net->d_flag = (uint32_t *)dev_alloc(net, 256);
+    if (!net->d_init_state || !net->d_flag) return bail(fail(SNN_ENOMEM, "device allocation failed"));
+    if (hipMemcpy(net->d_init_state, net->vh, 4 * 8 * (size_t)N, hipMemcpyDeviceToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(SNN_EDEVICE, "state copy failed"));
+    }
     if (hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail(SNN_EDEVICE, "device synchronisation failed"));
@@ -839,9 +882,15 @@ int snn_get_raster(snn_net *net, int32_t inst, int32_t pop, int64_t t0, int64_t 
     if (rc) return rc;
     const int s = seg_index(net, inst, pop, false);
     if (s < 0) return s;
-    if (net->raster_steps <= 0) return fail(SNN_ESTATE, "net was created without a raster");
-    if (t0 < 0 || t1 < t0 || t1 > net->t || t0 < net->t - net->raster_steps)
+    // the ring of the last raster_steps steps, else the recording of the
+    // last snn_forward_record
+    const bool rec = net->rec_timeline && t0 >= 0 && t0 <= t1 && t1 <= net->rec_T;
+    const bool ring = !rec && net->raster_steps > 0 && t0 >= 0 && t0 <= t1 && t1 <= net->t &&
+                      t0 >= net->t - net->raster_steps;
+    if (!ring && !rec)
         return fail(SNN_ERANGE, "steps [%lld, %lld) are not in the raster window", (long long)t0, (long long)t1);
+    const uint64_t *src = ring ? net->raster : net->d_rec_raster;
+    const int64_t slots = ring ? net->raster_steps : net->rec_T;
     if (!offsets || (cap > 0 && !ids)) return fail(SNN_EINVAL, "NULL output");
     const Seg &S = net->segs[s];
     const int64_t w0 = S.base / kWave, nw = align_up(S.n, kWave) / kWave;
@@ -849,7 +898,7 @@ int snn_get_raster(snn_net *net, int32_t inst, int32_t pop, int64_t t0, int64_t 
     int64_t n = 0;
     offsets[0] = 0;
     for (int64_t t = t0; t < t1; ++t) {
-        if ((rc = d2h(net, words.data(), net->raster + (t % net->raster_steps) * net->n_waves + w0, 8 * (size_t)nw))) return rc;
+        if ((rc = d2h(net, words.data(), src + (t % slots) * net->n_waves + w0, 8 * (size_t)nw))) return rc;
         for (int64_t w = 0; w < nw; ++w)
             for (uint64_t b = words[w]; b; b &= b - 1) {
                 const int32_t id = (int32_t)(w * kWave + __builtin_ctzll(b));
@@ -1161,6 +1210,209 @@ int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_pe
     }, &ms);
     if (rc) return rc;
     *ms_per_launch = ms / (double)launches;
+    return SNN_OK;
+}
+
+int snn_reset(snn_net *net)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    net->rec_timeline = false;
+    HIP_OK(hipMemsetAsync(net->d_arena, 0, (size_t)net->arena_bytes, net->stream));
+    HIP_OK(hipMemcpyAsync(net->vh, net->d_init_state, 4 * 8 * (size_t)net->n_neurons_padded, hipMemcpyDeviceToDevice,
+                          net->stream));
+    net->t = 0;
+    return SNN_OK;
+}
+
+int64_t snn_weight_count(const snn_net *net) { return net ? net->w_count : -1; }
+
+int snn_weight_offset(const snn_net *net, int32_t inst, int32_t proj, int64_t *offset)
+{
+    if (!net || !offset) return fail(SNN_EINVAL, "NULL argument");
+    const int q = proj_index(net, inst, proj);
+    if (q < 0) return q;
+    *offset = net->hprojs[q].syn_base;
+    return SNN_OK;
+}
+
+int snn_get_weights_device(snn_net *net, float *dst)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!dst) return fail(SNN_EINVAL, "dst is NULL");
+    HIP_OK(hipMemcpyAsync(dst, net->d_w, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream));
+    return SNN_OK;
+}
+
+int snn_set_weights_device(snn_net *net, const float *src)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!src) return fail(SNN_EINVAL, "src is NULL");
+    uint32_t flag = 0;
+    HIP_OK(hipMemsetAsync(net->d_flag, 0, 4, net->stream));
+    HIP_OK(launch_check_weights(src, net->w_count, net->d_flag, net->stream));
+    HIP_OK(hipMemcpyAsync(&flag, net->d_flag, 4, hipMemcpyDeviceToHost, net->stream));
+    HIP_OK(hipStreamSynchronize(net->stream));
+    if (flag) return fail(SNN_EINVAL, "weights must be finite and >= 0");
+    HIP_OK(hipMemcpyAsync(net->d_w, src, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream));
+    return SNN_OK;
+}
+
+int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_every, double *vbar)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (n_steps < 1 || ckpt_every < 1) return fail(SNN_EINVAL, "need n_steps >= 1 and ckpt_every >= 1");
+    if (!vbar) return fail(SNN_EINVAL, "vbar is NULL");
+    if (net->plastic) return fail(SNN_ESTATE, "the adjoint needs fixed weights (no STDP projection)");
+    if (net->substeps > kAdjMaxSub) return fail(SNN_EINVAL, "the adjoint supports at most %d substeps", kAdjMaxSub);
+    std::vector<int32_t> lseg(net->n_inst);
+    std::vector<int64_t> lbase(net->n_inst + 1, 0);
+    int n_in_max = 1, max_n = 1;
+    for (int b = 0; b < net->n_inst; ++b) {
+        if (pop < 0 || pop >= (int32_t)net->seg_of[b].size()) return fail(SNN_EINVAL, "instance %d has no population %d", b, pop);
+        const Seg &S = net->segs[net->seg_of[b][pop]];
+        if (S.kind != kHH) return fail(SNN_EINVAL, "population %d of instance %d is not Traub-Miles", pop, b);
+        if (!S.record_vbar) return fail(SNN_ESTATE, "population %d of instance %d was created without record_vbar", pop, b);
+        if (S.n > kAdjMaxLoss) return fail(SNN_EINVAL, "the adjoint supports at most %d neurons per instance", kAdjMaxLoss);
+        lseg[b] = net->seg_of[b][pop];
+        lbase[b + 1] = lbase[b] + S.n;
+        n_in_max = std::max(n_in_max, S.n_in);
+        max_n = std::max(max_n, S.n);
+    }
+    const int64_t T = n_steps, K = std::min<int64_t>(ckpt_every, T);
+    const int64_t nseg = (T + K - 1) / K;
+    const int64_t N = net->n_neurons_padded, W = net->n_waves;
+    const int64_t n_loss = lbase[net->n_inst];
+    std::vector<int32_t> owner(std::max<int64_t>(n_loss, 1), 0);
+    for (int b = 0; b < net->n_inst; ++b)
+        for (int64_t c = lbase[b]; c < lbase[b + 1]; ++c) owner[c] = b;
+    std::vector<int4> items;
+    for (int b = 0; b < net->n_inst; ++b) {
+        const Seg &S = net->segs[lseg[b]];
+        for (int q = 0; q < S.n_in; ++q) {
+            const Proj &P = net->projs[S.in_proj[q]];
+            const int nw = (int)(align_up(net->segs[P.pre_seg].n, kWave) / kWave);
+            for (int w = 0; w < nw; ++w) items.push_back(make_int4(b, q, P.pre_seg, w));
+        }
+    }
+    // (re)allocate the recording
+    void *old[] = {net->d_rec_raster, net->d_ckpt_state, net->d_ckpt_G, net->d_loss_seg, net->d_loss_base,
+                   net->d_loss_owner, net->d_gitems, net->d_tape_x, net->d_tape_g, net->d_lg, net->d_lam};
+    for (void *p : old) dev_free(net, p);
+    net->recorded = false;
+    net->d_rec_raster = (uint64_t *)dev_alloc(net, 8 * (size_t)(T * W));
+    net->d_ckpt_state = (float *)dev_alloc(net, 4 * (size_t)(nseg * 8 * N));
+    net->d_ckpt_G = (int64_t *)dev_alloc(net, 8 * (size_t)(nseg * std::max<int64_t>(net->G_count, 1)));
+    net->d_loss_seg = (int32_t *)dev_alloc(net, 4 * (size_t)net->n_inst);
+    net->d_loss_base = (int64_t *)dev_alloc(net, 8 * (size_t)(net->n_inst + 1));
+    net->d_loss_owner = (int32_t *)dev_alloc(net, 4 * owner.size());
+    net->d_gitems = (int4 *)dev_alloc(net, sizeof(int4) * std::max<size_t>(items.size(), 1));
+    net->d_tape_x = (double *)dev_alloc(net, 8 * (size_t)(K * 4 * std::max<int64_t>(n_loss, 1)));
+    net->d_tape_g = (double *)dev_alloc(net, 8 * (size_t)(K * n_in_max * std::max<int64_t>(n_loss, 1)));
+    net->d_lg = (double *)dev_alloc(net, 8 * (size_t)(K * n_in_max * std::max<int64_t>(n_loss, 1)));
+    net->d_lam = (double *)dev_alloc(net, 8 * (size_t)((4 + n_in_max) * std::max<int64_t>(n_loss, 1)));
+    if (!net->d_rec_raster || !net->d_ckpt_state || !net->d_ckpt_G || !net->d_loss_seg || !net->d_loss_base ||
+        !net->d_loss_owner || !net->d_gitems || !net->d_tape_x || !net->d_tape_g || !net->d_lg || !net->d_lam)
+        return fail(SNN_ENOMEM, "allocation of the adjoint recording failed");
+    if ((rc = h2d(net, net->d_loss_seg, lseg.data(), 4 * lseg.size()))) return rc;
+    if ((rc = h2d(net, net->d_loss_base, lbase.data(), 8 * lbase.size()))) return rc;
+    if ((rc = h2d(net, net->d_loss_owner, owner.data(), 4 * owner.size()))) return rc;
+    if ((rc = h2d(net, net->d_gitems, items.data(), sizeof(int4) * items.size()))) return rc;
+    net->n_loss = n_loss;
+    net->n_in_max = n_in_max;
+    net->loss_block = (int)align_up(max_n, kWave);
+    net->n_gitems = (int64_t)items.size();
+    net->rec_pop = pop;
+    net->rec_T = T;
+    net->rec_K = (int32_t)K;
+    net->rec_nseg = nseg;
+
+    // forward from the initial state, recording the raster and checkpoints
+    if ((rc = snn_reset(net))) return rc;
+    NeuronArgs na = neuron_args(net);
+    na.raster = net->d_rec_raster;
+    na.raster_steps = (int32_t)T;
+    const PropArgs pa = prop_args(net);
+    for (int64_t t = 0; t < T; ++t) {
+        if (t % K == 0) {
+            const int64_t sgi = t / K;
+            HIP_OK(hipMemcpyAsync(net->d_ckpt_state + sgi * 8 * N, net->vh, 4 * 8 * (size_t)N, hipMemcpyDeviceToDevice,
+                                  net->stream));
+            HIP_OK(hipMemcpyAsync(net->d_ckpt_G + sgi * std::max<int64_t>(net->G_count, 1), net->G,
+                                  8 * (size_t)net->G_count, hipMemcpyDeviceToDevice, net->stream));
+        }
+        HIP_OK(launch_propagate(pa, net->launch.prop_blocks, net->launch.prop_block, net->stream));
+        HIP_OK(launch_neuron(na, net->launch.neuron_block, net->stream));
+        net->t += 1;
+    }
+    HIP_OK(launch_gather_vbar(net->d_segs, net->d_loss_seg, net->d_loss_base, net->d_loss_owner, n_loss, net->vsum,
+                              1.0 / (double)T, vbar, net->stream));
+    net->recorded = true;
+    net->rec_timeline = true;
+    return SNN_OK;
+}
+
+int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_dgscale, int64_t *mismatch)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!net->recorded) return fail(SNN_ESTATE, "call snn_forward_record first");
+    if (!dL_dvbar || !dL_dg || !dL_dgscale) return fail(SNN_EINVAL, "NULL argument");
+    const int64_t N = net->n_neurons_padded;
+    const int64_t gstride = std::max<int64_t>(net->G_count, 1);
+    HIP_OK(hipMemsetAsync(net->d_lam, 0, 8 * (size_t)((4 + net->n_in_max) * std::max<int64_t>(net->n_loss, 1)), net->stream));
+    HIP_OK(hipMemsetAsync(dL_dg, 0, 4 * (size_t)net->w_count, net->stream));
+    HIP_OK(hipMemsetAsync(dL_dgscale, 0, 8 * (size_t)net->n_inst, net->stream));
+    HIP_OK(hipMemsetAsync(net->d_flag, 0, 4, net->stream));
+    AdjArgs a{};
+    a.segs = net->d_segs;
+    a.projs = net->d_projs;
+    a.n_inst = net->n_inst;
+    a.loss_seg = net->d_loss_seg;
+    a.loss_base = net->d_loss_base;
+    a.loss_owner = net->d_loss_owner;
+    a.n_loss = net->n_loss;
+    a.n_in_max = net->n_in_max;
+    a.raster = net->d_rec_raster;
+    a.n_waves = net->n_waves;
+    a.T = net->rec_T;
+    a.n_pad = N;
+    a.mismatch = net->d_flag;
+    a.rp_pool = net->d_rp;
+    a.col_pool = net->d_col;
+    a.w_pool = net->d_w;
+    a.gscale = net->d_gscale;
+    a.tape_x = net->d_tape_x;
+    a.tape_g = net->d_tape_g;
+    a.lam = net->d_lam;
+    a.lg = net->d_lg;
+    a.dvbar = dL_dvbar;
+    a.substeps = net->substeps;
+    a.hs = net->dt / net->substeps;
+    a.gitems = net->d_gitems;
+    a.n_gitems = net->n_gitems;
+    a.dg = dL_dg;
+    a.ds = dL_dgscale;
+    for (int64_t sg = net->rec_nseg - 1; sg >= 0; --sg) {
+        a.t_a = sg * net->rec_K;
+        a.K = (int32_t)std::min<int64_t>(net->rec_K, net->rec_T - a.t_a);
+        a.ckpt_state = net->d_ckpt_state + sg * 8 * N;
+        a.ckpt_G = net->d_ckpt_G + sg * gstride;
+        a.next_state = sg + 1 < net->rec_nseg ? net->d_ckpt_state + (sg + 1) * 8 * N : nullptr;
+        a.next_G = sg + 1 < net->rec_nseg ? net->d_ckpt_G + (sg + 1) * gstride : nullptr;
+        HIP_OK(launch_adj_recompute(a, net->loss_block, net->stream));
+        HIP_OK(launch_adj_reverse(a, net->stream));
+        HIP_OK(launch_adj_gather(a, net->stream));
+    }
+    if (mismatch) {
+        uint32_t m = 0;
+        HIP_OK(hipMemcpyAsync(&m, net->d_flag, 4, hipMemcpyDeviceToHost, net->stream));
+        HIP_OK(hipStreamSynchronize(net->stream));
+        *mismatch = m;
+    }
     return SNN_OK;
 }
 

@@ -26,7 +26,8 @@ EXPORTS = [
     "snn_set_state_f64", "snn_get_conductance", "snn_set_conductance", "snn_get_last_spikes",
     "snn_set_last_spikes", "snn_get_vbar", "snn_get_nan_counts", "snn_set_gscale", "snn_get_weights",
     "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel",
-    "snn_last_error",
+    "snn_last_error", "snn_reset", "snn_weight_count", "snn_weight_offset", "snn_get_weights_device",
+    "snn_set_weights_device", "snn_forward_record", "snn_backward",
 ]
 
 
@@ -108,6 +109,13 @@ def load():
         "snn_time_steps": (C.c_int, [vp, i64, vp]),
         "snn_time_kernel": (C.c_int, [vp, i32, i64, vp]),
         "snn_last_error": (C.c_char_p, []),
+        "snn_reset": (C.c_int, [vp]),
+        "snn_weight_count": (i64, [vp]),
+        "snn_weight_offset": (C.c_int, [vp, i32, i32, vp]),
+        "snn_get_weights_device": (C.c_int, [vp, vp]),
+        "snn_set_weights_device": (C.c_int, [vp, vp]),
+        "snn_forward_record": (C.c_int, [vp, i32, i64, i32, vp]),
+        "snn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -265,6 +273,53 @@ class Network:
         out = C.c_double()
         _check(load().snn_time_kernel(self.h, int(which), int(launches), C.byref(out)))
         return out.value
+
+    def reset(self):
+        _check(load().snn_reset(self.h))
+
+    # ------------------------------------------------------ weights / adjoint
+    @property
+    def weight_count(self):
+        return int(load().snn_weight_count(self.h))
+
+    def weight_offset(self, inst, proj):
+        out = C.c_int64()
+        _check(load().snn_weight_offset(self.h, int(inst), int(proj), C.byref(out)))
+        return out.value
+
+    def get_weights_device(self, out):
+        """Copy the weight pool into a float32 CUDA tensor."""
+        assert out.dtype == self._torch.float32 and out.is_cuda and out.numel() == self.weight_count
+        _check(load().snn_get_weights_device(self.h, C.c_void_p(out.data_ptr())))
+
+    def set_weights_device(self, src):
+        src = src.contiguous()
+        assert src.dtype == self._torch.float32 and src.is_cuda and src.numel() == self.weight_count
+        _check(load().snn_set_weights_device(self.h, C.c_void_p(src.data_ptr())))
+
+    def loss_size(self, pop):
+        return sum(int(inst["pops"][pop]["n"]) for inst in self.spec["instances"])
+
+    def forward_record(self, pop, n_steps, ckpt_every, vbar=None):
+        """Reset, run n_steps recording raster and checkpoints; returns Vbar of
+        population pop (float64 CUDA tensor, instance-major)."""
+        t = self._torch
+        if vbar is None:
+            vbar = t.empty(self.loss_size(pop), dtype=t.float64, device=self.device)
+        _check(load().snn_forward_record(self.h, int(pop), int(n_steps), int(ckpt_every), C.c_void_p(vbar.data_ptr())))
+        return vbar
+
+    def backward(self, dvbar, check=False):
+        """Returns (dL/dg float32 [weight_count], dL/dg_scale float64 [n_inst],
+        recompute mismatches or None)."""
+        t = self._torch
+        dvbar = dvbar.contiguous().to(t.float64)
+        dg = t.empty(self.weight_count, dtype=t.float32, device=self.device)
+        ds = t.empty(self.n_instances, dtype=t.float64, device=self.device)
+        mm = C.c_int64(-1)
+        _check(load().snn_backward(self.h, C.c_void_p(dvbar.data_ptr()), C.c_void_p(dg.data_ptr()),
+                                   C.c_void_p(ds.data_ptr()), C.byref(mm) if check else None))
+        return dg, ds, (mm.value if check else None)
 
     # ----------------------------------------------------------------- state
     def _n(self, inst, pop):

@@ -1,0 +1,171 @@
+"""GPU adjoint (through the C ABI) against the FP64 oracle adjoint run on the
+GPU's own raster, finite differences of the GPU forward, and the per-instance
+run."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1412_0595_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0595_amd import snn as S
+    S.load()
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _spec(n_inst, scale, seed_shift=0):
+    spec = netgen.make_config(5, n_instances=n_inst, scale=scale)
+    return spec
+
+
+def _loss_grad(vbar, spec):
+    """L = sum_b mean_j (Vbar_bj - y_bj)^2 and dL/dVbar."""
+    y = np.concatenate(spec["target"])
+    sizes = [inst["pops"][2]["n"] for inst in spec["instances"]]
+    w = np.concatenate([np.full(n, 1.0 / n) for n in sizes])
+    L = float(np.sum(w * (vbar - y) ** 2))
+    return L, 2 * w * (vbar - y)
+
+
+def _oracle_raster(net, spec, b, T):
+    """Replay arrays (all populations) from the GPU's recorded raster."""
+    n_pops = len(spec["instances"][b]["pops"])
+    t_l, p_l, i_l = [], [], []
+    for p in range(n_pops):
+        ras = net.raster(b, p, 0, T)
+        for t, ids in enumerate(ras):
+            t_l.append(np.full(ids.size, t, np.int32))
+            p_l.append(np.full(ids.size, p, np.int32))
+            i_l.append(ids.astype(np.int32))
+    ev = (np.concatenate(t_l), np.concatenate(p_l), np.concatenate(i_l))
+    return O.raster_arrays(ev, n_pops, T)
+
+
+def test_adjoint_matches_fp64_oracle(snn):
+    import torch
+    say("case: adjoint, 3 instances of the adjoint workload at scale 0.2, T=400, K=50")
+    spec = _spec(3, 0.2)
+    T, K = 400, 50
+    net = snn.Network(spec, record_vbar=("C",))
+    vbar = net.forward_record(2, T, K)
+    vb = vbar.cpu().numpy()
+    L, dv = _loss_grad(vb, spec)
+    dg, ds, mism = net.backward(torch.tensor(dv, device=net.device), check=True)
+    say(f"  recomputed segments differing from checkpoints: {mism} values")
+    assert mism == 0
+    dg = dg.cpu().numpy().astype(np.float64)
+    ds = ds.cpu().numpy()
+    off = 0
+    for b, inst in enumerate(spec["instances"]):
+        n_c = inst["pops"][2]["n"]
+        ro, ri = _oracle_raster(net, spec, b, T)
+        orc = O.OracleNet(inst)
+        for p in (1, 2):
+            orc.set_replay(p, ro, ri, T)
+        vb_o, grads, ds_o = orc.adjoint(T, 2, dv[off:off + n_c])
+        dvb = np.max(np.abs(vb_o - vb[off:off + n_c]))
+        rel_s = abs(ds[b] - ds_o) / abs(ds_o)
+        say(f"  instance {b}: max |Vbar gpu - oracle| {dvb:.2e} mV, dL/ds gpu {ds[b]:.6e} oracle {ds_o:.6e} "
+            f"rel {rel_s:.2e}")
+        assert dvb < 1e-3
+        assert rel_s <= 1e-3
+        for q in range(3):
+            o = net.weight_offset(b, q)
+            nnz = inst["projs"][q]["col_idx"].size
+            gq = dg[o:o + nnz]
+            if q == 0:
+                assert np.all(gq == 0.0) and np.all(grads[0] == 0.0)
+                continue
+            rel = np.linalg.norm(gq - grads[q]) / np.linalg.norm(grads[q])
+            say(f"    projection {q}: |dg gpu - oracle| / |dg oracle| = {rel:.2e}")
+            assert rel <= 1e-3
+        off += n_c
+    net.close()
+
+
+def test_autograd_function_against_finite_differences(snn):
+    """loss.backward() through SNNAdjoint gives dL/dg_scale equal to a central
+    difference of the GPU forward itself at a step that leaves the raster
+    unchanged."""
+    import torch
+    from paper_1412_0595_amd.adjoint import vbar as vbar_fn
+    say("case: autograd dL/dg_scale vs finite differences")
+    spec = _spec(2, 0.2)
+    T, K = 300, 64
+    y = torch.tensor(np.concatenate(spec["target"]), device="cuda")
+    sizes = [inst["pops"][2]["n"] for inst in spec["instances"]]
+    wts = torch.tensor(np.concatenate([np.full(n, 1.0 / n) for n in sizes]), device="cuda")
+    net = snn.Network(spec, record_vbar=("C",), raster_steps=T)
+    w0 = torch.empty(net.weight_count, dtype=torch.float32, device="cuda")
+    net.get_weights_device(w0)
+    gs = torch.tensor([1.0, 1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+    w = w0.clone().requires_grad_(True)
+    out = vbar_fn(net, w, gs, 2, T, K)
+    loss = torch.sum(wts * (out - y) ** 2)
+    loss.backward()
+    g_auto = gs.grad.cpu().numpy()
+
+    def run(s0, s1):
+        with torch.no_grad():
+            o = vbar_fn(net, w0, torch.tensor([s0, s1], dtype=torch.float64, device="cuda"), 2, T, K)
+            L = float(torch.sum(wts * (o - y) ** 2))
+        ras = [net.raster(b, p, 0, T) for b in range(2) for p in (1, 2)]
+        return L, ras
+
+    eps = 2.0 ** -18       # exact in fp32 around 1.0
+    for b in range(2):
+        sp = [1.0, 1.0]
+        sm = [1.0, 1.0]
+        sp[b] += eps
+        sm[b] -= eps
+        (Lp, rp), (Lm, rm) = run(*sp), run(*sm)
+        same = all(np.array_equal(x, z) for a, c in zip(rp, rm) for x, z in zip(a, c))
+        fd = (Lp - Lm) / (2 * eps)
+        say(f"  instance {b}: autograd {g_auto[b]:.6e}, central difference {fd:.6e}, raster unchanged {same}")
+        assert same
+        assert abs(g_auto[b] - fd) <= 1e-3 * abs(fd)
+    # dL/dw of the input projection is exactly zero
+    o0 = net.weight_offset(0, 0)
+    n0 = spec["instances"][0]["projs"][0]["col_idx"].size
+    assert torch.all(w.grad[o0:o0 + n0] == 0)
+    net.close()
+
+
+def test_instance_in_batch_has_the_gradient_it_has_alone(snn):
+    import torch
+    say("case: batched adjoint vs per-instance adjoint")
+    spec = _spec(3, 0.15)
+    T, K = 240, 40
+    net = snn.Network(spec, record_vbar=("C",))
+    vb = net.forward_record(2, T, K).cpu().numpy()
+    L, dv = _loss_grad(vb, spec)
+    dg, ds, _ = net.backward(torch.tensor(dv, device=net.device))
+    dg, ds = dg.cpu().numpy(), ds.cpu().numpy()
+    off = 0
+    for b, inst in enumerate(spec["instances"]):
+        n_c = inst["pops"][2]["n"]
+        one = dict(dt=spec["dt"], substeps=spec["substeps"], instances=[inst])
+        alone = snn.Network(one, record_vbar=("C",))
+        vb1 = alone.forward_record(2, T, K).cpu().numpy()
+        assert np.array_equal(vb1, vb[off:off + n_c])
+        dg1, ds1, _ = alone.backward(torch.tensor(dv[off:off + n_c], device=net.device))
+        dg1 = dg1.cpu().numpy()
+        o = net.weight_offset(b, 0)
+        assert np.array_equal(dg[o:o + dg1.size], dg1)
+        assert abs(ds[b] - float(ds1.cpu().numpy()[0])) <= 1e-12 * abs(ds[b])
+        alone.close()
+        off += n_c
+    net.close()
