@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=500)
+    ap.add_argument("--sweep", action="store_true",
+                    help="forced-activity sweep of the propagation kernel instead of the step benchmark")
+    ap.add_argument("--sweep-workload", type=int, default=3)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB of a plain device copy to run first (counter calibration)")
     return ap.parse_args()
 
 
@@ -71,8 +76,58 @@ def spike_totals(net, spec):
             for b, inst in enumerate(spec["instances"])]
 
 
+def sweep(args):
+    """Propagation kernel alone on a workload's connectivity with seeded
+    synthetic spike sets: every input (A) row and a fraction of the hidden (B)
+    rows spiking; one hipEvent pair around back-to-back launches."""
+    import numpy as np
+    from paper_1412_0595_amd import netgen, snn
+    spec = netgen.make_config(args.sweep_workload, n_instances=args.instances)
+    for inst in spec["instances"]:
+        for q in inst["projs"]:
+            q["stdp"] = None      # pure delivery: no depression writes
+    net = snn.Network(spec, autotune=False)
+    rng = np.random.default_rng(7)
+    deg = out_degree_table(spec)
+    for frac in (0.001, 0.01, 0.1, 1.0):
+        ev = rows = 0
+        for b, inst in enumerate(spec["instances"]):
+            n_a, n_b = inst["pops"][0]["n"], inst["pops"][1]["n"]
+            fa = np.ones(n_a, np.uint8)
+            fb = np.zeros(n_b, np.uint8)
+            fb[netgen.forced_spikes(rng, n_b, frac)] = 1
+            net.set_last_spikes(b, 0, fa)
+            net.set_last_spikes(b, 1, fb)
+            net.set_last_spikes(b, 2, np.zeros(inst["pops"][2]["n"], np.uint8))
+            ev += int(deg[b][0].sum() + deg[b][1][fb.astype(bool)].sum())
+            rows += n_a + int(fb.sum())
+        for L in (dict(prop_blocks=1024, prop_block=256), dict(prop_blocks=2048, prop_block=256),
+                  dict(prop_blocks=4096, prop_block=256)):
+            net.set_launch(**L)
+            launches = 20 if ev > 1e7 else 200
+            ms = net.time_kernel(0, launches)
+            byt = PROP_BYTES_PER_EVENT * ev + PROP_BYTES_PER_ROW * rows
+            gbs = byt / (ms * 1e-3) / 1e9
+            print(json.dumps({"sweep": "propagation", "workload": args.sweep_workload, "hidden_fraction": frac,
+                              "events_per_launch": ev, "rows": rows, "ms_per_launch": ms, "launch": net.launch,
+                              "events_per_s": ev / (ms * 1e-3), "achieved_GBs": gbs,
+                              "frac_of_hbm": gbs / HBM_PEAK_GBS}), flush=True)
+    net.close()
+
+
 def main():
     args = parse()
+    if args.calib_copy:
+        import torch
+        a = torch.ones(args.calib_copy * (1 << 18), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.sweep:
+        sweep(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note",
                           "n_gpus": args.gpus}))
