@@ -80,6 +80,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime; loading it first makes libsnn.so bind
+    # to that same runtime (one HSA runtime per process) instead of pulling
+    # in a second copy from /opt/rocm
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
