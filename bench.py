@@ -35,8 +35,92 @@ PROP_BYTES_PER_ROW = 16
 NEURON_STATE_BYTES = 64
 NEURON_G_BYTES = 16
 
-WORKLOADS = {2: "A=1000 Poisson @20 Hz, B=20000 HH, C=1000 HH; A->B p=0.2, B->C p=0.5, C->C all-to-all "
-                "inhibitory; dt=0.1 ms, 3 Euler substeps"}
+WORKLOADS = {
+    1: "A=100 Poisson @20 Hz, B=1000 HH, C=100 HH; A->B p=0.5, B->C and C->C all-to-all; dt=0.1 ms, 3 Euler substeps",
+    2: "A=1000 Poisson @20 Hz, B=20000 HH, C=1000 HH; A->B p=0.2, B->C p=0.5, C->C all-to-all "
+       "inhibitory; dt=0.1 ms, 3 Euler substeps",
+    3: "A=2000 Poisson @30 Hz, B=100000 HH, C=1000 HH; A->B p=0.2, B->C p=0.5 with pair STDP, C->C all-to-all; "
+       "dt=0.1 ms, 3 Euler substeps",
+    4: "256 instances, A~LU[200,1000], B~LU[2000,20000], C~LU[100,1000], g_scale~LU[0.1,10], p=0.2/0.5; "
+       "dt=0.1 ms, 3 Euler substeps",
+    5: "64 x (A=500, B=5000, C=200), p=0.2/0.5; loss = MSE of time-averaged C voltage to a seeded target; "
+       "dt=0.1 ms, 3 Euler substeps",
+}
+
+
+def sub_spec(spec, k):
+    return dict(dt=spec["dt"], substeps=spec["substeps"], instances=[spec["instances"][k]])
+
+
+def time_loop(spec, steps, warmup):
+    """Every instance alone on the same kernels, one after the other; step
+    time only (hipEvents around each instance's steps)."""
+    import torch
+    from paper_1412_0595_amd import snn
+    total_ms = 0.0
+    for k in range(len(spec["instances"])):
+        net = snn.Network(sub_spec(spec, k))
+        net.step(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s = torch.cuda.current_stream()
+        e0.record(s)
+        net.step(steps)
+        e1.record(s)
+        e1.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        net.close()
+    return total_ms
+
+
+def adjoint_bench(args):
+    """Recorded forward + reverse pass of workload 5 (gradient of the MSE of
+    the time-averaged output voltage w.r.t. every weight and g_scale),
+    batched, and the same per instance in a loop."""
+    import numpy as np
+    import torch
+    from paper_1412_0595_amd import netgen, snn
+    spec = netgen.make_config(args.workload, n_instances=args.instances)
+    T, K = args.steps, args.ckpt_every
+    y = torch.tensor(np.concatenate(spec["target"]), device="cuda")
+    sizes = [inst["pops"][2]["n"] for inst in spec["instances"]]
+    w = torch.tensor(np.concatenate([np.full(n, 1.0 / n) for n in sizes]), device="cuda")
+
+    def run(sp, yy, ww, reps=2):
+        net = snn.Network(sp, record_vbar=("C",))
+        best = None
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            s = torch.cuda.current_stream()
+            e[0].record(s)
+            vb = net.forward_record(2, T, K)
+            e[1].record(s)
+            dv = 2 * ww * (vb - yy)
+            dg, ds, _ = net.backward(dv)
+            e[2].record(s)
+            e[2].synchronize()
+            f, b = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+            if best is None or f + b < best[0] + best[1]:
+                best = (f, b)
+        n_hh = sum(p["n"] for inst in sp["instances"] for p in inst["pops"] if p["kind"] == "hh")
+        net.close()
+        return best, n_hh
+
+    (fb, bb), n_hh = run(spec, y, w)
+    loop_f = loop_b = 0.0
+    off = 0
+    for k, n in enumerate(sizes):
+        (f, b), _ = run(sub_spec(spec, k), y[off:off + n], w[off:off + n], reps=1)
+        loop_f += f
+        loop_b += b
+        off += n
+    rec = {"metric": "adjoint (recorded forward + reverse) time, batched vs plain per-instance loop",
+           "value": (loop_f + loop_b) / (fb + bb), "unit": "x speedup", "higher_is_better": True,
+           "n_gpus": 1, "steps": T, "ckpt_every": K, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WORKLOADS.get(args.workload), "instances": len(sizes), "hh_neurons": n_hh},
+           "batched_ms": {"forward_record": fb, "backward": bb},
+           "loop_ms": {"forward_record": loop_f, "backward": loop_b},
+           "neuron_steps_per_s_forward": n_hh * T / (fb * 1e-3)}
+    print(json.dumps(rec))
 
 
 def parse():
@@ -53,6 +137,11 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="forced-activity sweep of the propagation kernel instead of the step benchmark")
     ap.add_argument("--sweep-workload", type=int, default=3)
+    ap.add_argument("--loop", action="store_true",
+                    help="batched workloads: also time every instance alone on the same kernels (per-instance loop)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the recorded forward + reverse pass (gradient) instead of plain steps")
+    ap.add_argument("--ckpt-every", type=int, default=100)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration)")
     return ap.parse_args()
@@ -128,6 +217,9 @@ def main():
     if args.sweep:
         sweep(args)
         return
+    if args.adjoint:
+        adjoint_bench(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note",
                           "n_gpus": args.gpus}))
@@ -140,7 +232,9 @@ def main():
     n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
     n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
     cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    t_make = time.perf_counter()
     net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=cache)
+    t_make = time.perf_counter() - t_make
     stream = torch.cuda.current_stream()
 
     net.step(args.warmup)
@@ -232,11 +326,16 @@ def main():
         "synaptic_events_per_s": events_s,
         "spikes": spikes,
         "wall_s": t_wall,
+        "create_s": t_make,
         "launch": net.launch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     net.close()
+    if args.loop and len(spec["instances"]) > 1:
+        loop_ms = time_loop(spec, args.steps, args.warmup)
+        rec["per_instance_loop"] = {"ms": loop_ms, "neuron_steps_per_s": n_hh * args.steps / (loop_ms * 1e-3),
+                                    "batched_speedup": loop_ms / ms}
     print(json.dumps(rec))
 
 
