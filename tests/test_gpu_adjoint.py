@@ -99,7 +99,11 @@ def test_adjoint_matches_fp64_oracle(snn):
 def test_autograd_function_against_finite_differences(snn):
     """loss.backward() through SNNAdjoint gives dL/dg_scale equal to a central
     difference of the GPU forward itself at a step that leaves the raster
-    unchanged."""
+    unchanged.  The difference quotient is only good to about 1e-3 here: a
+    step of ~1e-6 in g_scale moves each delivered increment by ~100 units of
+    the 2^-40 uS conductance grid, so the rounding of every increment
+    perturbs it at that level; 1e-2 is asserted (the 1e-3 gradient check is
+    the comparison with the FP64 oracle adjoint above)."""
     import torch
     from paper_1412_0595_amd.adjoint import vbar as vbar_fn
     say("case: autograd dL/dg_scale vs finite differences")
@@ -140,7 +144,7 @@ def test_autograd_function_against_finite_differences(snn):
         say(f"  instance {b}: autograd {g_auto[b]:.6e}, central difference {fd:.6e} (eps {eps:.2e}), "
             f"raster unchanged {same}")
         assert same
-        assert abs(g_auto[b] - fd) <= 1e-3 * abs(fd)
+        assert abs(g_auto[b] - fd) <= 1e-2 * abs(fd)
     # dL/dw of the input projection is exactly zero
     o0 = net.weight_offset(0, 0)
     n0 = spec["instances"][0]["projs"][0]["col_idx"].size
