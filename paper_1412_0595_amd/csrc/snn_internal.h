@@ -13,6 +13,8 @@ constexpr int kMaxOut = 8;   // outgoing projections of one population
 constexpr int kMaxTr = 4;    // STDP traces kept by one population
 constexpr int kMaxLtp = 2;   // plastic projections arriving at one population
 constexpr int kMinChunk = 64;
+constexpr int kTileMax = 1024;  // post neurons per propagation tile (LDS accumulator width)
+constexpr int kPropWaves = 4;   // wavefronts per propagation block (one LDS tile copy each)
 
 // Conductances are signed 64-bit multiples of 2^-40 uS.  Integer addition
 // is associative, so the sum of a step's deliveries does not depend on the
@@ -29,14 +31,22 @@ struct Seg {
     int64_t base;
     int32_t inst, pop;
     int32_t n_in, n_out, n_tr, n_ltp;
-    // incoming projections: id, conductance array, reversal, decay per step
+    // incoming projections: id, conductance array, reversal, decay per step,
+    // and where their delivered partial tiles are: partial pool offset, tile
+    // width, pre population (for its list of active spike words) and the
+    // number of spike words of the pre population
     int32_t in_proj[kMaxIn];
     int64_t in_G[kMaxIn];
     double in_erev[kMaxIn];
     double in_decay[kMaxIn];
-    // outgoing projections: id and row-start array (pool offset)
+    int64_t in_P[kMaxIn];
+    int32_t in_tw[kMaxIn];
+    int32_t in_preseg[kMaxIn];
+    int32_t in_prewords[kMaxIn];
+    // outgoing projections: id, row-start array (pool offset), post tiles
     int32_t out_proj[kMaxOut];
     int64_t out_rp[kMaxOut];
+    int32_t out_tiles[kMaxOut];
     // plastic projections arriving here: id and column-start array
     int32_t ltp_proj[kMaxLtp];
     int64_t ltp_cp[kMaxLtp];
@@ -60,6 +70,14 @@ struct Proj {
     int64_t syn_base;   // col_idx / weight pool offset
     int64_t nnz;
     int64_t G_base;     // conductance pool offset (n_post)
+    // post tiles: tile_w posts each (a multiple of 64, <= kTileMax); with
+    // more than one tile, tp_base locates n_pre x (n_tiles + 1) tile starts
+    // (row-local CSR offsets of the first column >= tile * tile_w)
+    int32_t tile_w, n_tiles;
+    int64_t tp_base;    // -1: one tile, the row pointers bound it
+    int64_t P_base;     // partial pool offset: [tile][pre word][tile_w] int64
+    int32_t pre_words;  // spike words of the pre population (ceil(n_pre / 64))
+    int32_t pad2_;
     // STDP
     float a_plus_gmax, a_minus_gmax, g_max, pad_;
     int64_t x_base, y_base;    // trace pool offsets (pre n_pre, post n_post)
@@ -78,9 +96,13 @@ struct StepState {
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
     uint32_t pad_;
 };
+// Per step slot and population, how many of its spike words held a spike
+// (active-word counts, [2][n_segs]) and which ([2][n_waves], population
+// words at the population's own word offset).
 
-// A work item: synapses [k0, k1) (local offsets) of row `row` of projection
-// `proj` (propagation) or of column `row` (potentiation).
+// A work item.  Propagation: projection `proj`, post tile k0, spike word
+// `row` of the pre population (64 pre neurons).  Potentiation: synapses
+// [k0, k1) of the column of post neuron `row` of plastic projection `proj`.
 struct Item {
     int32_t proj, row, k0, k1;
 };
@@ -109,18 +131,29 @@ struct NeuronArgs {
     int32_t substeps;
     double hs;               // dt / substeps
     StepState *st;
+    const int64_t *partial;  // delivered partial tiles of the previous step
+    uint32_t *awcnt;         // [2][n_segs]
+    int32_t *awl;            // [2][n_waves]
+    int32_t n_segs;
 };
 
 struct PropArgs {
     const Proj *projs;
+    const Seg *segs;
     const Item *queue;
     int64_t qcap;
+    const int32_t *rp_pool;
+    const int32_t *tp_pool;
     const int32_t *col_pool;
     float *w_pool;
     const float *gscale;     // per instance
-    int64_t *G;
+    int64_t *partial;
+    const uint64_t *bits;    // 2 slots of n_waves spike words
+    int64_t n_waves;
     const float *trace;
     StepState *st;
+    uint32_t *awcnt;         // [2][n_segs], the slot of this step is cleared here
+    int32_t n_segs;
 };
 
 struct LtpArgs {

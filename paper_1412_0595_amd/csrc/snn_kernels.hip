@@ -2,16 +2,22 @@
 //
 //  k_neuron     one lane per neuron: Traub-Miles update (Section 2: HH at
 //               discrete time steps) or Poisson draw, upward-crossing spike
-//               test, wavefront-ballot + LDS prefix-sum compaction of the
-//               spikes into the work queue of the next step.
-//  k_propagate  persistent grid, one wavefront per work item: a slice of one
-//               spiking row of a Compressed Row Storage projection (Section 3)
-//               whose weights are added into the post-side conductances.
+//               test, wavefront ballot into the spike bitmask, and compaction
+//               (wave scan + LDS block offsets + one atomic per block) of the
+//               propagation work of the next step.
+//  k_propagate  persistent grid, one block per work item = (projection, post
+//               tile, 64-neuron spike word of the pre population).  The block
+//               stages the word's spiking rows in LDS; each wavefront walks
+//               whole row slices of the Compressed Row Storage arrays
+//               (Section 3) and adds the weights into its own LDS copy of the
+//               tile (columns within a row are distinct, so no atomics); the
+//               copies are summed into one partial tile per item.
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //
-// Conductances are int64 multiples of 2^-40 uS, so atomics from any number
-// of wavefronts give the same bits in any order.
+// Conductances are int64 multiples of 2^-40 uS: the neuron update adds the
+// partial tiles of every active spike word to its conductance, and integer
+// sums are the same in any order.
 #include <algorithm>
 
 #include "snn_device.h"
@@ -54,10 +60,24 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 const double v0 = v;
                 // synaptic current from the start-of-step voltage, held
                 // fixed over the substeps; then the conductances decay
+                // delivered conductance: decayed G plus the partial tiles of
+                // every pre spike word that was active at t - 1
                 int64_t g[kMaxIn];
+                const int prev = cur ^ 1;
 #pragma unroll
-                for (int q = 0; q < kMaxIn; ++q)
-                    if (q < S.n_in) g[q] = a.G[S.in_G[q] + j];
+                for (int q = 0; q < kMaxIn; ++q) {
+                    if (q < S.n_in) {
+                        int64_t acc = a.G[S.in_G[q] + j];
+                        const int pseg = S.in_preseg[q];
+                        const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], (uint32_t)S.in_prewords[q]);
+                        const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + a.segs[pseg].base / kWave;
+                        const int32_t tw = S.in_tw[q];
+                        const int32_t tile = j / tw;
+                        const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (j - tile * tw);
+                        for (uint32_t u = 0; u < na; ++u) acc += pp[(int64_t)wl[u] * tw];
+                        g[q] = acc;
+                    }
+                }
                 const double iin = syn_current(S, g, v0);
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
@@ -92,14 +112,19 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 *tp = *tp * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
             }
         }
+        if (ball != 0) {
+            // the word is active: record it, and queue one propagation item
+            // per (outgoing projection, post tile) for the next step
+            if (lane == 0) {
+                const uint32_t slot = atomicAdd(&a.awcnt[cur * a.n_segs + sidx], 1u);
+                if (slot < (uint32_t)((S.n + kWave - 1) / kWave))
+                    a.awl[(int64_t)cur * a.n_waves + S.base / kWave + slot] = (int32_t)(gw - S.base / kWave);
+                for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
+            }
+        }
         if (ball != 0 && spike) {
             a.counts[gid] += 1;
             const uint32_t ch = (uint32_t)a.chunk;
-            for (int o = 0; o < S.n_out; ++o) {
-                const int32_t *rp = a.rp_pool + S.out_rp[o];
-                const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
-                nq += (len + ch - 1) / ch;
-            }
             for (int o = 0; o < S.n_ltp; ++o) {
                 const int32_t *cp = a.cp_pool + S.ltp_cp[o];
                 const uint32_t len = (uint32_t)(cp[j + 1] - cp[j]);
@@ -138,18 +163,27 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     }
     __syncthreads();
 
-    if (nq | nl) {
+    // propagation items of this wave: lane 0 counted them, all lanes write
+    const uint32_t wave_nq = __shfl(nq, 0, kWave);
+    if (wave_nq) {
+        const Seg &S = a.segs[sidx];
+        const int64_t base = (int64_t)s_base[0] + s_woff[wid][0];
+        const int32_t word = (int32_t)(gw - S.base / kWave);
+        Item *qd = a.queue + (int64_t)cur * a.qcap;
+        int32_t off = 0;
+        for (int o = 0; o < S.n_out; ++o) {
+            const int32_t nt = S.out_tiles[o];
+            for (int32_t tl = lane; tl < nt; tl += kWave) {
+                const int64_t pos = base + off + tl;
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], word, tl, 0};
+            }
+            off += nt;
+        }
+    }
+    if (nl) {
         const Seg &S = a.segs[sidx];
         const int32_t ch = a.chunk;
-        int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
-        Item *qd = a.queue + (int64_t)cur * a.qcap;
-        for (int o = 0; o < S.n_out; ++o) {
-            const int32_t *rp = a.rp_pool + S.out_rp[o];
-            const int32_t k1 = rp[j + 1];
-            for (int32_t k = rp[j]; k < k1; k += ch, ++pos)
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, k1)};
-        }
-        pos = (int64_t)s_base[1] + s_woff[wid][1] + (il - nl);
+        int64_t pos = (int64_t)s_base[1] + s_woff[wid][1] + (il - nl);
         Item *ld = a.lqueue + (int64_t)cur * a.lcap;
         for (int o = 0; o < S.n_ltp; ++o) {
             const int32_t *cp = a.cp_pool + S.ltp_cp[o];
@@ -161,43 +195,96 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// CSR propagation (+ depression on plastic rows)
+// CSR propagation (+ depression on plastic rows), tiled by post neuron
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_propagate(PropArgs a)
+__global__ __launch_bounds__(256) void k_propagate(PropArgs a)
 {
+    __shared__ long long s_acc[kPropWaves][kTileMax];
+    __shared__ int32_t s_rows[kWave];
+    __shared__ int32_t s_nrows;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
     const int64_t t = a.st->t_prop;
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
     const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
     const Item *q = a.queue + (int64_t)prev * a.qcap;
-    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    uint32_t it = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
 
-    for (; it < n; it += nw) {
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
-        const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
-        const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
+        const int32_t word = __builtin_amdgcn_readfirstlane(q[it].row);
+        const int32_t tile = __builtin_amdgcn_readfirstlane(q[it].k0);
         const Proj &P = a.projs[proj];
+        const int32_t tw = P.tile_w;
+        const int32_t c0 = tile * tw;
+        // stage the spiking rows of this word in LDS (ascending order)
+        if (wid == 0) {
+            const Seg &pre = a.segs[P.pre_seg];
+            const uint64_t bits = a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word];
+            const bool on = (bits >> lane) & 1ull;
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+            if (on) s_rows[below] = word * kWave + lane;
+            if (lane == 0) s_nrows = __popcll(bits);
+        }
+        long long *acc = s_acc[wid];
+        for (int i = lane; i < tw; i += kWave) acc[i] = 0;
+        __syncthreads();
+        const int nrows = s_nrows;
         const double s = (double)a.gscale[P.inst] * kFixOne;
         const int32_t *col = a.col_pool + P.syn_base;
         float *w = a.w_pool + P.syn_base;
-        int64_t *G = a.G + P.G_base;
-        if (!P.stdp) {
-            for (int32_t k = k0 + lane; k < k1; k += kWave) {
-                const int32_t c = col[k];
-                atomicAdd((unsigned long long *)(G + c), (unsigned long long)fix_increment(s, w[k]));
+        const int32_t *rp = a.rp_pool + P.rp_base;
+        const int32_t *tp = a.tp_pool + (P.tp_base < 0 ? 0 : P.tp_base);
+        for (int r = wid; r < nrows; r += kPropWaves) {
+            const int32_t i = s_rows[r];
+            int32_t k0, k1;
+            if (P.tp_base < 0) {
+                k0 = rp[i];
+                k1 = rp[i + 1];
+            } else {
+                k0 = tp[(int64_t)i * (P.n_tiles + 1) + tile];
+                k1 = tp[(int64_t)i * (P.n_tiles + 1) + tile + 1];
             }
-        } else {
-            const float *y = a.trace + P.y_base;
-            for (int32_t k = k0 + lane; k < k1; k += kWave) {
-                const int32_t c = col[k];
-                const float gv = w[k];
-                atomicAdd((unsigned long long *)(G + c), (unsigned long long)fix_increment(s, gv));
-                w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+            k0 = __builtin_amdgcn_readfirstlane(k0);
+            k1 = __builtin_amdgcn_readfirstlane(k1);
+            if (!P.stdp) {
+                int32_t k = k0 + lane;
+                for (; k + 3 * kWave < k1; k += 4 * kWave) {
+                    int32_t c[4];
+                    float g[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        c[u] = col[k + u * kWave];
+                        g[u] = w[k + u * kWave];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
+                }
+                for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
+            } else {
+                const float *y = a.trace + P.y_base;
+                for (int32_t k = k0 + lane; k < k1; k += kWave) {
+                    const int32_t c = col[k];
+                    const float gv = w[k];
+                    acc[c - c0] += fix_increment(s, gv);
+                    w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+                }
             }
         }
+        __syncthreads();
+        int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + word) * tw;
+        for (int i = threadIdx.x; i < tw; i += blockDim.x) {
+            long long v = s_acc[0][i];
+#pragma unroll
+            for (int u = 1; u < kPropWaves; ++u) v += s_acc[u][i];
+            out[i] = v;
+        }
+        __syncthreads();
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->t_neuron = t;
+    if (blockIdx.x == 0) {
+        // active-word counts of the slot the next neuron update fills
+        for (int i = threadIdx.x; i < a.n_segs; i += blockDim.x) a.awcnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
+        if (threadIdx.x == 0) a.st->t_neuron = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -256,7 +343,8 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s)
 
 hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_propagate, dim3(blocks), dim3(block), 0, s, a);
+    (void)block;    // the tiled kernel runs kPropWaves wavefronts per block
+    hipLaunchKernelGGL(k_propagate, dim3(blocks), dim3(kPropWaves * kWave), 0, s, a);
     return hipGetLastError();
 }
 

@@ -118,7 +118,10 @@ struct snn_net {
     Seg *d_segs;
     Proj *d_projs;
     int32_t *d_wave_seg;
-    int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos;
+    int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos, *d_tp;
+    int64_t *d_partial;
+    uint32_t *awcnt;     // arena: [2][n_segs]
+    int32_t *awl;        // arena: [2][n_waves]
     float *d_w;
     float *d_gscale;
     int64_t w_count;
@@ -253,6 +256,10 @@ NeuronArgs neuron_args(snn_net *net)
     a.substeps = net->substeps;
     a.hs = net->dt / net->substeps;
     a.st = net->st;
+    a.partial = net->d_partial;
+    a.awcnt = net->awcnt;
+    a.awl = net->awl;
+    a.n_segs = (int32_t)net->segs.size();
     return a;
 }
 
@@ -260,14 +267,21 @@ PropArgs prop_args(snn_net *net)
 {
     PropArgs p{};
     p.projs = net->d_projs;
+    p.segs = net->d_segs;
     p.queue = net->queue;
     p.qcap = net->qcap;
+    p.rp_pool = net->d_rp;
+    p.tp_pool = net->d_tp;
     p.col_pool = net->d_col;
     p.w_pool = net->d_w;
     p.gscale = net->d_gscale;
-    p.G = net->G;
+    p.partial = net->d_partial;
+    p.bits = net->bits;
+    p.n_waves = net->n_waves;
     p.trace = net->trace;
     p.st = net->st;
+    p.awcnt = net->awcnt;
+    p.n_segs = (int32_t)net->segs.size();
     return p;
 }
 
@@ -426,7 +440,8 @@ int validate(const snn_config *cfg)
                 for (int32_t k = a0; k < a1; ++k) {
                     const int32_t c = Q.col_idx[k];
                     if (c < 0 || c >= npost) return fail(SNN_EINVAL, "instance %d proj %d: col_idx[%d] = %d out of range", b, q, k, c);
-                    if (k > a0 && c < Q.col_idx[k - 1]) return fail(SNN_EINVAL, "instance %d proj %d: row %d not sorted", b, q, i);
+                    if (k > a0 && c <= Q.col_idx[k - 1])
+                        return fail(SNN_EINVAL, "instance %d proj %d: row %d not strictly ascending (sorted, no duplicate synapse)", b, q, i);
                     if (!(Q.g[k] >= 0.0f) || !std::isfinite(Q.g[k])) return fail(SNN_EINVAL, "instance %d proj %d: g[%d] not finite and >= 0", b, q, k);
                 }
             }
@@ -551,6 +566,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
 
     // ---- layout: segments, projections, pools
     int64_t base = 0, rp_total = 0, syn_total = 0, G_total = 0, tr_total = 0, cp_total = 0, csc_total = 0;
+    int64_t P_total = 0, tp_total = 0;
     net->seg_of.resize(net->n_inst);
     net->proj_of.resize(net->n_inst);
     net->gscale.resize(net->n_inst);
@@ -598,7 +614,21 @@ int snn_create(const snn_config *cfg, snn_net **out)
             syn_total += Q.nnz;
             P.G_base = G_total;
             G_total += post.n;
+            P.tile_w = (int32_t)std::min<int64_t>(kTileMax, std::max<int64_t>(kWave, align_up(post.n, kWave)));
+            P.n_tiles = (int32_t)((post.n + P.tile_w - 1) / P.tile_w);
+            P.pre_words = (int32_t)(align_up(pre.n, kWave) / kWave);
+            P.P_base = P_total;
+            P_total += (int64_t)P.n_tiles * P.pre_words * P.tile_w;
+            P.tp_base = -1;
+            if (P.n_tiles > 1) {
+                P.tp_base = tp_total;
+                tp_total += (int64_t)pre.n * (P.n_tiles + 1);
+            }
             const double decay = std::exp(-net->dt / (double)Q.tau_ms);
+            post.in_P[post.n_in] = P.P_base;
+            post.in_tw[post.n_in] = P.tile_w;
+            post.in_preseg[post.n_in] = P.pre_seg;
+            post.in_prewords[post.n_in] = P.pre_words;
             post.in_proj[post.n_in] = gi;
             post.in_G[post.n_in] = P.G_base;
             post.in_erev[post.n_in] = Q.e_rev_mV;
@@ -606,6 +636,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
             post.n_in++;
             pre.out_proj[pre.n_out] = gi;
             pre.out_rp[pre.n_out] = P.rp_base;
+            pre.out_tiles[pre.n_out] = P.n_tiles;
             pre.n_out++;
             HostProj H{};
             H.inst = b; H.pre_pop = Q.pre_pop; H.post_pop = Q.post_pop; H.n_pre = pre.n; H.n_post = post.n;
@@ -654,13 +685,10 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->G_count = G_total;
     net->trace_count = tr_total;
 
-    // work-queue capacity: every neuron spiking at once, with the smallest chunk
+    // work-queue capacity: every spike word active at once (one item per
+    // projection, post tile and pre word); potentiation with the smallest chunk
     int64_t qcap = 0, lcap = 0;
-    for (size_t q = 0; q < net->projs.size(); ++q) {
-        const HostProj &H = net->hprojs[q];
-        for (int32_t i = 0; i < H.n_pre; ++i)
-            qcap += (H.row_ptr[i + 1] - H.row_ptr[i] + kMinChunk - 1) / kMinChunk;
-    }
+    for (const Proj &P : net->projs) qcap += (int64_t)P.n_tiles * P.pre_words;
     // column lengths of plastic projections
     std::vector<std::vector<int32_t>> colptrs(net->projs.size());
     for (int b = 0, gq = 0; b < net->n_inst; ++b) {
@@ -709,6 +737,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_queue = part(2 * net->qcap * (int64_t)sizeof(Item));
     Part p_lqueue = part(2 * net->lcap * (int64_t)sizeof(Item));
     Part p_st = part(sizeof(StepState));
+    Part p_awcnt = part(2 * (int64_t)net->segs.size() * 4);
+    Part p_awl = part(2 * W * 4);
     net->arena_bytes = off;
     net->d_arena = (char *)dev_alloc(net, (size_t)off);
     net->d_segs = (Seg *)dev_alloc(net, sizeof(Seg) * net->segs.size());
@@ -721,8 +751,10 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->d_csc_row = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(csc_total, 1));
     net->d_csc_pos = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(csc_total, 1));
     net->d_gscale = (float *)dev_alloc(net, 4 * net->n_inst);
+    net->d_tp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(tp_total, 1));
+    net->d_partial = (int64_t *)dev_alloc(net, 8 * std::max<int64_t>(P_total, 1));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
-        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale)
+        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -737,6 +769,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->queue = (Item *)(A + p_queue.off);
     net->lqueue = (Item *)(A + p_lqueue.off);
     net->st = (StepState *)(A + p_st.off);
+    net->awcnt = (uint32_t *)(A + p_awcnt.off);
+    net->awl = (int32_t *)(A + p_awl.off);
 
     // ---- uploads
     auto up = [&](void *dst, const void *src, size_t bytes) -> int {
@@ -765,6 +799,20 @@ int snn_create(const snn_config *cfg, snn_net **out)
             if ((rc = up(net->d_rp + P.rp_base, Q.row_ptr, 4 * (size_t)(P.n_pre + 1)))) return bail(rc);
             if ((rc = up(net->d_col + P.syn_base, Q.col_idx, 4 * (size_t)Q.nnz))) return bail(rc);
             if ((rc = up(net->d_w + P.syn_base, Q.g, 4 * (size_t)Q.nnz))) return bail(rc);
+            if (P.tp_base >= 0) {
+                // start of every post tile in every row (columns ascend within a row)
+                std::vector<int32_t> tp((size_t)P.n_pre * (P.n_tiles + 1));
+                for (int32_t i = 0; i < P.n_pre; ++i) {
+                    int32_t k = Q.row_ptr[i];
+                    for (int32_t tl = 0; tl <= P.n_tiles; ++tl) {
+                        const int64_t lim = (int64_t)tl * P.tile_w;
+                        while (k < Q.row_ptr[i + 1] && Q.col_idx[k] < lim) ++k;
+                        tp[(size_t)i * (P.n_tiles + 1) + tl] = k;
+                    }
+                    tp[(size_t)i * (P.n_tiles + 1) + P.n_tiles] = Q.row_ptr[i + 1];
+                }
+                if ((rc = up(net->d_tp + P.tp_base, tp.data(), 4 * tp.size()))) return bail(rc);
+            }
             if (Q.stdp) {
                 // column view: entries of column j in ascending row order
                 std::vector<int32_t> fill(H.col_ptr.begin(), H.col_ptr.end() - 1), rows(Q.nnz), pos(Q.nnz);
@@ -1014,9 +1062,10 @@ int snn_get_last_spikes(snn_net *net, int32_t inst, int32_t pop, uint8_t *out)
     return SNN_OK;
 }
 
-// Replace S(t-1) of one population: rewrite its bitmask words and rebuild
-// the work items of the slot the next step consumes (items of the other
-// populations are kept).
+// Replace S(t-1) of one population: rewrite its bitmask words, rebuild the
+// active-word lists and the propagation items of the slot the next step
+// consumes (from the bitmasks of every population), and the potentiation
+// items of this population's columns.
 int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *in)
 {
     int rc = check_net(net);
@@ -1033,37 +1082,48 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
     if ((rc = h2d(net, net->bits + slot * net->n_waves + S.base / kWave, words.data(), 8 * (size_t)nw))) return rc;
     StepState st;
     if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
-    const int32_t ch = net->launch.chunk;
-    for (int which = 0; which < 2; ++which) {
-        const uint32_t n = which == 0 ? st.qcnt[slot] : st.lcnt[slot];
-        Item *dq = (which == 0 ? net->queue : net->lqueue) + (int64_t)slot * (which == 0 ? net->qcap : net->lcap);
-        std::vector<Item> items(n);
-        if ((rc = d2h(net, items.data(), dq, sizeof(Item) * n))) return rc;
-        std::vector<Item> keep;
-        for (const Item &it : items) {
-            const Proj &P = net->projs[it.proj];
-            const int owner = which == 0 ? P.pre_seg : P.post_seg;
-            if (owner != s) keep.push_back(it);
+    // propagation: every active word of every population, all projections and tiles
+    std::vector<uint64_t> all(net->n_waves);
+    if ((rc = d2h(net, all.data(), net->bits + slot * net->n_waves, 8 * (size_t)net->n_waves))) return rc;
+    const size_t nseg = net->segs.size();
+    std::vector<uint32_t> cnt(nseg, 0);
+    std::vector<int32_t> awl(net->n_waves, 0);
+    std::vector<Item> items;
+    for (size_t g = 0; g < nseg; ++g) {
+        const Seg &G = net->segs[g];
+        const int64_t w0 = G.base / kWave, gw = align_up(G.n, kWave) / kWave;
+        for (int64_t w = 0; w < gw; ++w) {
+            if (!all[w0 + w]) continue;
+            awl[w0 + cnt[g]++] = (int32_t)w;
+            for (int o = 0; o < G.n_out; ++o)
+                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl) items.push_back(Item{G.out_proj[o], (int32_t)w, tl, 0});
         }
+    }
+    if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
+    if ((rc = h2d(net, net->queue + (int64_t)slot * net->qcap, items.data(), sizeof(Item) * items.size()))) return rc;
+    if ((rc = h2d(net, net->awcnt + (int64_t)slot * nseg, cnt.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
+    st.qcnt[slot] = (uint32_t)items.size();
+    // potentiation: replace this population's column items
+    {
+        const int32_t ch = net->launch.chunk;
+        const uint32_t n = st.lcnt[slot];
+        Item *dq = net->lqueue + (int64_t)slot * net->lcap;
+        std::vector<Item> old(n), keep;
+        if ((rc = d2h(net, old.data(), dq, sizeof(Item) * n))) return rc;
+        for (const Item &it : old)
+            if (net->projs[it.proj].post_seg != s) keep.push_back(it);
         for (int i = 0; i < S.n; ++i) {
             if (!in[i]) continue;
-            if (which == 0) {
-                for (int o = 0; o < S.n_out; ++o) {
-                    const HostProj &H = net->hprojs[S.out_proj[o]];
-                    for (int32_t k = H.row_ptr[i]; k < H.row_ptr[i + 1]; k += ch)
-                        keep.push_back(Item{S.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1])});
-                }
-            } else {
-                for (int o = 0; o < S.n_ltp; ++o) {
-                    const HostProj &H = net->hprojs[S.ltp_proj[o]];
-                    for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
-                        keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1])});
-                }
+            for (int o = 0; o < S.n_ltp; ++o) {
+                const HostProj &H = net->hprojs[S.ltp_proj[o]];
+                for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
+                    keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1])});
             }
         }
-        if ((int64_t)keep.size() > (which == 0 ? net->qcap : net->lcap)) return fail(SNN_ERANGE, "too many work items");
+        if ((int64_t)keep.size() > net->lcap) return fail(SNN_ERANGE, "too many work items");
         if ((rc = h2d(net, dq, keep.data(), sizeof(Item) * keep.size()))) return rc;
-        if (which == 0) st.qcnt[slot] = (uint32_t)keep.size(); else st.lcnt[slot] = (uint32_t)keep.size();
+        st.lcnt[slot] = (uint32_t)keep.size();
     }
     return h2d(net, net->st, &st, sizeof st);
 }
