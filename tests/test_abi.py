@@ -81,7 +81,21 @@ def test_unsorted_row_rejected():
             q["col_idx"][rp[i] + 1] = a
             break
     rc, msg = snn.create_status(spec)
-    assert rc == snn.SNN_EINVAL and "not sorted" in msg
+    assert rc == snn.SNN_EINVAL and "not strictly ascending" in msg
+
+
+def test_duplicate_synapse_rejected():
+    """A row may not list the same post neuron twice: the tiled propagation
+    relies on distinct columns within a row."""
+    spec = copy.deepcopy(_tiny())
+    q = _first_nonempty(spec["instances"][0])
+    rp = q["row_ptr"]
+    for i in range(rp.size - 1):
+        if rp[i + 1] - rp[i] >= 2:
+            q["col_idx"][rp[i] + 1] = q["col_idx"][rp[i]]
+            break
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_EINVAL and "not strictly ascending" in msg
 
 
 def test_decreasing_row_ptr_rejected():
