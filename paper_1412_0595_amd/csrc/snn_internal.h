@@ -15,6 +15,23 @@ constexpr int kMaxLtp = 2;   // plastic projections arriving at one population
 constexpr int kMinChunk = 64;
 constexpr int kTileMax = 1024;  // post neurons per propagation tile (LDS accumulator width)
 constexpr int kPropWaves = 4;   // wavefronts per propagation block (one LDS tile copy each)
+constexpr int kMinGroups = 32;  // partial tiles per (projection, post tile) the neuron update sums at least
+constexpr int kRowsPerGroup = 32;  // spiking rows per group aimed for when more groups are allowed
+
+// Active spike words of a pre population are processed in groups of
+// consecutive active-list slots: with na active words and `rows` spiking
+// rows at the previous step, a group holds ceil(na / n_groups) words, where
+// n_groups = clamp(rows / kRowsPerGroup, kMinGroups, words).  Each group
+// leaves one partial tile; the neuron update sums the groups' partials.
+__host__ __device__ inline uint32_t group_words(uint32_t na, uint32_t rows, uint32_t words)
+{
+    uint32_t g = rows / kRowsPerGroup;
+    if (g < (uint32_t)kMinGroups) g = kMinGroups;
+    if (g > words) g = words;
+    if (g < 1) g = 1;
+    const uint32_t gw = (na + g - 1) / g;
+    return gw < 1 ? 1 : gw;
+}
 
 // Conductances are signed 64-bit multiples of 2^-40 uS.  Integer addition
 // is associative, so the sum of a step's deliveries does not depend on the
@@ -75,7 +92,7 @@ struct Proj {
     // (row-local CSR offsets of the first column >= tile * tile_w)
     int32_t tile_w, n_tiles;
     int64_t tp_base;    // -1: one tile, the row pointers bound it
-    int64_t P_base;     // partial pool offset: [tile][pre word][tile_w] int64
+    int64_t P_base;     // partial pool offset: [tile][active-word slot][tile_w] int64
     int32_t pre_words;  // spike words of the pre population (ceil(n_pre / 64))
     int32_t pad2_;
     // STDP
@@ -101,7 +118,8 @@ struct StepState {
 // words at the population's own word offset).
 
 // A work item.  Propagation: projection `proj`, post tile k0, spike word
-// `row` of the pre population (64 pre neurons).  Potentiation: synapses
+// `row` of the pre population (64 pre neurons), whose slot in the active
+// list is k1 (its partial tile is stored at that slot).  Potentiation: synapses
 // [k0, k1) of the column of post neuron `row` of plastic projection `proj`.
 struct Item {
     int32_t proj, row, k0, k1;
@@ -132,7 +150,8 @@ struct NeuronArgs {
     double hs;               // dt / substeps
     StepState *st;
     const int64_t *partial;  // delivered partial tiles of the previous step
-    uint32_t *awcnt;         // [2][n_segs]
+    uint32_t *awcnt;         // [2][n_segs]  active spike words
+    uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
     int32_t n_segs;
 };
@@ -153,6 +172,8 @@ struct PropArgs {
     const float *trace;
     StepState *st;
     uint32_t *awcnt;         // [2][n_segs], the slot of this step is cleared here
+    uint32_t *scnt;          // [2][n_segs], likewise
+    const int32_t *awl;      // [2][n_waves]
     int32_t n_segs;
 };
 

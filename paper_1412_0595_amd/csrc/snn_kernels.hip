@@ -6,12 +6,13 @@
 //               (wave scan + LDS block offsets + one atomic per block) of the
 //               propagation work of the next step.
 //  k_propagate  persistent grid, one block per work item = (projection, post
-//               tile, 64-neuron spike word of the pre population).  The block
-//               stages the word's spiking rows in LDS; each wavefront walks
-//               whole row slices of the Compressed Row Storage arrays
-//               (Section 3) and adds the weights into its own LDS copy of the
-//               tile (columns within a row are distinct, so no atomics); the
-//               copies are summed into one partial tile per item.
+//               tile, group of active 64-neuron spike words of the pre
+//               population).  The block stages each word's spiking rows in
+//               LDS; each wavefront walks whole row slices of the Compressed
+//               Row Storage arrays (Section 3) and adds the weights into its
+//               own LDS copy of the tile (columns within a row are distinct,
+//               so no atomics); the copies are summed into one partial tile
+//               per group.
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //
@@ -41,6 +42,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 
     bool spike = false;
     uint32_t nq = 0, nl = 0;       // work items this lane emits
+    uint32_t wslot = 0;            // slot of this wave's word in the active list
     int sidx = 0;
     int32_t j = 0;
 
@@ -69,12 +71,25 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                     if (q < S.n_in) {
                         int64_t acc = a.G[S.in_G[q] + j];
                         const int pseg = S.in_preseg[q];
-                        const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], (uint32_t)S.in_prewords[q]);
-                        const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + a.segs[pseg].base / kWave;
+                        const uint32_t words = (uint32_t)S.in_prewords[q];
+                        const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], words);
+                        const uint32_t ng = na ? (na + group_words(na, a.scnt[prev * a.n_segs + pseg], words) - 1) /
+                                                     group_words(na, a.scnt[prev * a.n_segs + pseg], words)
+                                               : 0u;
                         const int32_t tw = S.in_tw[q];
                         const int32_t tile = j / tw;
+                        // one partial tile per group of active words, stored
+                        // contiguously by group index
                         const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (j - tile * tw);
-                        for (uint32_t u = 0; u < na; ++u) acc += pp[(int64_t)wl[u] * tw];
+                        uint32_t u = 0;
+                        for (; u + 16 <= ng; u += 16) {
+                            int64_t v[16];
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) v[k] = pp[(int64_t)(u + k) * tw];
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) acc += v[k];
+                        }
+                        for (; u < ng; ++u) acc += pp[(int64_t)u * tw];
                         g[q] = acc;
                     }
                 }
@@ -116,10 +131,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             // the word is active: record it, and queue one propagation item
             // per (outgoing projection, post tile) for the next step
             if (lane == 0) {
-                const uint32_t slot = atomicAdd(&a.awcnt[cur * a.n_segs + sidx], 1u);
-                if (slot < (uint32_t)((S.n + kWave - 1) / kWave))
-                    a.awl[(int64_t)cur * a.n_waves + S.base / kWave + slot] = (int32_t)(gw - S.base / kWave);
-                for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
+                wslot = atomicAdd(&a.awcnt[cur * a.n_segs + sidx], 1u);
+                // a slot beyond the population's word count can only come
+                // from repeating one step's update (kernel timing): no items
+                if (wslot < (uint32_t)((S.n + kWave - 1) / kWave)) {
+                    a.awl[(int64_t)cur * a.n_waves + S.base / kWave + wslot] = (int32_t)(gw - S.base / kWave);
+                    atomicAdd(&a.scnt[cur * a.n_segs + sidx], (uint32_t)__popcll(ball));
+                    for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
+                }
             }
         }
         if (ball != 0 && spike) {
@@ -169,13 +188,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         const Seg &S = a.segs[sidx];
         const int64_t base = (int64_t)s_base[0] + s_woff[wid][0];
         const int32_t word = (int32_t)(gw - S.base / kWave);
+        const int32_t slot = (int32_t)__shfl(wslot, 0, kWave);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
         int32_t off = 0;
         for (int o = 0; o < S.n_out; ++o) {
             const int32_t nt = S.out_tiles[o];
             for (int32_t tl = lane; tl < nt; tl += kWave) {
                 const int64_t pos = base + off + tl;
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], word, tl, 0};
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], word, tl, slot};
             }
             off += nt;
         }
@@ -211,67 +231,80 @@ __global__ __launch_bounds__(256) void k_propagate(PropArgs a)
 
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
-        const int32_t word = __builtin_amdgcn_readfirstlane(q[it].row);
         const int32_t tile = __builtin_amdgcn_readfirstlane(q[it].k0);
+        const int32_t slot = __builtin_amdgcn_readfirstlane(q[it].k1);
         const Proj &P = a.projs[proj];
+        if (slot >= P.pre_words || tile >= P.n_tiles) continue;   // malformed item
+        // the item of the first slot of each group processes the whole group
+        const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        const uint32_t gw = group_words(na, a.scnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        if ((uint32_t)slot % gw != 0 || (uint32_t)slot >= na) continue;
+        const uint32_t group = (uint32_t)slot / gw;
+        const uint32_t nwords = min(gw, na - (uint32_t)slot);
         const int32_t tw = P.tile_w;
         const int32_t c0 = tile * tw;
-        // stage the spiking rows of this word in LDS (ascending order)
-        if (wid == 0) {
-            const Seg &pre = a.segs[P.pre_seg];
-            const uint64_t bits = a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word];
-            const bool on = (bits >> lane) & 1ull;
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
-            if (on) s_rows[below] = word * kWave + lane;
-            if (lane == 0) s_nrows = __popcll(bits);
-        }
+        const Seg &pre = a.segs[P.pre_seg];
         long long *acc = s_acc[wid];
         for (int i = lane; i < tw; i += kWave) acc[i] = 0;
-        __syncthreads();
-        const int nrows = s_nrows;
         const double s = (double)a.gscale[P.inst] * kFixOne;
         const int32_t *col = a.col_pool + P.syn_base;
         float *w = a.w_pool + P.syn_base;
         const int32_t *rp = a.rp_pool + P.rp_base;
         const int32_t *tp = a.tp_pool + (P.tp_base < 0 ? 0 : P.tp_base);
-        for (int r = wid; r < nrows; r += kPropWaves) {
-            const int32_t i = s_rows[r];
-            int32_t k0, k1;
-            if (P.tp_base < 0) {
-                k0 = rp[i];
-                k1 = rp[i + 1];
-            } else {
-                k0 = tp[(int64_t)i * (P.n_tiles + 1) + tile];
-                k1 = tp[(int64_t)i * (P.n_tiles + 1) + tile + 1];
+        const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + pre.base / kWave + slot;
+        for (uint32_t wi = 0; wi < nwords; ++wi) {
+            const int32_t word = wl[wi];
+            // stage the spiking rows of this word in LDS (ascending order)
+            __syncthreads();
+            if (wid == 0) {
+                const uint64_t bits = a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word];
+                const bool on = (bits >> lane) & 1ull;
+                const uint32_t below =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+                if (on) s_rows[below] = word * kWave + lane;
+                if (lane == 0) s_nrows = __popcll(bits);
             }
-            k0 = __builtin_amdgcn_readfirstlane(k0);
-            k1 = __builtin_amdgcn_readfirstlane(k1);
-            if (!P.stdp) {
-                int32_t k = k0 + lane;
-                for (; k + 3 * kWave < k1; k += 4 * kWave) {
-                    int32_t c[4];
-                    float g[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        c[u] = col[k + u * kWave];
-                        g[u] = w[k + u * kWave];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
+            __syncthreads();
+            const int nrows = s_nrows;
+            for (int r = wid; r < nrows; r += kPropWaves) {
+                const int32_t i = s_rows[r];
+                int32_t k0, k1;
+                if (P.tp_base < 0) {
+                    k0 = rp[i];
+                    k1 = rp[i + 1];
+                } else {
+                    k0 = tp[(int64_t)i * (P.n_tiles + 1) + tile];
+                    k1 = tp[(int64_t)i * (P.n_tiles + 1) + tile + 1];
                 }
-                for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
-            } else {
-                const float *y = a.trace + P.y_base;
-                for (int32_t k = k0 + lane; k < k1; k += kWave) {
-                    const int32_t c = col[k];
-                    const float gv = w[k];
-                    acc[c - c0] += fix_increment(s, gv);
-                    w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+                k0 = __builtin_amdgcn_readfirstlane(k0);
+                k1 = __builtin_amdgcn_readfirstlane(k1);
+                if (!P.stdp) {
+                    int32_t k = k0 + lane;
+                    for (; k + 3 * kWave < k1; k += 4 * kWave) {
+                        int32_t c[4];
+                        float g[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            c[u] = col[k + u * kWave];
+                            g[u] = w[k + u * kWave];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
+                    }
+                    for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
+                } else {
+                    const float *y = a.trace + P.y_base;
+                    for (int32_t k = k0 + lane; k < k1; k += kWave) {
+                        const int32_t c = col[k];
+                        const float gv = w[k];
+                        acc[c - c0] += fix_increment(s, gv);
+                        w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+                    }
                 }
             }
         }
         __syncthreads();
-        int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + word) * tw;
+        int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
         for (int i = threadIdx.x; i < tw; i += blockDim.x) {
             long long v = s_acc[0][i];
 #pragma unroll
@@ -282,7 +315,10 @@ __global__ __launch_bounds__(256) void k_propagate(PropArgs a)
     }
     if (blockIdx.x == 0) {
         // active-word counts of the slot the next neuron update fills
-        for (int i = threadIdx.x; i < a.n_segs; i += blockDim.x) a.awcnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
+        for (int i = threadIdx.x; i < a.n_segs; i += blockDim.x) {
+            a.awcnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
+            a.scnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
+        }
         if (threadIdx.x == 0) a.st->t_neuron = t;
     }
 }

@@ -121,6 +121,7 @@ struct snn_net {
     int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos, *d_tp;
     int64_t *d_partial;
     uint32_t *awcnt;     // arena: [2][n_segs]
+    uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
     float *d_w;
     float *d_gscale;
@@ -258,6 +259,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.st = net->st;
     a.partial = net->d_partial;
     a.awcnt = net->awcnt;
+    a.scnt = net->scnt;
     a.awl = net->awl;
     a.n_segs = (int32_t)net->segs.size();
     return a;
@@ -281,6 +283,8 @@ PropArgs prop_args(snn_net *net)
     p.trace = net->trace;
     p.st = net->st;
     p.awcnt = net->awcnt;
+    p.scnt = net->scnt;
+    p.awl = net->awl;
     p.n_segs = (int32_t)net->segs.size();
     return p;
 }
@@ -738,6 +742,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_lqueue = part(2 * net->lcap * (int64_t)sizeof(Item));
     Part p_st = part(sizeof(StepState));
     Part p_awcnt = part(2 * (int64_t)net->segs.size() * 4);
+    Part p_scnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_awl = part(2 * W * 4);
     net->arena_bytes = off;
     net->d_arena = (char *)dev_alloc(net, (size_t)off);
@@ -770,6 +775,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->lqueue = (Item *)(A + p_lqueue.off);
     net->st = (StepState *)(A + p_st.off);
     net->awcnt = (uint32_t *)(A + p_awcnt.off);
+    net->scnt = (uint32_t *)(A + p_scnt.off);
     net->awl = (int32_t *)(A + p_awl.off);
 
     // ---- uploads
@@ -1086,7 +1092,7 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
     std::vector<uint64_t> all(net->n_waves);
     if ((rc = d2h(net, all.data(), net->bits + slot * net->n_waves, 8 * (size_t)net->n_waves))) return rc;
     const size_t nseg = net->segs.size();
-    std::vector<uint32_t> cnt(nseg, 0);
+    std::vector<uint32_t> cnt(nseg, 0), spk(nseg, 0);
     std::vector<int32_t> awl(net->n_waves, 0);
     std::vector<Item> items;
     for (size_t g = 0; g < nseg; ++g) {
@@ -1094,14 +1100,17 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
         const int64_t w0 = G.base / kWave, gw = align_up(G.n, kWave) / kWave;
         for (int64_t w = 0; w < gw; ++w) {
             if (!all[w0 + w]) continue;
-            awl[w0 + cnt[g]++] = (int32_t)w;
+            const int32_t slot = (int32_t)cnt[g]++;
+            awl[w0 + slot] = (int32_t)w;
+            spk[g] += (uint32_t)__builtin_popcountll(all[w0 + w]);
             for (int o = 0; o < G.n_out; ++o)
-                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl) items.push_back(Item{G.out_proj[o], (int32_t)w, tl, 0});
+                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl) items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot});
         }
     }
     if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
     if ((rc = h2d(net, net->queue + (int64_t)slot * net->qcap, items.data(), sizeof(Item) * items.size()))) return rc;
     if ((rc = h2d(net, net->awcnt + (int64_t)slot * nseg, cnt.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->scnt + (int64_t)slot * nseg, spk.data(), 4 * nseg))) return rc;
     if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
     st.qcnt[slot] = (uint32_t)items.size();
     // potentiation: replace this population's column items
