@@ -58,13 +58,6 @@ __device__ __forceinline__ void hh_substep_vjp(const Seg &S, double hs, double h
     ln = nn;
 }
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // ---------------------------------------------------------------------------
 // Recompute one segment of the loss population of every instance from its
 // checkpoint (block b = instance b, thread j = neuron j), writing the tape.

@@ -43,6 +43,14 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
     return x;
 }
 
+// A 64-bit value known to be the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Fixed-point increment of one delivered synapse: g_scale * g on the
 // 2^-40 uS grid (s_fix = g_scale * 2^40; the product of two fp32 values is
 // exact in double, so the only rounding is the final one).

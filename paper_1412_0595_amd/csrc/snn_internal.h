@@ -118,11 +118,14 @@ struct StepState {
 // words at the population's own word offset).
 
 // A work item.  Propagation: projection `proj`, post tile k0, spike word
-// `row` of the pre population (64 pre neurons), whose slot in the active
-// list is k1 (its partial tile is stored at that slot).  Potentiation: synapses
+// `row` of the pre population (64 pre neurons) with its bits, and the
+// word's slot k1 in the active list (the item of a group's first slot
+// processes the group).  Potentiation: synapses
 // [k0, k1) of the column of post neuron `row` of plastic projection `proj`.
 struct Item {
     int32_t proj, row, k0, k1;
+    uint64_t bits;      // propagation: the spike word itself
+    uint64_t pad_;
 };
 
 struct NeuronArgs {

@@ -5,14 +5,13 @@
 //               test, wavefront ballot into the spike bitmask, and compaction
 //               (wave scan + LDS block offsets + one atomic per block) of the
 //               propagation work of the next step.
-//  k_propagate  persistent grid, one block per work item = (projection, post
-//               tile, group of active 64-neuron spike words of the pre
-//               population).  The block stages each word's spiking rows in
-//               LDS; each wavefront walks whole row slices of the Compressed
-//               Row Storage arrays (Section 3) and adds the weights into its
-//               own LDS copy of the tile (columns within a row are distinct,
-//               so no atomics); the copies are summed into one partial tile
-//               per group.
+//  k_propagate  persistent grid of independent wavefronts, one per work item =
+//               (projection, post tile, group of active 64-neuron spike words
+//               of the pre population).  The wavefront walks the row slices
+//               of the group's spiking rows in the Compressed Row Storage
+//               arrays (Section 3) and adds the weights into its own LDS tile
+//               (columns within a row are distinct, so no atomics), then
+//               writes the tile out as the group's partial.
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //
@@ -43,6 +42,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     bool spike = false;
     uint32_t nq = 0, nl = 0;       // work items this lane emits
     uint32_t wslot = 0;            // slot of this wave's word in the active list
+    uint64_t wball = 0;            // this wave's spike word
     int sidx = 0;
     int32_t j = 0;
 
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         }
 
         const uint64_t ball = __ballot(spike);
+        wball = ball;
         if (lane == 0) {
             a.bits[(int64_t)cur * a.n_waves + gw] = ball;
             if (a.raster) a.raster[(t % a.raster_steps) * a.n_waves + gw] = ball;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             const int32_t nt = S.out_tiles[o];
             for (int32_t tl = lane; tl < nt; tl += kWave) {
                 const int64_t pos = base + off + tl;
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], word, tl, slot};
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], word, tl, slot, wball, 0};
             }
             off += nt;
         }
@@ -209,32 +210,35 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             const int32_t *cp = a.cp_pool + S.ltp_cp[o];
             const int32_t k1 = cp[j + 1];
             for (int32_t k = cp[j]; k < k1; k += ch, ++pos)
-                if (pos < a.lcap) ld[pos] = Item{S.ltp_proj[o], j, k, min(k + ch, k1)};
+                if (pos < a.lcap) ld[pos] = Item{S.ltp_proj[o], j, k, min(k + ch, k1), 0, 0};
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// CSR propagation (+ depression on plastic rows), tiled by post neuron
+// CSR propagation (+ depression on plastic rows), tiled by post neuron.
+// Every wavefront is an independent worker with its own LDS tile.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_propagate(PropArgs a)
+__global__ __launch_bounds__(kPropWaves * kWave) void k_propagate(PropArgs a)
 {
     __shared__ long long s_acc[kPropWaves][kTileMax];
-    __shared__ int32_t s_rows[kWave];
-    __shared__ int32_t s_nrows;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x >> 6;
     const int64_t t = a.st->t_prop;
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
     const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
     const Item *q = a.queue + (int64_t)prev * a.qcap;
+    const uint32_t nw = gridDim.x * kPropWaves;
+    long long *acc = s_acc[wid];
 
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    for (uint32_t it = blockIdx.x * kPropWaves + wid; it < n; it += nw) {
         const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
+        const int32_t word0 = __builtin_amdgcn_readfirstlane(q[it].row);
         const int32_t tile = __builtin_amdgcn_readfirstlane(q[it].k0);
         const int32_t slot = __builtin_amdgcn_readfirstlane(q[it].k1);
+        const uint64_t bits0 = uniform_u64(q[it].bits);
         const Proj &P = a.projs[proj];
-        if (slot >= P.pre_words || tile >= P.n_tiles) continue;   // malformed item
+        if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) continue;   // malformed item
         // the item of the first slot of each group processes the whole group
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         const uint32_t gw = group_words(na, a.scnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
@@ -244,7 +248,6 @@ __global__ __launch_bounds__(256) void k_propagate(PropArgs a)
         const int32_t tw = P.tile_w;
         const int32_t c0 = tile * tw;
         const Seg &pre = a.segs[P.pre_seg];
-        long long *acc = s_acc[wid];
         for (int i = lane; i < tw; i += kWave) acc[i] = 0;
         const double s = (double)a.gscale[P.inst] * kFixOne;
         const int32_t *col = a.col_pool + P.syn_base;
@@ -253,21 +256,15 @@ __global__ __launch_bounds__(256) void k_propagate(PropArgs a)
         const int32_t *tp = a.tp_pool + (P.tp_base < 0 ? 0 : P.tp_base);
         const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + pre.base / kWave + slot;
         for (uint32_t wi = 0; wi < nwords; ++wi) {
-            const int32_t word = wl[wi];
-            // stage the spiking rows of this word in LDS (ascending order)
-            __syncthreads();
-            if (wid == 0) {
-                const uint64_t bits = a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word];
-                const bool on = (bits >> lane) & 1ull;
-                const uint32_t below =
-                    __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
-                if (on) s_rows[below] = word * kWave + lane;
-                if (lane == 0) s_nrows = __popcll(bits);
+            int32_t word = word0;
+            uint64_t bits = bits0;
+            if (wi > 0) {
+                word = __builtin_amdgcn_readfirstlane(wl[wi]);
+                bits = uniform_u64(a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word]);
             }
-            __syncthreads();
-            const int nrows = s_nrows;
-            for (int r = wid; r < nrows; r += kPropWaves) {
-                const int32_t i = s_rows[r];
+            while (bits) {
+                const int32_t i = word * kWave + __builtin_ctzll(bits);
+                bits &= bits - 1;
                 int32_t k0, k1;
                 if (P.tp_base < 0) {
                     k0 = rp[i];
@@ -303,18 +300,11 @@ __global__ __launch_bounds__(256) void k_propagate(PropArgs a)
                 }
             }
         }
-        __syncthreads();
         int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
-        for (int i = threadIdx.x; i < tw; i += blockDim.x) {
-            long long v = s_acc[0][i];
-#pragma unroll
-            for (int u = 1; u < kPropWaves; ++u) v += s_acc[u][i];
-            out[i] = v;
-        }
-        __syncthreads();
+        for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
     }
     if (blockIdx.x == 0) {
-        // active-word counts of the slot the next neuron update fills
+        // active-word and spike counts of the slot the next neuron update fills
         for (int i = threadIdx.x; i < a.n_segs; i += blockDim.x) {
             a.awcnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
             a.scnt[(int64_t)(t & 1) * a.n_segs + i] = 0;

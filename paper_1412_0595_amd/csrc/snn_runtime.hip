@@ -1104,7 +1104,8 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
             awl[w0 + slot] = (int32_t)w;
             spk[g] += (uint32_t)__builtin_popcountll(all[w0 + w]);
             for (int o = 0; o < G.n_out; ++o)
-                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl) items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot});
+                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl)
+                    items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot, all[w0 + w], 0});
         }
     }
     if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
@@ -1127,7 +1128,7 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
             for (int o = 0; o < S.n_ltp; ++o) {
                 const HostProj &H = net->hprojs[S.ltp_proj[o]];
                 for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
-                    keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1])});
+                    keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1]), 0, 0});
             }
         }
         if ((int64_t)keep.size() > net->lcap) return fail(SNN_ERANGE, "too many work items");
