@@ -57,6 +57,7 @@ struct Seg {
     double in_erev[kMaxIn];
     double in_decay[kMaxIn];
     int64_t in_P[kMaxIn];
+    int64_t in_F[kMaxIn];
     int32_t in_tw[kMaxIn];
     int32_t in_preseg[kMaxIn];
     int32_t in_prewords[kMaxIn];
@@ -92,7 +93,8 @@ struct Proj {
     // (row-local CSR offsets of the first column >= tile * tile_w)
     int32_t tile_w, n_tiles;
     int64_t tp_base;    // -1: one tile, the row pointers bound it
-    int64_t P_base;     // partial pool offset: [tile][active-word slot][tile_w] int64
+    int64_t P_base;     // partial pool offset: [tile][group][tile_w] int64
+    int64_t F_base;     // partial flag offset: [tile][group] bytes (1: a partial tile was written)
     int32_t pre_words;  // spike words of the pre population (ceil(n_pre / 64))
     int32_t pad2_;
     // STDP
@@ -153,6 +155,7 @@ struct NeuronArgs {
     double hs;               // dt / substeps
     StepState *st;
     const int64_t *partial;  // delivered partial tiles of the previous step
+    const uint8_t *pflag;    // which groups wrote a partial tile
     uint32_t *awcnt;         // [2][n_segs]  active spike words
     uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
@@ -170,6 +173,8 @@ struct PropArgs {
     float *w_pool;
     const float *gscale;     // per instance
     int64_t *partial;
+    uint8_t *pflag;
+    int64_t *G;              // sparse items add here directly
     const uint64_t *bits;    // 2 slots of n_waves spike words
     int64_t n_waves;
     const float *trace;

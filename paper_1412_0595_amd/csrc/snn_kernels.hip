@@ -81,15 +81,17 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                         // one partial tile per group of active words, stored
                         // contiguously by group index
                         const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (j - tile * tw);
+                        const uint8_t *fl = a.pflag + S.in_F[q] + (int64_t)tile * S.in_prewords[q];
                         uint32_t u = 0;
                         for (; u + 16 <= ng; u += 16) {
                             int64_t v[16];
 #pragma unroll
-                            for (int k = 0; k < 16; ++k) v[k] = pp[(int64_t)(u + k) * tw];
+                            for (int k = 0; k < 16; ++k) v[k] = fl[u + k] ? pp[(int64_t)(u + k) * tw] : 0;
 #pragma unroll
                             for (int k = 0; k < 16; ++k) acc += v[k];
                         }
-                        for (; u < ng; ++u) acc += pp[(int64_t)u * tw];
+                        for (; u < ng; ++u)
+                            if (fl[u]) acc += pp[(int64_t)u * tw];
                         g[q] = acc;
                     }
                 }
@@ -217,8 +219,32 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 
 // ---------------------------------------------------------------------------
 // CSR propagation (+ depression on plastic rows), tiled by post neuron.
-// Every wavefront is an independent worker with its own LDS tile.
+// Every wavefront is an independent worker with its own LDS tile.  A sparse
+// item (few synapses for the tile width) adds its synapses to G with global
+// atomics instead; its group's flag tells the neuron update that no partial
+// tile was written.
 // ---------------------------------------------------------------------------
+constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
+
+// Walk one row slice into the wavefront's LDS tile (8 loads in flight per lane).
+__device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col, const float *w, int32_t k0,
+                                              int32_t k1, int32_t c0, double s, int lane)
+{
+    int32_t k = k0 + lane;
+    for (; k + 7 * kWave < k1; k += 8 * kWave) {
+        int32_t c[8];
+        float g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c[u] = col[k + u * kWave];
+            g[u] = w[k + u * kWave];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
+    }
+    for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
+}
+
 __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate(PropArgs a)
 {
     __shared__ long long s_acc[kPropWaves][kTileMax];
@@ -247,48 +273,68 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate(PropArgs a)
         const uint32_t nwords = min(gw, na - (uint32_t)slot);
         const int32_t tw = P.tile_w;
         const int32_t c0 = tile * tw;
-        const Seg &pre = a.segs[P.pre_seg];
-        for (int i = lane; i < tw; i += kWave) acc[i] = 0;
         const double s = (double)a.gscale[P.inst] * kFixOne;
         const int32_t *col = a.col_pool + P.syn_base;
         float *w = a.w_pool + P.syn_base;
         const int32_t *rp = a.rp_pool + P.rp_base;
         const int32_t *tp = a.tp_pool + (P.tp_base < 0 ? 0 : P.tp_base);
+        const int64_t stride = (int64_t)P.n_tiles + 1;
+        // bounds of the first word's rows, one lane per spiking row
+        int32_t b0 = 0, b1 = 0;
+        if ((bits0 >> lane) & 1ull) {
+            const int32_t i = word0 * kWave + lane;
+            if (P.tp_base < 0) {
+                b0 = rp[i];
+                b1 = rp[i + 1];
+            } else {
+                b0 = tp[(int64_t)i * stride + tile];
+                b1 = tp[(int64_t)i * stride + tile + 1];
+            }
+        }
+        uint8_t *flag = a.pflag + P.F_base + (int64_t)tile * P.pre_words + group;
+        if (nwords == 1 && !P.stdp) {
+            int32_t ev = b1 - b0;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) ev += __shfl_xor(ev, d, kWave);
+            if (ev * kSparseRatio < tw) {
+                // sparse: straight into G with atomics
+                unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
+                for (uint64_t bits = bits0; bits;) {
+                    const int r = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
+                    for (int32_t k = k0 + lane; k < k1; k += kWave) atomicAdd(G + col[k], (unsigned long long)fix_increment(s, w[k]));
+                }
+                if (lane == 0) *flag = 0;
+                continue;
+            }
+        }
+        for (int i = lane; i < tw; i += kWave) acc[i] = 0;
+        const Seg &pre = a.segs[P.pre_seg];
         const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + pre.base / kWave + slot;
         for (uint32_t wi = 0; wi < nwords; ++wi) {
-            int32_t word = word0;
             uint64_t bits = bits0;
             if (wi > 0) {
-                word = __builtin_amdgcn_readfirstlane(wl[wi]);
+                const int32_t word = __builtin_amdgcn_readfirstlane(wl[wi]);
                 bits = uniform_u64(a.bits[(int64_t)prev * a.n_waves + pre.base / kWave + word]);
+                b0 = b1 = 0;
+                if ((bits >> lane) & 1ull) {
+                    const int32_t i = word * kWave + lane;
+                    if (P.tp_base < 0) {
+                        b0 = rp[i];
+                        b1 = rp[i + 1];
+                    } else {
+                        b0 = tp[(int64_t)i * stride + tile];
+                        b1 = tp[(int64_t)i * stride + tile + 1];
+                    }
+                }
             }
             while (bits) {
-                const int32_t i = word * kWave + __builtin_ctzll(bits);
+                const int r = __builtin_ctzll(bits);
                 bits &= bits - 1;
-                int32_t k0, k1;
-                if (P.tp_base < 0) {
-                    k0 = rp[i];
-                    k1 = rp[i + 1];
-                } else {
-                    k0 = tp[(int64_t)i * (P.n_tiles + 1) + tile];
-                    k1 = tp[(int64_t)i * (P.n_tiles + 1) + tile + 1];
-                }
-                k0 = __builtin_amdgcn_readfirstlane(k0);
-                k1 = __builtin_amdgcn_readfirstlane(k1);
+                const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
                 if (!P.stdp) {
-                    int32_t k = k0 + lane;
-                    for (; k + 3 * kWave < k1; k += 4 * kWave) {
-                        int32_t c[4];
-                        float g[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            c[u] = col[k + u * kWave];
-                            g[u] = w[k + u * kWave];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
-                    }
-                    for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
+                    slice_to_tile(acc, col, w, k0, k1, c0, s, lane);
                 } else {
                     const float *y = a.trace + P.y_base;
                     for (int32_t k = k0 + lane; k < k1; k += kWave) {
@@ -302,6 +348,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate(PropArgs a)
         }
         int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
         for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
+        if (lane == 0) *flag = 1;
     }
     if (blockIdx.x == 0) {
         // active-word and spike counts of the slot the next neuron update fills

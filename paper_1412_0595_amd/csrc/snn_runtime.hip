@@ -120,6 +120,7 @@ struct snn_net {
     int32_t *d_wave_seg;
     int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos, *d_tp;
     int64_t *d_partial;
+    uint8_t *d_pflag;
     uint32_t *awcnt;     // arena: [2][n_segs]
     uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
@@ -258,6 +259,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.hs = net->dt / net->substeps;
     a.st = net->st;
     a.partial = net->d_partial;
+    a.pflag = net->d_pflag;
     a.awcnt = net->awcnt;
     a.scnt = net->scnt;
     a.awl = net->awl;
@@ -278,6 +280,8 @@ PropArgs prop_args(snn_net *net)
     p.w_pool = net->d_w;
     p.gscale = net->d_gscale;
     p.partial = net->d_partial;
+    p.pflag = net->d_pflag;
+    p.G = net->G;
     p.bits = net->bits;
     p.n_waves = net->n_waves;
     p.trace = net->trace;
@@ -570,7 +574,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
 
     // ---- layout: segments, projections, pools
     int64_t base = 0, rp_total = 0, syn_total = 0, G_total = 0, tr_total = 0, cp_total = 0, csc_total = 0;
-    int64_t P_total = 0, tp_total = 0;
+    int64_t P_total = 0, tp_total = 0, F_total = 0;
     net->seg_of.resize(net->n_inst);
     net->proj_of.resize(net->n_inst);
     net->gscale.resize(net->n_inst);
@@ -623,6 +627,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
             P.pre_words = (int32_t)(align_up(pre.n, kWave) / kWave);
             P.P_base = P_total;
             P_total += (int64_t)P.n_tiles * P.pre_words * P.tile_w;
+            P.F_base = F_total;
+            F_total += (int64_t)P.n_tiles * P.pre_words;
             P.tp_base = -1;
             if (P.n_tiles > 1) {
                 P.tp_base = tp_total;
@@ -630,6 +636,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
             }
             const double decay = std::exp(-net->dt / (double)Q.tau_ms);
             post.in_P[post.n_in] = P.P_base;
+            post.in_F[post.n_in] = P.F_base;
             post.in_tw[post.n_in] = P.tile_w;
             post.in_preseg[post.n_in] = P.pre_seg;
             post.in_prewords[post.n_in] = P.pre_words;
@@ -758,8 +765,9 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->d_gscale = (float *)dev_alloc(net, 4 * net->n_inst);
     net->d_tp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(tp_total, 1));
     net->d_partial = (int64_t *)dev_alloc(net, 8 * std::max<int64_t>(P_total, 1));
+    net->d_pflag = (uint8_t *)dev_alloc(net, std::max<int64_t>(F_total, 1));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
-        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial)
+        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
