@@ -85,9 +85,13 @@ __device__ __forceinline__ HHRates hh_rates(double v)
 {
     HHRates r;
     r.am = 1.28 * xexpm1_ratio((-52.0 - v) * 0.25);
-    r.bm = 1.4 * xexpm1_ratio((v + 25.0) * 0.2);
+    // beta_m and beta_h share y = (V + 25)/5: with E = e^y - 1,
+    // beta_m = 1.4 y / E and beta_h = 4 / (e^-y + 1) = 4 (1 + E) / (2 + E)
+    const double y = (v + 25.0) * 0.2;
+    const double em1 = expm1(y);
+    r.bm = y == 0.0 ? 1.4 : 1.4 * (y / em1);
+    r.bh = em1 < 1e300 ? 4.0 * (1.0 + em1) / (2.0 + em1) : 4.0;   // E -> inf: the limit 4
     r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
-    r.bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
     r.an = 0.16 * xexpm1_ratio((-50.0 - v) * 0.2);
     r.bn = 0.5 * exp((-55.0 - v) * 0.025);
     return r;
