@@ -190,8 +190,8 @@ def sweep(args):
             net.set_last_spikes(b, 2, np.zeros(inst["pops"][2]["n"], np.uint8))
             ev += int(deg[b][0].sum() + deg[b][1][fb.astype(bool)].sum())
             rows += n_a + int(fb.sum())
-        for L in (dict(prop_blocks=1024, prop_block=256), dict(prop_blocks=2048, prop_block=256),
-                  dict(prop_blocks=4096, prop_block=256)):
+        for L in (dict(mode=0, prop_blocks=1024, prop_block=256), dict(mode=0, prop_blocks=4096, prop_block=256),
+                  dict(mode=1, prop_blocks=1024), dict(mode=1, prop_blocks=2048), dict(mode=1, prop_blocks=4096)):
             net.set_launch(**L)
             launches = 20 if ev > 1e7 else 200
             ms = net.time_kernel(0, launches)

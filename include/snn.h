@@ -145,12 +145,17 @@ typedef struct {
     const char *tune_cache;
 } snn_config;
 
-/* Launch shape of the step kernels (see snn_get_launch). */
+/* Launch shape of the step kernels (see snn_get_launch).  Every choice gives
+ * bit-identical results (conductances are integer multiples of 2^-40 uS, so
+ * the order of deliveries does not matter); they differ only in speed. */
 typedef struct {
     int32_t neuron_block;   /* threads per block of the neuron update: 64..1024, multiple of 64 */
     int32_t prop_blocks;    /* blocks of the propagation kernel (persistent grid) */
-    int32_t prop_block;     /* threads per block of the propagation kernel */
+    int32_t prop_block;     /* threads per block of the row-mode propagation kernel */
     int32_t chunk;          /* synapses per work item of a row or column walk, multiple of 64 */
+    int32_t mode;           /* delivery: 0 rows (a wavefront per row chunk, atomics into G;
+                               sparse activity), 1 tiles (a wavefront per post tile and group of
+                               active spike words, LDS accumulation; dense activity) */
 } snn_launch;
 
 /* Fill p[0..6] with the Traub-Miles parameters (7.15 uS, 50 mV, 1.43 uS,

@@ -41,6 +41,12 @@ constexpr double kFixInv = 1.0 / 1099511627776.0;    // 2^-40
 
 enum { kPoisson = 0, kHH = 1 };
 
+// Delivery strategies (bitwise the same result; chosen by measurement):
+// rows = a work item per chunk of a spiking row, 64-bit atomics into G;
+// tiles = a work item per (projection, post tile, group of active spike
+// words), LDS tile accumulation and partial tiles summed by the neuron update.
+enum { kModeRows = 0, kModeTiles = 1 };
+
 // One population of one instance; its neurons occupy the global ids
 // [base, base + n), base a multiple of 64, so a wavefront never spans two.
 struct Seg {
@@ -119,7 +125,8 @@ struct StepState {
 // (active-word counts, [2][n_segs]) and which ([2][n_waves], population
 // words at the population's own word offset).
 
-// A work item.  Propagation: projection `proj`, post tile k0, spike word
+// A work item.  Row mode: synapses [k0, k1) of row `row` of projection
+// `proj`.  Tile mode: projection `proj`, post tile k0, spike word
 // `row` of the pre population (64 pre neurons) with its bits, and the
 // word's slot k1 in the active list (the item of a group's first slot
 // processes the group).  Potentiation: synapses
@@ -154,6 +161,7 @@ struct NeuronArgs {
     int32_t substeps;
     double hs;               // dt / substeps
     StepState *st;
+    int32_t mode;            // kModeRows / kModeTiles
     const int64_t *partial;  // delivered partial tiles of the previous step
     const uint8_t *pflag;    // which groups wrote a partial tile
     uint32_t *awcnt;         // [2][n_segs]  active spike words
@@ -163,6 +171,7 @@ struct NeuronArgs {
 };
 
 struct PropArgs {
+    int32_t mode;
     const Proj *projs;
     const Seg *segs;
     const Item *queue;

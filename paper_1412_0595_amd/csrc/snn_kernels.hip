@@ -5,7 +5,10 @@
 //               test, wavefront ballot into the spike bitmask, and compaction
 //               (wave scan + LDS block offsets + one atomic per block) of the
 //               propagation work of the next step.
-//  k_propagate  persistent grid of independent wavefronts, one per work item =
+//  k_propagate_rows  (sparse activity) persistent grid, one wavefront per
+//               chunk of a spiking row; 64-bit atomics into G.
+//  k_propagate_tiles (dense activity) persistent grid of independent
+//               wavefronts, one per work item =
 //               (projection, post tile, group of active 64-neuron spike words
 //               of the pre population).  The wavefront walks the row slices
 //               of the group's spiking rows in the Compressed Row Storage
@@ -68,7 +71,8 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 const int prev = cur ^ 1;
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q) {
-                    if (q < S.n_in) {
+                    if (q < S.n_in && a.mode == kModeRows) g[q] = a.G[S.in_G[q] + j];
+                    if (q < S.n_in && a.mode == kModeTiles) {
                         int64_t acc = a.G[S.in_G[q] + j];
                         const int pseg = S.in_preseg[q];
                         const uint32_t words = (uint32_t)S.in_prewords[q];
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 *tp = *tp * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
             }
         }
-        if (ball != 0) {
+        if (ball != 0 && a.mode == kModeTiles) {
             // the word is active: record it, and queue one propagation item
             // per (outgoing projection, post tile) for the next step
             if (lane == 0) {
@@ -147,6 +151,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         if (ball != 0 && spike) {
             a.counts[gid] += 1;
             const uint32_t ch = (uint32_t)a.chunk;
+            if (a.mode == kModeRows) {
+                // one propagation item per chunk of each outgoing row
+                for (int o = 0; o < S.n_out; ++o) {
+                    const int32_t *rp = a.rp_pool + S.out_rp[o];
+                    const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
+                    nq += (len + ch - 1) / ch;
+                }
+            }
             for (int o = 0; o < S.n_ltp; ++o) {
                 const int32_t *cp = a.cp_pool + S.ltp_cp[o];
                 const uint32_t len = (uint32_t)(cp[j + 1] - cp[j]);
@@ -185,8 +197,20 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     }
     __syncthreads();
 
-    // propagation items of this wave: lane 0 counted them, all lanes write
-    const uint32_t wave_nq = __shfl(nq, 0, kWave);
+    if (a.mode == kModeRows && nq) {
+        const Seg &S = a.segs[sidx];
+        const int32_t ch = a.chunk;
+        int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
+        Item *qd = a.queue + (int64_t)cur * a.qcap;
+        for (int o = 0; o < S.n_out; ++o) {
+            const int32_t *rp = a.rp_pool + S.out_rp[o];
+            const int32_t k1 = rp[j + 1];
+            for (int32_t k = rp[j]; k < k1; k += ch, ++pos)
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, k1), 0, 0};
+        }
+    }
+    // tile mode: lane 0 counted the wave's items, all lanes write
+    const uint32_t wave_nq = a.mode == kModeTiles ? __shfl(nq, 0, kWave) : 0u;
     if (wave_nq) {
         const Seg &S = a.segs[sidx];
         const int64_t base = (int64_t)s_base[0] + s_woff[wid][0];
@@ -218,7 +242,47 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// CSR propagation (+ depression on plastic rows), tiled by post neuron.
+// CSR propagation, row mode: one wavefront per work item = a chunk of one
+// spiking row; 64-bit atomics add the fixed-point weights into G (+ the
+// depression of plastic rows).  Suited to sparse activity.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = a.st->t_prop;
+    const int prev = (int)((t + 1) & 1);          // slot of step t - 1
+    const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
+    const Item *q = a.queue + (int64_t)prev * a.qcap;
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    uint32_t it = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+
+    for (; it < n; it += nw) {
+        const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
+        const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
+        const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
+        const Proj &P = a.projs[proj];
+        if (k0 < 0 || k1 > P.nnz || k0 > k1) continue;   // malformed item
+        const double s = (double)a.gscale[P.inst] * kFixOne;
+        const int32_t *col = a.col_pool + P.syn_base;
+        float *w = a.w_pool + P.syn_base;
+        unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
+        if (!P.stdp) {
+            for (int32_t k = k0 + lane; k < k1; k += kWave) atomicAdd(G + col[k], (unsigned long long)fix_increment(s, w[k]));
+        } else {
+            const float *y = a.trace + P.y_base;
+            for (int32_t k = k0 + lane; k < k1; k += kWave) {
+                const int32_t c = col[k];
+                const float gv = w[k];
+                atomicAdd(G + c, (unsigned long long)fix_increment(s, gv));
+                w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->t_neuron = t;
+}
+
+// ---------------------------------------------------------------------------
+// CSR propagation (+ depression on plastic rows), tile mode: tiled by post neuron.
 // Every wavefront is an independent worker with its own LDS tile.  A sparse
 // item (few synapses for the tile width) adds its synapses to G with global
 // atomics instead; its group's flag tells the neuron update that no partial
@@ -245,7 +309,7 @@ __device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col
     for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
 }
 
-__global__ __launch_bounds__(kPropWaves * kWave) void k_propagate(PropArgs a)
+__global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs a)
 {
     __shared__ long long s_acc[kPropWaves][kTileMax];
     const int lane = threadIdx.x & (kWave - 1);
@@ -416,8 +480,10 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s)
 
 hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s)
 {
-    (void)block;    // the tiled kernel runs kPropWaves wavefronts per block
-    hipLaunchKernelGGL(k_propagate, dim3(blocks), dim3(kPropWaves * kWave), 0, s, a);
+    if (a.mode == kModeRows)
+        hipLaunchKernelGGL(k_propagate_rows, dim3(blocks), dim3(block), 0, s, a);
+    else    // the tiled kernel runs kPropWaves wavefronts per block
+        hipLaunchKernelGGL(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), 0, s, a);
     return hipGetLastError();
 }
 

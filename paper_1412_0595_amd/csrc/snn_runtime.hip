@@ -258,6 +258,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.substeps = net->substeps;
     a.hs = net->dt / net->substeps;
     a.st = net->st;
+    a.mode = net->launch.mode;
     a.partial = net->d_partial;
     a.pflag = net->d_pflag;
     a.awcnt = net->awcnt;
@@ -270,6 +271,7 @@ NeuronArgs neuron_args(snn_net *net)
 PropArgs prop_args(snn_net *net)
 {
     PropArgs p{};
+    p.mode = net->launch.mode;
     p.projs = net->d_projs;
     p.segs = net->d_segs;
     p.queue = net->queue;
@@ -565,7 +567,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->free_fn = cfg->free;
     net->alloc_ctx = cfg->alloc_ctx;
     net->raster_steps = cfg->raster_steps;
-    net->launch = snn_launch{256, 1024, 256, 256};
+    net->launch = snn_launch{256, 1024, 256, 256, kModeRows};
     auto bail = [&](int code) {
         release(net);
         delete net;
@@ -698,8 +700,11 @@ int snn_create(const snn_config *cfg, snn_net **out)
 
     // work-queue capacity: every spike word active at once (one item per
     // projection, post tile and pre word); potentiation with the smallest chunk
-    int64_t qcap = 0, lcap = 0;
-    for (const Proj &P : net->projs) qcap += (int64_t)P.n_tiles * P.pre_words;
+    int64_t qcap_tiles = 0, qcap_rows = 0, lcap = 0;
+    for (const Proj &P : net->projs) qcap_tiles += (int64_t)P.n_tiles * P.pre_words;
+    for (const HostProj &H : net->hprojs)
+        for (int32_t i = 0; i < H.n_pre; ++i) qcap_rows += (H.row_ptr[i + 1] - H.row_ptr[i] + kMinChunk - 1) / kMinChunk;
+    const int64_t qcap = std::max(qcap_tiles, qcap_rows);
     // column lengths of plastic projections
     std::vector<std::vector<int32_t>> colptrs(net->projs.size());
     for (int b = 0, gq = 0; b < net->n_inst; ++b) {
@@ -1076,10 +1081,83 @@ int snn_get_last_spikes(snn_net *net, int32_t inst, int32_t pop, uint8_t *out)
     return SNN_OK;
 }
 
-// Replace S(t-1) of one population: rewrite its bitmask words, rebuild the
-// active-word lists and the propagation items of the slot the next step
-// consumes (from the bitmasks of every population), and the potentiation
-// items of this population's columns.
+// Rebuild the propagation work of the pending step from the spike bitmasks
+// of the slot it consumes, in the current delivery mode (rows: chunk items
+// per spiking row; tiles: active-word lists, spike counts and one item per
+// (projection, post tile, active word)); with ltp_seg >= 0 also the
+// potentiation items of that population's columns.
+static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
+{
+    int rc;
+    const int slot = (int)((net->t + 1) & 1);
+    StepState st;
+    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
+    std::vector<uint64_t> all(net->n_waves);
+    if ((rc = d2h(net, all.data(), net->bits + slot * net->n_waves, 8 * (size_t)net->n_waves))) return rc;
+    const size_t nseg = net->segs.size();
+    std::vector<uint32_t> cnt(nseg, 0), spk(nseg, 0);
+    std::vector<int32_t> awl(net->n_waves, 0);
+    std::vector<Item> items;
+    const int32_t ch = net->launch.chunk;
+    for (size_t g = 0; g < nseg; ++g) {
+        const Seg &G = net->segs[g];
+        const int64_t w0 = G.base / kWave, gw = align_up(G.n, kWave) / kWave;
+        for (int64_t w = 0; w < gw; ++w) {
+            const uint64_t bits = all[w0 + w];
+            if (!bits) continue;
+            const int32_t slot_w = (int32_t)cnt[g]++;
+            awl[w0 + slot_w] = (int32_t)w;
+            spk[g] += (uint32_t)__builtin_popcountll(bits);
+            for (int o = 0; o < G.n_out; ++o) {
+                if (net->launch.mode == kModeTiles) {
+                    for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl)
+                        items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot_w, bits, 0});
+                } else {
+                    const HostProj &H = net->hprojs[G.out_proj[o]];
+                    for (uint64_t b = bits; b; b &= b - 1) {
+                        const int32_t i = (int32_t)(w * kWave + __builtin_ctzll(b));
+                        for (int32_t k = H.row_ptr[i]; k < H.row_ptr[i + 1]; k += ch)
+                            items.push_back(Item{G.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1]), 0, 0});
+                    }
+                }
+            }
+        }
+    }
+    if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
+    if ((rc = h2d(net, net->queue + (int64_t)slot * net->qcap, items.data(), sizeof(Item) * items.size()))) return rc;
+    std::vector<uint32_t> zero(nseg, 0);
+    if ((rc = h2d(net, net->awcnt + (int64_t)slot * nseg, cnt.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->scnt + (int64_t)slot * nseg, spk.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->awcnt + (int64_t)(slot ^ 1) * nseg, zero.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->scnt + (int64_t)(slot ^ 1) * nseg, zero.data(), 4 * nseg))) return rc;
+    if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
+    st.qcnt[slot] = (uint32_t)items.size();
+    if (ltp_seg >= 0) {
+        const Seg &S = net->segs[ltp_seg];
+        const uint32_t n = st.lcnt[slot];
+        Item *dq = net->lqueue + (int64_t)slot * net->lcap;
+        std::vector<Item> old(n), keep;
+        if ((rc = d2h(net, old.data(), dq, sizeof(Item) * n))) return rc;
+        for (const Item &it : old)
+            if (net->projs[it.proj].post_seg != ltp_seg) keep.push_back(it);
+        for (int i = 0; i < S.n; ++i) {
+            if (!ltp_flags[i]) continue;
+            for (int o = 0; o < S.n_ltp; ++o) {
+                const HostProj &H = net->hprojs[S.ltp_proj[o]];
+                for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
+                    keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1]), 0, 0});
+            }
+        }
+        if ((int64_t)keep.size() > net->lcap) return fail(SNN_ERANGE, "too many work items");
+        if ((rc = h2d(net, dq, keep.data(), sizeof(Item) * keep.size()))) return rc;
+        st.lcnt[slot] = (uint32_t)keep.size();
+    }
+    return h2d(net, net->st, &st, sizeof st);
+}
+
+// Replace S(t-1) of one population: rewrite its bitmask words and rebuild
+// the pending work (propagation of every population, potentiation of this
+// population's columns).
 int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *in)
 {
     int rc = check_net(net);
@@ -1094,56 +1172,7 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
     for (int i = 0; i < S.n; ++i)
         if (in[i]) words[i / kWave] |= (uint64_t)1 << (i % kWave);
     if ((rc = h2d(net, net->bits + slot * net->n_waves + S.base / kWave, words.data(), 8 * (size_t)nw))) return rc;
-    StepState st;
-    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
-    // propagation: every active word of every population, all projections and tiles
-    std::vector<uint64_t> all(net->n_waves);
-    if ((rc = d2h(net, all.data(), net->bits + slot * net->n_waves, 8 * (size_t)net->n_waves))) return rc;
-    const size_t nseg = net->segs.size();
-    std::vector<uint32_t> cnt(nseg, 0), spk(nseg, 0);
-    std::vector<int32_t> awl(net->n_waves, 0);
-    std::vector<Item> items;
-    for (size_t g = 0; g < nseg; ++g) {
-        const Seg &G = net->segs[g];
-        const int64_t w0 = G.base / kWave, gw = align_up(G.n, kWave) / kWave;
-        for (int64_t w = 0; w < gw; ++w) {
-            if (!all[w0 + w]) continue;
-            const int32_t slot = (int32_t)cnt[g]++;
-            awl[w0 + slot] = (int32_t)w;
-            spk[g] += (uint32_t)__builtin_popcountll(all[w0 + w]);
-            for (int o = 0; o < G.n_out; ++o)
-                for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl)
-                    items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot, all[w0 + w], 0});
-        }
-    }
-    if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
-    if ((rc = h2d(net, net->queue + (int64_t)slot * net->qcap, items.data(), sizeof(Item) * items.size()))) return rc;
-    if ((rc = h2d(net, net->awcnt + (int64_t)slot * nseg, cnt.data(), 4 * nseg))) return rc;
-    if ((rc = h2d(net, net->scnt + (int64_t)slot * nseg, spk.data(), 4 * nseg))) return rc;
-    if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
-    st.qcnt[slot] = (uint32_t)items.size();
-    // potentiation: replace this population's column items
-    {
-        const int32_t ch = net->launch.chunk;
-        const uint32_t n = st.lcnt[slot];
-        Item *dq = net->lqueue + (int64_t)slot * net->lcap;
-        std::vector<Item> old(n), keep;
-        if ((rc = d2h(net, old.data(), dq, sizeof(Item) * n))) return rc;
-        for (const Item &it : old)
-            if (net->projs[it.proj].post_seg != s) keep.push_back(it);
-        for (int i = 0; i < S.n; ++i) {
-            if (!in[i]) continue;
-            for (int o = 0; o < S.n_ltp; ++o) {
-                const HostProj &H = net->hprojs[S.ltp_proj[o]];
-                for (int32_t k = H.col_ptr[i]; k < H.col_ptr[i + 1]; k += ch)
-                    keep.push_back(Item{S.ltp_proj[o], i, k, std::min(k + ch, H.col_ptr[i + 1]), 0, 0});
-            }
-        }
-        if ((int64_t)keep.size() > net->lcap) return fail(SNN_ERANGE, "too many work items");
-        if ((rc = h2d(net, dq, keep.data(), sizeof(Item) * keep.size()))) return rc;
-        st.lcnt[slot] = (uint32_t)keep.size();
-    }
-    return h2d(net, net->st, &st, sizeof st);
+    return rebuild_pending(net, s, in);
 }
 
 int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out)
@@ -1236,12 +1265,11 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
     if (in->prop_blocks < 1 || in->prop_blocks > 65536) return fail(SNN_EINVAL, "prop_blocks must be in [1, 65536]");
     if (in->chunk < kMinChunk || in->chunk % kWave || in->chunk > (1 << 20))
         return fail(SNN_EINVAL, "chunk must be a multiple of 64 in [64, 2^20]");
-    if (in->chunk != net->launch.chunk) {
-        // the pending items of the next step were cut with the old chunk;
-        // they stay valid (any chunk >= 64 fits the queue), so only new
-        // items use the new length
-    }
+    if (in->mode != kModeRows && in->mode != kModeTiles) return fail(SNN_EINVAL, "mode must be 0 (rows) or 1 (tiles)");
+    const bool remake = in->mode != net->launch.mode;
     net->launch = *in;
+    // the pending work of the next step was laid out for the old mode
+    if (remake && (rc = rebuild_pending(net, -1, nullptr))) return rc;
     if (net->graph_exec) {
         (void)hipGraphExecDestroy(net->graph_exec);
         net->graph_exec = nullptr;
@@ -1523,8 +1551,8 @@ static bool cache_lookup(const char *path, const std::string &sig, snn_launch *o
     while (fgets(line, sizeof line, f)) {
         char key[300];
         snn_launch L{};
-        if (sscanf(line, " \"%299[^\"]\" : [ %d , %d , %d , %d ]", key, &L.neuron_block, &L.prop_blocks,
-                   &L.prop_block, &L.chunk) == 5 && sig == key) {
+        if (sscanf(line, " \"%299[^\"]\" : [ %d , %d , %d , %d , %d ]", key, &L.neuron_block, &L.prop_blocks,
+                   &L.prop_block, &L.chunk, &L.mode) == 6 && sig == key) {
             *out = L;
             found = true;
         }
@@ -1549,7 +1577,8 @@ static void cache_store(const char *path, const std::string &sig, const snn_laun
         fclose(f);
     }
     char buf[512];
-    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d]", sig.c_str(), L.neuron_block, L.prop_blocks, L.prop_block, L.chunk);
+    snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d, %d]", sig.c_str(), L.neuron_block, L.prop_blocks, L.prop_block,
+             L.chunk, L.mode);
     keep.push_back(buf);
     if (FILE *f = fopen(path, "w")) {
         fprintf(f, "{\n");
@@ -1569,18 +1598,20 @@ int snn_autotune_internal(snn_net *net, const char *cache)
     int rc = snn_time_steps(net, steps, &best_ms);   // also warms up
     if (rc) return rc;
     if ((rc = snn_time_steps(net, steps, &best_ms))) return rc;
+    const int md[] = {kModeRows, kModeTiles};
     const int nb[] = {64, 128, 256, 512, 1024};
     const int pb[] = {256, 512, 1024, 2048, 4096, 8192};
     const int ck[] = {128, 256, 512, 1024, 2048};
-    for (int dim = 0; dim < 3; ++dim) {
-        const int *vals = dim == 0 ? nb : dim == 1 ? pb : ck;
-        const int nv = dim == 0 ? 5 : dim == 1 ? 6 : 5;
+    for (int dim = 0; dim < 4; ++dim) {
+        const int *vals = dim == 0 ? md : dim == 1 ? nb : dim == 2 ? pb : ck;
+        const int nv = dim == 0 ? 2 : dim == 1 ? 5 : dim == 2 ? 6 : 5;
         snn_launch cur_best = best;
         for (int k = 0; k < nv; ++k) {
             snn_launch L = best;
-            if (dim == 0) L.neuron_block = vals[k];
-            if (dim == 1) L.prop_blocks = vals[k];
-            if (dim == 2) L.chunk = vals[k];
+            if (dim == 0) L.mode = vals[k];
+            if (dim == 1) L.neuron_block = vals[k];
+            if (dim == 2) L.prop_blocks = vals[k];
+            if (dim == 3) L.chunk = vals[k];
             if ((rc = snn_set_launch(net, &L))) return rc;
             double ms = 0.0;
             if ((rc = snn_time_steps(net, steps, &ms))) return rc;

@@ -61,7 +61,7 @@ class Config(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("neuron_block", C.c_int32), ("prop_blocks", C.c_int32), ("prop_block", C.c_int32),
-                ("chunk", C.c_int32)]
+                ("chunk", C.c_int32), ("mode", C.c_int32)]
 
 
 class SNNError(RuntimeError):
@@ -415,7 +415,8 @@ class Network:
     def launch(self):
         L = Launch()
         _check(load().snn_get_launch(self.h, C.byref(L)))
-        return dict(neuron_block=L.neuron_block, prop_blocks=L.prop_blocks, prop_block=L.prop_block, chunk=L.chunk)
+        return dict(neuron_block=L.neuron_block, prop_blocks=L.prop_blocks, prop_block=L.prop_block, chunk=L.chunk,
+                    mode=L.mode)
 
     def set_launch(self, **kw):
         cur = self.launch

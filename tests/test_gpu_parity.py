@@ -254,8 +254,10 @@ def test_launch_shape_does_not_change_results(snn):
     spec = netgen.make_config(1, scale=0.5)
     ref = snn.Network(spec)
     ref.step(200)
-    for shape in [dict(neuron_block=64, prop_blocks=7, prop_block=64, chunk=64),
-                  dict(neuron_block=1024, prop_blocks=4096, prop_block=1024, chunk=2048)]:
+    for shape in [dict(neuron_block=64, prop_blocks=7, prop_block=64, chunk=64, mode=0),
+                  dict(neuron_block=1024, prop_blocks=4096, prop_block=1024, chunk=2048, mode=0),
+                  dict(neuron_block=128, prop_blocks=3, prop_block=256, chunk=256, mode=1),
+                  dict(neuron_block=256, prop_blocks=2048, prop_block=256, chunk=256, mode=1)]:
         n = snn.Network(spec)
         n.set_launch(**shape)
         n.step(200)
@@ -266,6 +268,35 @@ def test_launch_shape_does_not_change_results(snn):
             assert np.array_equal(n.conductance(0, q), ref.conductance(0, q))
         n.close()
     ref.close()
+
+
+@pytest.mark.parametrize("workload,scale", [(1, 0.5), (2, 0.25), (3, 0.05)])
+def test_delivery_modes_agree_bitwise_with_switches(snn, workload, scale):
+    """Row-mode and tile-mode delivery, and switching between them while
+    spikes are pending, give the same bits (fixed-point conductances); plastic
+    weights included."""
+    say(f"case: delivery modes, workload {workload} at scale {scale}")
+    spec = netgen.make_config(workload, scale=scale)
+    a = snn.Network(spec)
+    b = snn.Network(spec)
+    b.set_launch(mode=1)
+    a.step(150)
+    b.step(150)
+    a.set_launch(mode=1)      # switch with work pending
+    b.set_launch(mode=0)
+    a.step(130)
+    b.step(130)
+    inst = spec["instances"][0]
+    for p in range(len(inst["pops"])):
+        assert np.array_equal(a.spikes(0, p), b.spikes(0, p))
+        if inst["pops"][p]["kind"] == "hh":
+            for var in range(4):
+                assert np.array_equal(a.state(0, p, var), b.state(0, p, var))
+    for q in range(len(inst["projs"])):
+        assert np.array_equal(a.conductance(0, q), b.conductance(0, q))
+        assert np.array_equal(a.weights(0, q), b.weights(0, q))
+    a.close()
+    b.close()
 
 
 def test_vbar_accumulates_post_step_voltage(snn):
