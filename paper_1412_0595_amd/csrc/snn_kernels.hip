@@ -267,7 +267,19 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
         float *w = a.w_pool + P.syn_base;
         unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
         if (!P.stdp) {
-            for (int32_t k = k0 + lane; k < k1; k += kWave) atomicAdd(G + col[k], (unsigned long long)fix_increment(s, w[k]));
+            for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
+                int32_t c[8];
+                float g[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int32_t k = kb + u * kWave + lane;
+                    c[u] = k < k1 ? col[k] : -1;
+                    g[u] = k < k1 ? w[k] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (c[u] >= 0) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+            }
         } else {
             const float *y = a.trace + P.y_base;
             for (int32_t k = k0 + lane; k < k1; k += kWave) {
@@ -290,23 +302,26 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 // ---------------------------------------------------------------------------
 constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
 
-// Walk one row slice into the wavefront's LDS tile (8 loads in flight per lane).
+// Walk one row slice into the wavefront's LDS tile: batches of up to 8
+// entries per lane whose loads are all issued before the first add (the
+// tail batch is predicated), so a slice costs one memory round trip per
+// 512 synapses rather than per 64.
 __device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col, const float *w, int32_t k0,
                                               int32_t k1, int32_t c0, double s, int lane)
 {
-    int32_t k = k0 + lane;
-    for (; k + 7 * kWave < k1; k += 8 * kWave) {
+    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
         int32_t c[8];
         float g[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            c[u] = col[k + u * kWave];
-            g[u] = w[k + u * kWave];
+            const int32_t k = kb + u * kWave + lane;
+            c[u] = k < k1 ? col[k] : -1;
+            g[u] = k < k1 ? w[k] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[c[u] - c0] += fix_increment(s, g[u]);
+        for (int u = 0; u < 8; ++u)
+            if (c[u] >= 0) acc[c[u] - c0] += fix_increment(s, g[u]);
     }
-    for (; k < k1; k += kWave) acc[col[k] - c0] += fix_increment(s, w[k]);
 }
 
 __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs a)
@@ -367,7 +382,19 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                     const int r = __builtin_ctzll(bits);
                     bits &= bits - 1;
                     const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
-                    for (int32_t k = k0 + lane; k < k1; k += kWave) atomicAdd(G + col[k], (unsigned long long)fix_increment(s, w[k]));
+                    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
+                        int32_t c[8];
+                        float g[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int32_t k = kb + u * kWave + lane;
+                            c[u] = k < k1 ? col[k] : -1;
+                            g[u] = k < k1 ? w[k] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (c[u] >= 0) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+                    }
                 }
                 if (lane == 0) *flag = 0;
                 continue;
