@@ -8,8 +8,8 @@ the neuron update and spike compaction.
 
 Prints ONE JSON line: value = Traub-Miles neuron-steps per second over the
 timed steps (inputs already resident in HBM), plus synaptic events per
-second, the roofline of the dominant kernel (its per-launch time measured
-with hipEvents around each launch) and the FP64 oracle timed on a bounded
+second, the roofline of the dominant kernel (its per-launch duration from
+event-stamped launches over live steps after the timed region) and the FP64 oracle timed on a bounded
 sample on the host cores.
 """
 import argparse
@@ -133,7 +133,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=500)
+    ap.add_argument("--profile-steps", type=int, default=2000)
     ap.add_argument("--sweep", action="store_true",
                     help="forced-activity sweep of the propagation kernel instead of the step benchmark")
     ap.add_argument("--sweep-workload", type=int, default=3)
@@ -263,34 +263,43 @@ def main():
     neuron_steps = n_hh * args.steps / sec
     events_s = events / sec
 
-    # Per-kernel launch duration: one hipEvent pair around `profile_steps`
-    # back-to-back launches of that kernel alone on the final state (state
-    # restored afterwards).  The propagation launches all walk the pending
-    # spikes of the last step; the neuron launches update every neuron.
+    # Per-kernel launch duration: `profile_steps` further live steps, each
+    # kernel launched directly with a start/stop hipEvent pair that the HIP
+    # runtime stamps with that dispatch's own begin and end.  The algorithmic
+    # bytes of those launches are counted exactly: the propagation launches
+    # deliver the spikes pending at the start plus those emitted during the
+    # window, less those still pending at its end.
+    pend0 = [[net.last_spikes(b, p).astype(np.int64) for p in range(len(spec["instances"][b]["pops"]))]
+             for b in range(len(spec["instances"]))]
+    ca = spike_totals(net, spec)
+    prof = net.profile_steps(args.profile_steps)
+    cb = spike_totals(net, spec)
     pend_events = 0
     pend_rows = 0
     for b in range(len(spec["instances"])):
         for p in range(len(spec["instances"][b]["pops"])):
-            f = net.last_spikes(b, p).astype(bool)
-            pend_events += int(deg[b][p][f].sum())
-            pend_rows += int(f.sum()) * sum(1 for q in spec["instances"][b]["projs"] if q["pre"] == p)
-    k_prop = net.time_kernel(0, args.profile_steps)
-    k_neur = net.time_kernel(2, args.profile_steps)
+            delivered = pend0[b][p] + (cb[b][p] - ca[b][p]) - net.last_spikes(b, p).astype(np.int64)
+            n_out = sum(1 for q in spec["instances"][b]["projs"] if q["pre"] == p)
+            pend_events += int((delivered * deg[b][p]).sum())
+            pend_rows += int(delivered.sum()) * n_out
     n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
                for inst in spec["instances"] for k in range(len(inst["pops"])))
     neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
     prop_bytes = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
     kern = {
-        "propagate": dict(ms=k_prop, bytes=prop_bytes),
-        "neuron": dict(ms=k_neur, bytes=neuron_bytes),
+        "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_bytes),
+        "neuron": dict(ms=prof["neuron"][0], n=prof["neuron"][1], bytes=neuron_bytes * prof["neuron"][1]),
     }
-    # dominant = larger share of the timed step
+    if prof["potentiate"][1]:
+        kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1], bytes=0)
+    # dominant = the larger share of kernel time over the profiled steps
     dom = max(kern, key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
     roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
-            "ms_per_launch": {k: round(v["ms"], 6) for k, v in kern.items()},
-            "bytes_per_launch": {k: int(v["bytes"]) for k, v in kern.items()}}
+            "profiled_steps": args.profile_steps,
+            "ms_per_launch": {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()},
+            "bytes_per_launch": {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}}
 
     cpu = None
     if not args.no_cpu:

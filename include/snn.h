@@ -259,6 +259,16 @@ int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms);
  * Synchronises. */
 int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_per_launch);
 
+/* Advance the network by n_steps (1..100000) steps, exactly as snn_step
+ * does, but with every kernel launched directly (no graph) together with a
+ * start/stop hipEvent pair that the runtime stamps with that dispatch's own
+ * begin and end times.  On return ms_total[k] is the summed kernel
+ * duration and launches[k] the number of launches of kernel k (0
+ * propagation, 1 potentiation, 2 neuron update) over those steps: the
+ * per-kernel average duration of a live sequence of steps.  Both arrays
+ * are caller-owned host arrays of 3 elements.  Synchronises. */
+int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *launches);
+
 /* Restore the state created by snn_create: every Traub-Miles neuron at its
  * resting point, conductances, traces, counts, Vbar sums, NaN counts and
  * spikes at zero, step counter 0.  Weights (including STDP changes) and

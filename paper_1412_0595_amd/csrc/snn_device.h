@@ -26,63 +26,11 @@ __device__ __forceinline__ uint32_t philox_first_word(uint32_t x0, uint32_t x1, 
     return x0;
 }
 
-// e^x in double precision: Cody-Waite reduction x = k ln2 + r with
-// |r| <= ln2/2 (ln2 split into a 32-bit-exact high part and a low part, as in
-// Cody & Waite, "Software Manual for the Elementary Functions", 1980), the
-// Taylor series of e^r to r^13 (truncation below 1e-17 relative), and
-// e^x = 2^k e^r.  NaN propagates; overflow gives +inf, underflow 0.
-__device__ __forceinline__ double exp_d(double x)
+// phi(x) = x / (e^x - 1) with its limit 1 at x = 0; expm1 keeps it accurate
+// near 0, and a NaN argument gives NaN.
+__device__ __forceinline__ double phi(double x)
 {
-    const double kLog2e = 1.4426950408889634074;
-    const double kLn2Hi = 6.93147180369123816490e-01;
-    const double kLn2Lo = 1.90821492927058770002e-10;
-    const double xc = x > 709.0 ? 709.0 : (x < -745.0 ? -745.0 : x);
-    const double k = rint(xc * kLog2e);
-    double r = fma(-k, kLn2Hi, xc);
-    r = fma(-k, kLn2Lo, r);
-    // sum_{n=0..13} r^n / n!
-    double p = 1.0 / 6227020800.0;               // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);            // 1/12!
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    const double e = ldexp(p, (int)k);
-    return x > 709.78 ? __builtin_inf() : (x < -745.2 ? 0.0 : e);
-}
-
-// 1 / phi(x) = (e^x - 1) / x = sum_{n>=0} x^n / (n+1)! for |x| <= ln2/2,
-// where e^x - 1 would cancel (truncation below 1e-17 relative).
-__device__ __forceinline__ double inv_phi_series(double x)
-{
-    double p = 1.0 / 6227020800.0;               // 1/13!
-    p = fma(p, x, 1.0 / 479001600.0);
-    p = fma(p, x, 1.0 / 39916800.0);
-    p = fma(p, x, 1.0 / 3628800.0);
-    p = fma(p, x, 1.0 / 362880.0);
-    p = fma(p, x, 1.0 / 40320.0);
-    p = fma(p, x, 1.0 / 5040.0);
-    p = fma(p, x, 1.0 / 720.0);
-    p = fma(p, x, 1.0 / 120.0);
-    p = fma(p, x, 1.0 / 24.0);
-    p = fma(p, x, 1.0 / 6.0);
-    p = fma(p, x, 0.5);
-    return fma(p, x, 1.0);
-}
-
-// phi(x) = x / (e^x - 1), limit 1 at x = 0, given ex = e^x.
-__device__ __forceinline__ double phi_from_exp(double x, double ex)
-{
-    if (fabs(x) <= 0.34657359027997264) return 1.0 / inv_phi_series(x);
-    return x / (ex - 1.0);
+    return x == 0.0 ? 1.0 : x / expm1(x);
 }
 
 // Wave-wide inclusive sum (64 lanes).
@@ -137,18 +85,12 @@ struct HHRates {
 __device__ __forceinline__ HHRates hh_rates(double v)
 {
     HHRates r;
-    const double xm = (-52.0 - v) * 0.25;
-    r.am = 1.28 * phi_from_exp(xm, exp_d(xm));
-    // beta_m and beta_h share y = (V + 25)/5: beta_m = 1.4 phi(y) and
-    // beta_h = 4 / (e^-y + 1) = 4 e^y / (1 + e^y)
-    const double y = (v + 25.0) * 0.2;
-    const double ey = exp_d(y);
-    r.bm = 1.4 * phi_from_exp(y, ey);
-    r.bh = !(ey >= 1e300) ? 4.0 * ey / (1.0 + ey) : 4.0;   // e^y -> inf: the limit 4
-    r.ah = 0.128 * exp_d((-48.0 - v) * (1.0 / 18.0));
-    const double xn = (-50.0 - v) * 0.2;
-    r.an = 0.16 * phi_from_exp(xn, exp_d(xn));
-    r.bn = 0.5 * exp_d((-55.0 - v) * 0.025);
+    r.am = 1.28 * phi((-52.0 - v) * 0.25);
+    r.bm = 1.4 * phi((v + 25.0) * 0.2);
+    r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
+    r.bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
+    r.an = 0.16 * phi((-50.0 - v) * 0.2);
+    r.bn = 0.5 * exp((-55.0 - v) * 0.025);
     return r;
 }
 

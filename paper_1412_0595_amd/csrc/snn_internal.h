@@ -256,9 +256,12 @@ hipError_t launch_gather_vbar(const Seg *segs, const int32_t *loss_seg, const in
                               double *vbar, hipStream_t s);
 
 // Launchers (snn_kernels.hip).
-hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s);
-hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s);
-hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s);
+hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
+hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
+hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
 hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s);
 
 }  // namespace snn

@@ -22,6 +22,7 @@
 // partial tiles of every active spike word to its conductance, and integer
 // sums are the same in any order.
 #include <algorithm>
+#include <hip/hip_ext.h>
 
 #include "snn_device.h"
 
@@ -241,6 +242,58 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     }
 }
 
+// Walk one row slice into the wavefront's LDS tile in batches of up to 8
+// entries per lane.  The loads of a batch are issued back to back at an index
+// clamped into the slice, so they are always in bounds.  Then all 8 tile
+// entries are read before any is written; the entries of one row have
+// distinct columns, so this order is exact.  A clamped duplicate reads the
+// same pre-batch value and adds the same increment as the slice's last entry,
+// so it writes the identical sum: every write is unconditional and harmless
+// in any order, and the batch has no branch.
+__device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col, const float *w, int32_t k0,
+                                              int32_t k1, int32_t c0, double s, int lane)
+{
+    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
+        int32_t c[8];
+        float g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t k = min(kb + u * kWave + lane, k1 - 1);
+            c[u] = col[k] - c0;
+            g[u] = w[k];
+        }
+        long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = acc[c[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[c[u]] = v[u] + fix_increment(s, g[u]);
+    }
+}
+
+// The same walk for delivery straight into G with 64-bit atomics.  Here a
+// duplicate must not add again, so the atomics are predicated; the empty asm
+// consumes the loaded registers so the compiler keeps all 16 loads ahead of
+// the predicated atomics (nothing waits on an atomic without a return value).
+__device__ __forceinline__ void slice_to_global(unsigned long long *G, const int32_t *col, const float *w,
+                                                int32_t k0, int32_t k1, double s, int lane)
+{
+    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
+        int32_t c[8];
+        float g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t k = min(kb + u * kWave + lane, k1 - 1);
+            c[u] = col[k];
+            g[u] = w[k];
+        }
+        asm volatile("" ::"v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]), "v"(c[7]),
+                     "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]));
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (kb + u * kWave + lane < k1) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CSR propagation, row mode: one wavefront per work item = a chunk of one
 // spiking row; 64-bit atomics add the fixed-point weights into G (+ the
@@ -267,19 +320,7 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
         float *w = a.w_pool + P.syn_base;
         unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
         if (!P.stdp) {
-            for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
-                int32_t c[8];
-                float g[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int32_t k = kb + u * kWave + lane;
-                    c[u] = k < k1 ? col[k] : -1;
-                    g[u] = k < k1 ? w[k] : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (c[u] >= 0) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
-            }
+            slice_to_global(G, col, w, k0, k1, s, lane);
         } else {
             const float *y = a.trace + P.y_base;
             for (int32_t k = k0 + lane; k < k1; k += kWave) {
@@ -301,28 +342,6 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 // tile was written.
 // ---------------------------------------------------------------------------
 constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
-
-// Walk one row slice into the wavefront's LDS tile: batches of up to 8
-// entries per lane whose loads are all issued before the first add (the
-// tail batch is predicated), so a slice costs one memory round trip per
-// 512 synapses rather than per 64.
-__device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col, const float *w, int32_t k0,
-                                              int32_t k1, int32_t c0, double s, int lane)
-{
-    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
-        int32_t c[8];
-        float g[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t k = kb + u * kWave + lane;
-            c[u] = k < k1 ? col[k] : -1;
-            g[u] = k < k1 ? w[k] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (c[u] >= 0) acc[c[u] - c0] += fix_increment(s, g[u]);
-    }
-}
 
 __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs a)
 {
@@ -382,19 +401,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                     const int r = __builtin_ctzll(bits);
                     bits &= bits - 1;
                     const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
-                    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
-                        int32_t c[8];
-                        float g[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int32_t k = kb + u * kWave + lane;
-                            c[u] = k < k1 ? col[k] : -1;
-                            g[u] = k < k1 ? w[k] : 0.0f;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 8; ++u)
-                            if (c[u] >= 0) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
-                    }
+                    slice_to_global(G, col, w, k0, k1, s, lane);
                 }
                 if (lane == 0) *flag = 0;
                 continue;
@@ -496,27 +503,37 @@ hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s)
+// With a start/stop event pair the launch goes through hipExtLaunchKernelGGL,
+// which stamps the events with that dispatch's own begin and end times.
+#define SNN_LAUNCH(kern, grid, blk, s, e0, e1, ...)                                               \
+    do {                                                                                         \
+        if (e0)                                                                                  \
+            hipExtLaunchKernelGGL(kern, grid, blk, 0, s, e0, e1, 0, __VA_ARGS__);                  \
+        else                                                                                     \
+            hipLaunchKernelGGL(kern, grid, blk, 0, s, __VA_ARGS__);                                \
+    } while (0)
+
+hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int64_t wpb = block / kWave;
     const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_neuron, dim3((unsigned)blocks), dim3(block), 0, s, a);
+    SNN_LAUNCH(k_neuron, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
     return hipGetLastError();
 }
 
-hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s)
+hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.mode == kModeRows)
-        hipLaunchKernelGGL(k_propagate_rows, dim3(blocks), dim3(block), 0, s, a);
+        SNN_LAUNCH(k_propagate_rows, dim3(blocks), dim3(block), s, e0, e1, a);
     else    // the tiled kernel runs kPropWaves wavefronts per block
-        hipLaunchKernelGGL(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), 0, s, a);
+        SNN_LAUNCH(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), s, e0, e1, a);
     return hipGetLastError();
 }
 
-hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s)
+hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_potentiate, dim3(blocks), dim3(block), 0, s, a);
+    SNN_LAUNCH(k_potentiate, dim3(blocks), dim3(block), s, e0, e1, a);
     return hipGetLastError();
 }
 

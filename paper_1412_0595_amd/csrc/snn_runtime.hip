@@ -1319,6 +1319,49 @@ int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_pe
     return SNN_OK;
 }
 
+int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *launches)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (n_steps < 1 || n_steps > 100000 || !ms_total || !launches)
+        return fail(SNN_EINVAL, "need 1 <= n_steps <= 100000 and two output arrays");
+    const int per_step = net->plastic ? 3 : 2;
+    std::vector<hipEvent_t> ev((size_t)(2 * per_step * n_steps), nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    const PropArgs p = prop_args(net);
+    const LtpArgs l = ltp_args(net);
+    const NeuronArgs a = neuron_args(net);
+    int64_t done = 0;
+    for (; done < n_steps && e == hipSuccess; ++done) {
+        hipEvent_t *E = ev.data() + 2 * per_step * done;
+        e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream, E[0], E[1]);
+        if (e == hipSuccess && net->plastic)
+            e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, net->stream, E[4], E[5]);
+        if (e == hipSuccess) e = launch_neuron(a, net->launch.neuron_block, net->stream, E[2], E[3]);
+        if (e == hipSuccess) net->t += 1;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    for (int k = 0; k < 3; ++k) ms_total[k] = 0.0, launches[k] = 0;
+    for (int64_t t = 0; t < n_steps && e == hipSuccess; ++t) {
+        hipEvent_t *E = ev.data() + 2 * per_step * t;
+        for (int k = 0; k < per_step && e == hipSuccess; ++k) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, E[2 * k], E[2 * k + 1]);
+            const int which = k == 0 ? 0 : k == 1 ? 2 : 1;
+            ms_total[which] += (double)ms;
+            launches[which] += 1;
+        }
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "profiled steps failed: %s", hipGetErrorString(e));
+    }
+    return SNN_OK;
+}
+
 int snn_reset(snn_net *net)
 {
     int rc = check_net(net);

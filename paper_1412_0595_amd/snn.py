@@ -25,7 +25,7 @@ EXPORTS = [
     "snn_get_spikes", "snn_get_raster", "snn_get_state", "snn_set_state", "snn_get_state_f64",
     "snn_set_state_f64", "snn_get_conductance", "snn_set_conductance", "snn_get_last_spikes",
     "snn_set_last_spikes", "snn_get_vbar", "snn_get_nan_counts", "snn_set_gscale", "snn_get_weights",
-    "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel",
+    "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel", "snn_profile_steps",
     "snn_last_error", "snn_reset", "snn_weight_count", "snn_weight_offset", "snn_get_weights_device",
     "snn_set_weights_device", "snn_forward_record", "snn_backward",
 ]
@@ -112,6 +112,7 @@ def load():
         "snn_set_launch": (C.c_int, [vp, vp]),
         "snn_time_steps": (C.c_int, [vp, i64, vp]),
         "snn_time_kernel": (C.c_int, [vp, i32, i64, vp]),
+        "snn_profile_steps": (C.c_int, [vp, i64, vp, vp]),
         "snn_last_error": (C.c_char_p, []),
         "snn_reset": (C.c_int, [vp]),
         "snn_weight_count": (i64, [vp]),
@@ -277,6 +278,14 @@ class Network:
         out = C.c_double()
         _check(load().snn_time_kernel(self.h, int(which), int(launches), C.byref(out)))
         return out.value
+
+    def profile_steps(self, n):
+        """Advance n steps with direct, event-stamped launches; returns
+        {kernel: (total ms, launches)} for propagate, potentiate, neuron."""
+        ms = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        _check(load().snn_profile_steps(self.h, int(n), ms, cnt))
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(("propagate", "potentiate", "neuron"))}
 
     def reset(self):
         _check(load().snn_reset(self.h))
