@@ -49,6 +49,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     uint64_t wball = 0;            // this wave's spike word
     int sidx = 0;
     int32_t j = 0;
+    uint32_t cnt = 0;              // prefetched spike count
+    int32_t ra0 = 0, ra1 = 0, rb0 = 0, rb1 = 0;   // prefetched rows of outgoing projections 0 and 1
+    float trv[kMaxTr] = {};        // prefetched traces
 
     if (gw < a.n_waves) {
         sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[gw]);
@@ -56,63 +59,88 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         const int64_t gid = gw * kWave + lane;
         j = (int32_t)(gid - S.base);
         const bool active = j < S.n;
+        // Every load of the update is issued up front and unconditionally,
+        // so that they share one memory round trip: padded arrays at gid,
+        // unpadded ones (conductances, traces, row starts) at jj, the index
+        // clamped into the population.  Lanes past the population compute on
+        // that data and store nothing.
+        const int32_t jj = active ? j : S.n - 1;
+        cnt = a.counts[gid];
+        {
+            // (used in rows mode; a missing projection reads rp_pool[0..1])
+            const int32_t *rpa = a.rp_pool + (S.n_out > 0 ? S.out_rp[0] + jj : 0);
+            const int32_t *rpb = a.rp_pool + (S.n_out > 1 ? S.out_rp[1] + jj : 0);
+            ra0 = rpa[0];
+            ra1 = rpa[1];
+            rb0 = rpb[0];
+            rb1 = rpb[1];
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxTr; ++q)
+            if (q < S.n_tr) trv[q] = a.trace[S.tr_base[q] + jj];
 
         if (S.kind == kHH) {
-            if (active) {
-                double v = pair_load(a.vh, a.vl, gid);
-                double m = pair_load(a.mh, a.ml, gid);
-                double h = pair_load(a.hh, a.hl, gid);
-                double n = pair_load(a.nh, a.nl, gid);
-                const double v0 = v;
-                // synaptic current from the start-of-step voltage, held
-                // fixed over the substeps; then the conductances decay
-                // delivered conductance: decayed G plus the partial tiles of
-                // every pre spike word that was active at t - 1
-                int64_t g[kMaxIn];
-                const int prev = cur ^ 1;
+            const double vs = S.record_vbar ? a.vsum[gid] : 0.0;
+            double v = pair_load(a.vh, a.vl, gid);
+            double m = pair_load(a.mh, a.ml, gid);
+            double h = pair_load(a.hh, a.hl, gid);
+            double n = pair_load(a.nh, a.nl, gid);
+            const double v0 = v;
+            // delivered conductance: G (rows mode), or G plus the partial
+            // tiles of every group of pre spike words active at t - 1
+            int64_t g[kMaxIn];
+            const int prev = cur ^ 1;
 #pragma unroll
-                for (int q = 0; q < kMaxIn; ++q) {
-                    if (q < S.n_in && a.mode == kModeRows) g[q] = a.G[S.in_G[q] + j];
-                    if (q < S.n_in && a.mode == kModeTiles) {
-                        int64_t acc = a.G[S.in_G[q] + j];
-                        const int pseg = S.in_preseg[q];
-                        const uint32_t words = (uint32_t)S.in_prewords[q];
-                        const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], words);
-                        const uint32_t ng = na ? (na + group_words(na, a.scnt[prev * a.n_segs + pseg], words) - 1) /
-                                                     group_words(na, a.scnt[prev * a.n_segs + pseg], words)
-                                               : 0u;
-                        const int32_t tw = S.in_tw[q];
-                        const int32_t tile = j / tw;
-                        // one partial tile per group of active words, stored
-                        // contiguously by group index
-                        const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (j - tile * tw);
-                        const uint8_t *fl = a.pflag + S.in_F[q] + (int64_t)tile * S.in_prewords[q];
-                        uint32_t u = 0;
-                        for (; u + 16 <= ng; u += 16) {
-                            int64_t v[16];
+            for (int q = 0; q < kMaxIn; ++q) {
+                if (q < S.n_in && a.mode == kModeRows) g[q] = a.G[S.in_G[q] + jj];
+                if (q < S.n_in && a.mode == kModeTiles) {
+                    int64_t acc = a.G[S.in_G[q] + jj];
+                    const int pseg = S.in_preseg[q];
+                    const uint32_t words = (uint32_t)S.in_prewords[q];
+                    const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], words);
+                    const uint32_t ng = na ? (na + group_words(na, a.scnt[prev * a.n_segs + pseg], words) - 1) /
+                                                 group_words(na, a.scnt[prev * a.n_segs + pseg], words)
+                                           : 0u;
+                    const int32_t tw = S.in_tw[q];
+                    const int32_t tile = jj / tw;
+                    // one partial tile per group of active words, stored
+                    // contiguously by group index
+                    const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (jj - tile * tw);
+                    const uint8_t *fl = a.pflag + S.in_F[q] + (int64_t)tile * S.in_prewords[q];
+                    // batches of 16 groups: flags and partials loaded
+                    // unconditionally at group indices clamped below ng (a
+                    // group without a partial has flag 0), then summed
+                    for (uint32_t u = 0; u < ng; u += 16) {
+                        uint32_t f[16];
+                        int64_t v[16];
 #pragma unroll
-                            for (int k = 0; k < 16; ++k) v[k] = fl[u + k] ? pp[(int64_t)(u + k) * tw] : 0;
-#pragma unroll
-                            for (int k = 0; k < 16; ++k) acc += v[k];
+                        for (int k = 0; k < 16; ++k) {
+                            const uint32_t uu = min(u + (uint32_t)k, ng - 1);
+                            f[k] = fl[uu];
+                            v[k] = pp[(int64_t)uu * tw];
                         }
-                        for (; u < ng; ++u)
-                            if (fl[u]) acc += pp[(int64_t)u * tw];
-                        g[q] = acc;
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) acc += (u + (uint32_t)k < ng && f[k]) ? v[k] : 0;
                     }
+                    g[q] = acc;
                 }
-                const double iin = syn_current(S, g, v0);
+            }
+            // synaptic current from the start-of-step voltage, held fixed
+            // over the substeps; then the conductances decay
+            const double iin = syn_current(S, g, v0);
+            const double hc = a.hs * S.inv_c;
+            for (int k = 0; k < a.substeps; ++k) hh_substep(S, a.hs, hc, iin, v, m, h, n);
+            if (active) {
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
                     if (q < S.n_in) a.G[S.in_G[q] + j] = fix_decay(g[q], S.in_decay[q]);
-                const double hc = a.hs * S.inv_c;
-                for (int k = 0; k < a.substeps; ++k) hh_substep(S, a.hs, hc, iin, v, m, h, n);
                 spike = (v0 < 0.0) && (v >= 0.0);
                 pair_split(v, a.vh[gid], a.vl[gid]);
                 pair_split(m, a.mh[gid], a.ml[gid]);
                 pair_split(h, a.hh[gid], a.hl[gid]);
                 pair_split(n, a.nh[gid], a.nl[gid]);
                 if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[S.inst], 1);
-                if (S.record_vbar) a.vsum[gid] += v;
+                if (S.record_vbar) a.vsum[gid] = vs + v;
             }
         } else {
             if (active) {
@@ -130,10 +158,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             if (a.raster) a.raster[(t % a.raster_steps) * a.n_waves + gw] = ball;
         }
         if (active) {
-            for (int q = 0; q < S.n_tr; ++q) {
-                float *tp = a.trace + S.tr_base[q] + j;
-                *tp = *tp * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
-            }
+#pragma unroll
+            for (int q = 0; q < kMaxTr; ++q)
+                if (q < S.n_tr) a.trace[S.tr_base[q] + j] = trv[q] * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
         }
         if (ball != 0 && a.mode == kModeTiles) {
             // the word is active: record it, and queue one propagation item
@@ -150,14 +177,15 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             }
         }
         if (ball != 0 && spike) {
-            a.counts[gid] += 1;
+            a.counts[gid] = cnt + 1;
             const uint32_t ch = (uint32_t)a.chunk;
             if (a.mode == kModeRows) {
                 // one propagation item per chunk of each outgoing row
-                for (int o = 0; o < S.n_out; ++o) {
+                if (S.n_out > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
+                if (S.n_out > 1) nq += ((uint32_t)(rb1 - rb0) + ch - 1) / ch;
+                for (int o = 2; o < S.n_out; ++o) {
                     const int32_t *rp = a.rp_pool + S.out_rp[o];
-                    const uint32_t len = (uint32_t)(rp[j + 1] - rp[j]);
-                    nq += (len + ch - 1) / ch;
+                    nq += ((uint32_t)(rp[j + 1] - rp[j]) + ch - 1) / ch;
                 }
             }
             for (int o = 0; o < S.n_ltp; ++o) {
@@ -203,11 +231,15 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         const int32_t ch = a.chunk;
         int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
-        for (int o = 0; o < S.n_out; ++o) {
+        auto emit = [&](int o, int32_t r0, int32_t r1) {
+            for (int32_t k = r0; k < r1; k += ch, ++pos)
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, r1), 0, 0};
+        };
+        if (S.n_out > 0) emit(0, ra0, ra1);
+        if (S.n_out > 1) emit(1, rb0, rb1);
+        for (int o = 2; o < S.n_out; ++o) {
             const int32_t *rp = a.rp_pool + S.out_rp[o];
-            const int32_t k1 = rp[j + 1];
-            for (int32_t k = rp[j]; k < k1; k += ch, ++pos)
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, k1), 0, 0};
+            emit(o, rp[j], rp[j + 1]);
         }
     }
     // tile mode: lane 0 counted the wave's items, all lanes write

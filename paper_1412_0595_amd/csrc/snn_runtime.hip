@@ -761,7 +761,9 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->d_segs = (Seg *)dev_alloc(net, sizeof(Seg) * net->segs.size());
     net->d_projs = (Proj *)dev_alloc(net, sizeof(Proj) * std::max<size_t>(net->projs.size(), 1));
     net->d_wave_seg = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(W, 1));
-    net->d_rp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(rp_total, 1));
+    // at least two entries: the neuron update reads rp[0..1] as a harmless
+    // stand-in when a population has no outgoing projection
+    net->d_rp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(rp_total, 2));
     net->d_col = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(syn_total, 1));
     net->d_w = (float *)dev_alloc(net, 4 * std::max<int64_t>(syn_total, 1));
     net->d_cp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(cp_total, 1));
