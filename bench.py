@@ -48,6 +48,41 @@ WORKLOADS = {
 }
 
 
+def kernel_sources_sha256():
+    """Hash of the HIP sources the kernels are built from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1412_0595_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE passes, each scaled
+    by the same counter's reading for a plain copy of known size), or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_workload{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def sub_spec(spec, k):
     return dict(dt=spec["dt"], substeps=spec["substeps"], instances=[spec["instances"][k]])
 
@@ -142,6 +177,7 @@ def parse():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the recorded forward + reverse pass (gradient) instead of plain steps")
     ap.add_argument("--ckpt-every", type=int, default=100)
+    ap.add_argument("--sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration)")
     return ap.parse_args()
@@ -206,6 +242,9 @@ def sweep(args):
 
 def main():
     args = parse()
+    if args.sources_sha:
+        print(kernel_sources_sha256())
+        return
     if args.calib_copy:
         import torch
         a = torch.ones(args.calib_copy * (1 << 18), dtype=torch.float32, device="cuda")
@@ -296,7 +335,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
     roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+            "traffic": profiled_traffic("k_" + dom, args.workload),
             "profiled_steps": args.profile_steps,
             "ms_per_launch": {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()},
             "bytes_per_launch": {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}}
