@@ -12,9 +12,10 @@
 //               (projection, post tile, group of active 64-neuron spike words
 //               of the pre population).  The wavefront walks the row slices
 //               of the group's spiking rows in the Compressed Row Storage
-//               arrays (Section 3) and adds the weights into its own LDS tile
-//               (columns within a row are distinct, so no atomics), then
-//               writes the tile out as the group's partial.
+//               arrays (Section 3), packed several rows to a batch of loads,
+//               and adds the weights into its own LDS tile (columns within a
+//               row are distinct, so no atomics), then writes the tile out as
+//               the group's partial.
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //
@@ -274,55 +275,136 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     }
 }
 
-// Walk one row slice into the wavefront's LDS tile in batches of up to 8
-// entries per lane.  The loads of a batch are issued back to back at an index
-// clamped into the slice, so they are always in bounds.  Then all 8 tile
-// entries are read before any is written; the entries of one row have
-// distinct columns, so this order is exact.  A clamped duplicate reads the
-// same pre-batch value and adds the same increment as the slice's last entry,
-// so it writes the identical sum: every write is unconditional and harmless
-// in any order, and the batch has no branch.
-__device__ __forceinline__ void slice_to_tile(long long *acc, const int32_t *col, const float *w, int32_t k0,
-                                              int32_t k1, int32_t c0, double s, int lane)
+// A batch of up to kSlots slots of kWave consecutive synapses each, packed
+// from the slices of one or more spiking rows of a spike word (a long slice
+// spans several slots and batches).  Slot u holds CSR entries
+// [sk[u], min(sk[u] + kWave, se[u])); all of a slot's fields are uniform.
+// Slots of the same row form one phase (ph[u]); an unused slot has ph -1
+// and repeats the last used slot's range, so its loads stay in bounds.
+constexpr int kSlots = 8;
+
+struct Batch {
+    int32_t sk[kSlots], se[kSlots], ph[kSlots];
+    int32_t nph;
+};
+
+// Fill the next batch from the row in progress [k, k1) and the spiking rows
+// left in rem (lane r holds row r's slice bounds in b0, b1).  Returns false
+// when nothing is left.
+__device__ __forceinline__ bool fill_batch(Batch &B, uint64_t &rem, int32_t &k, int32_t &k1, int32_t b0, int32_t b1)
 {
-    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
-        int32_t c[8];
-        float g[8];
+    int32_t nph = 0;
+    bool fresh = true;              // the next used slot starts a new phase
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t k = min(kb + u * kWave + lane, k1 - 1);
-            c[u] = col[k] - c0;
-            g[u] = w[k];
+    for (int u = 0; u < kSlots; ++u) {
+        while (k >= k1 && rem) {
+            const int r = __builtin_ctzll(rem);
+            rem &= rem - 1;
+            k = __builtin_amdgcn_readlane(b0, r);
+            k1 = __builtin_amdgcn_readlane(b1, r);
+            fresh = true;
         }
-        long long v[8];
+        if (k < k1) {
+            if (fresh) ++nph;
+            fresh = false;
+            B.sk[u] = k;
+            B.se[u] = k1;
+            B.ph[u] = nph - 1;
+            k += kWave;
+        } else if (u > 0) {
+            B.sk[u] = B.sk[u - 1];
+            B.se[u] = B.se[u - 1];
+            B.ph[u] = -1;
+        } else {
+            return false;
+        }
+    }
+    B.nph = nph;
+    return true;
+}
+
+// Add the slices of a spike word's rows into the wavefront's LDS tile.  The
+// loads of a batch are issued back to back at indices clamped into their
+// slot's row slice, so they are always in bounds.  Then, one row (phase) at a
+// time, the tile entries are all read before the row's own are written:
+// columns within one row are distinct, so this order is exact, and the phases
+// run in program order, so rows sharing a column see each other's sums.  A clamped
+// duplicate reads the same value and adds the same increment as its row's
+// last entry, so it writes the identical sum: the writes need no predicate.
+__device__ __forceinline__ void word_to_tile(long long *acc, const int32_t *col, const float *w, uint64_t rem,
+                                             int32_t b0, int32_t b1, int32_t c0, double s, int lane)
+{
+    int32_t k = 0, k1 = 0;
+    Batch B;
+    while (fill_batch(B, rem, k, k1, b0, b1)) {
+        int32_t c[kSlots];
+        float g[kSlots];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = acc[c[u]];
+        for (int u = 0; u < kSlots; ++u) {
+            const int32_t kk = min(B.sk[u] + lane, B.se[u] - 1);
+            c[u] = col[kk] - c0;
+            g[u] = w[kk];
+        }
+        long long inc[kSlots], v[kSlots];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[c[u]] = v[u] + fix_increment(s, g[u]);
+        for (int u = 0; u < kSlots; ++u) inc[u] = fix_increment(s, g[u]);
+        for (int32_t p = 0; p < B.nph; ++p) {
+            // every slot is read (a read is harmless and keeps the reads
+            // free of branches); only the phase's own slots are written
+#pragma unroll
+            for (int u = 0; u < kSlots; ++u) v[u] = acc[c[u]];
+#pragma unroll
+            for (int u = 0; u < kSlots; ++u)
+                if (B.ph[u] == p) acc[c[u]] = v[u] + inc[u];
+        }
     }
 }
 
-// The same walk for delivery straight into G with 64-bit atomics.  Here a
-// duplicate must not add again, so the atomics are predicated; the empty asm
-// consumes the loaded registers so the compiler keeps all 16 loads ahead of
-// the predicated atomics (nothing waits on an atomic without a return value).
+// The same walk for delivery straight into G with 64-bit atomics; a clamped
+// duplicate must not add again, so the atomics are predicated, and the empty
+// asm consumes the loaded registers so the compiler keeps all the loads ahead
+// of the predicated atomics (nothing waits on an atomic without a return).
+__device__ __forceinline__ void atomics_from_batch(unsigned long long *G, const int32_t *col, const float *w,
+                                                   const int32_t *sk, const int32_t *se, const int32_t *ph, double s,
+                                                   int lane)
+{
+    int32_t c[kSlots];
+    float g[kSlots];
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const int32_t kk = min(sk[u] + lane, se[u] - 1);
+        c[u] = col[kk];
+        g[u] = w[kk];
+    }
+    asm volatile("" ::"v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]), "v"(c[7]),
+                 "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]));
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u)
+        if (ph[u] >= 0 && sk[u] + lane < se[u]) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+}
+
+__device__ __forceinline__ void word_to_global(unsigned long long *G, const int32_t *col, const float *w, uint64_t rem,
+                                               int32_t b0, int32_t b1, double s, int lane)
+{
+    int32_t k = 0, k1 = 0;
+    Batch B;
+    while (fill_batch(B, rem, k, k1, b0, b1)) atomics_from_batch(G, col, w, B.sk, B.se, B.ph, s, lane);
+}
+
+// One row slice [k0, k1) into G with atomics (rows mode), in full batches.
 __device__ __forceinline__ void slice_to_global(unsigned long long *G, const int32_t *col, const float *w,
                                                 int32_t k0, int32_t k1, double s, int lane)
 {
-    for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
-        int32_t c[8];
-        float g[8];
+    for (int32_t kb = k0; kb < k1; kb += kSlots * kWave) {
+        int32_t sk[kSlots], se[kSlots], ph[kSlots];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t k = min(kb + u * kWave + lane, k1 - 1);
-            c[u] = col[k];
-            g[u] = w[k];
+        for (int u = 0; u < kSlots; ++u) {
+            const bool used = kb + u * kWave < k1;
+            sk[u] = used ? kb + u * kWave : kb;
+            se[u] = k1;
+            ph[u] = used ? 0 : -1;
         }
-        asm volatile("" ::"v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]), "v"(c[7]),
-                     "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]));
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (kb + u * kWave + lane < k1) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+        atomics_from_batch(G, col, w, sk, se, ph, s, lane);
     }
 }
 
@@ -428,13 +510,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
             for (int d = kWave / 2; d > 0; d >>= 1) ev += __shfl_xor(ev, d, kWave);
             if (ev * kSparseRatio < tw) {
                 // sparse: straight into G with atomics
-                unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
-                for (uint64_t bits = bits0; bits;) {
-                    const int r = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
-                    slice_to_global(G, col, w, k0, k1, s, lane);
-                }
+                word_to_global((unsigned long long *)(a.G + P.G_base), col, w, bits0, b0, b1, s, lane);
                 if (lane == 0) *flag = 0;
                 continue;
             }
@@ -459,13 +535,15 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                     }
                 }
             }
+            if (!P.stdp) {
+                word_to_tile(acc, col, w, bits, b0, b1, c0, s, lane);
+                continue;
+            }
             while (bits) {
                 const int r = __builtin_ctzll(bits);
                 bits &= bits - 1;
                 const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
-                if (!P.stdp) {
-                    slice_to_tile(acc, col, w, k0, k1, c0, s, lane);
-                } else {
+                {
                     const float *y = a.trace + P.y_base;
                     for (int32_t k = k0 + lane; k < k1; k += kWave) {
                         const int32_t c = col[k];
