@@ -323,40 +323,69 @@ __device__ __forceinline__ bool fill_batch(Batch &B, uint64_t &rem, int32_t &k, 
     return true;
 }
 
-// Add the slices of a spike word's rows into the wavefront's LDS tile.  The
-// loads of a batch are issued back to back at indices clamped into their
-// slot's row slice, so they are always in bounds.  Then, one row (phase) at a
-// time, the tile entries are all read before the row's own are written:
-// columns within one row are distinct, so this order is exact, and the phases
-// run in program order, so rows sharing a column see each other's sums.  A clamped
-// duplicate reads the same value and adds the same increment as its row's
-// last entry, so it writes the identical sum: the writes need no predicate.
+// Loads of one batch: column (relative to the tile) and weight per slot, at
+// indices clamped into the slot's row slice, so always in bounds.
+struct BatchData {
+    int32_t c[kSlots];
+    float g[kSlots];
+};
+
+__device__ __forceinline__ void load_batch(BatchData &D, const Batch &B, const int32_t *col, const float *w,
+                                           int32_t c0, int lane)
+{
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const int32_t kk = min(B.sk[u] + lane, B.se[u] - 1);
+        D.c[u] = col[kk] - c0;
+        D.g[u] = w[kk];
+    }
+}
+
+// One row (phase) at a time, the tile entries are all read before the row's
+// own are written: columns within one row are distinct, so this order is
+// exact, and the phases run in program order, so rows sharing a column see
+// each other's sums.  A clamped duplicate reads the same value and adds the
+// same increment as its row's last entry, so it writes the identical sum.
+__device__ __forceinline__ void batch_to_tile(long long *acc, const Batch &B, const BatchData &D, double s)
+{
+    long long inc[kSlots], v[kSlots];
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) inc[u] = fix_increment(s, D.g[u]);
+    for (int32_t p = 0; p < B.nph; ++p) {
+        // every slot is read (a read is harmless and keeps the reads free of
+        // branches); only the phase's own slots are written
+#pragma unroll
+        for (int u = 0; u < kSlots; ++u) v[u] = acc[D.c[u]];
+#pragma unroll
+        for (int u = 0; u < kSlots; ++u)
+            if (B.ph[u] == p) acc[D.c[u]] = v[u] + inc[u];
+    }
+}
+
+// Add the slices of a spike word's rows into the wavefront's LDS tile,
+// software-pipelined over two explicit buffers: the loads of the next batch
+// are in flight while the current batch is added (a register swap would make
+// the compiler wait for them).  When there is no next batch, its buffer
+// repeats the current ranges, so its loads stay in bounds and go unused.
 __device__ __forceinline__ void word_to_tile(long long *acc, const int32_t *col, const float *w, uint64_t rem,
                                              int32_t b0, int32_t b1, int32_t c0, double s, int lane)
 {
     int32_t k = 0, k1 = 0;
-    Batch B;
-    while (fill_batch(B, rem, k, k1, b0, b1)) {
-        int32_t c[kSlots];
-        float g[kSlots];
-#pragma unroll
-        for (int u = 0; u < kSlots; ++u) {
-            const int32_t kk = min(B.sk[u] + lane, B.se[u] - 1);
-            c[u] = col[kk] - c0;
-            g[u] = w[kk];
-        }
-        long long inc[kSlots], v[kSlots];
-#pragma unroll
-        for (int u = 0; u < kSlots; ++u) inc[u] = fix_increment(s, g[u]);
-        for (int32_t p = 0; p < B.nph; ++p) {
-            // every slot is read (a read is harmless and keeps the reads
-            // free of branches); only the phase's own slots are written
-#pragma unroll
-            for (int u = 0; u < kSlots; ++u) v[u] = acc[c[u]];
-#pragma unroll
-            for (int u = 0; u < kSlots; ++u)
-                if (B.ph[u] == p) acc[c[u]] = v[u] + inc[u];
-        }
+    Batch BA, BB;
+    BatchData DA, DB;
+    if (!fill_batch(BA, rem, k, k1, b0, b1)) return;
+    load_batch(DA, BA, col, w, c0, lane);
+    for (;;) {
+        const bool more_b = fill_batch(BB, rem, k, k1, b0, b1);
+        if (!more_b) BB = BA;
+        load_batch(DB, BB, col, w, c0, lane);
+        batch_to_tile(acc, BA, DA, s);
+        if (!more_b) return;
+        const bool more_a = fill_batch(BA, rem, k, k1, b0, b1);
+        if (!more_a) BA = BB;
+        load_batch(DA, BA, col, w, c0, lane);
+        batch_to_tile(acc, BB, DB, s);
+        if (!more_a) return;
     }
 }
 
