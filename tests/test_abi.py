@@ -1,6 +1,7 @@
 """The C-ABI library loads, exports every declared symbol, and rejects invalid
 network descriptions on the host before touching the GPU."""
 import copy
+import ctypes
 import os
 import re
 
@@ -148,4 +149,7 @@ def test_null_arguments():
     assert L.snn_create(None, None) == snn.SNN_EINVAL
     assert L.snn_step(None, 1) == snn.SNN_EINVAL
     assert L.snn_time(None) == -1
+    ms = (ctypes.c_double * 3)()
+    cnt = (ctypes.c_int64 * 3)()
+    assert L.snn_profile_steps(None, 10, ms, cnt) == snn.SNN_EINVAL
     L.snn_destroy(None)

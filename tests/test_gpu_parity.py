@@ -249,6 +249,35 @@ def test_graph_and_direct_launches_agree(snn):
     b.close()
 
 
+@pytest.mark.parametrize("workload,scale", [(1, 0.5), (3, 0.05)])
+def test_profiled_steps_advance_like_steps(snn, workload, scale):
+    """snn_profile_steps advances the network exactly as snn_step does (the
+    plastic workload included) and reports one launch of each step kernel
+    per step with a positive duration."""
+    say(f"case: profiled steps, workload {workload} at scale {scale}")
+    spec = netgen.make_config(workload, scale=scale)
+    a = snn.Network(spec)
+    b = snn.Network(spec)
+    a.step(150)
+    b.step(20)
+    prof = b.profile_steps(130)
+    assert b.t == a.t == 150
+    plastic = any(q.get("stdp") for q in spec["instances"][0]["projs"])
+    for k, (ms, n) in prof.items():
+        expect = 130 if (k != "potentiate" or plastic) else 0
+        assert n == expect, (k, n)
+        assert (ms > 0) == (expect > 0), (k, ms)
+    for p in (1, 2):
+        for var in range(4):
+            assert np.array_equal(a.state(0, p, var), b.state(0, p, var))
+        assert np.array_equal(a.spikes(0, p), b.spikes(0, p))
+    for q in range(len(spec["instances"][0]["projs"])):
+        assert np.array_equal(a.conductance(0, q), b.conductance(0, q))
+        assert np.array_equal(a.weights(0, q), b.weights(0, q))
+    a.close()
+    b.close()
+
+
 def test_launch_shape_does_not_change_results(snn):
     say("case: launch shapes")
     spec = netgen.make_config(1, scale=0.5)
