@@ -54,10 +54,17 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 
 // Fixed-point increment of one delivered synapse: g_scale * g on the
 // 2^-40 uS grid (s_fix = g_scale * 2^40; the product of two fp32 values is
-// exact in double, so the only rounding is the final one).
+// exact in double, so the only rounding is the final one).  The library
+// keeps every increment below 2^51 in magnitude, so it is rounded to an
+// integer by the classic addition of 1.5 * 2^52: the sum lies in
+// [2^52, 2^53), where the spacing of doubles is 1, so the addition rounds x to
+// the nearest integer (ties to even) and that integer is the difference of the
+// sum's bit pattern and the constant's.
 __device__ __forceinline__ long long fix_increment(double s_fix, float w)
 {
-    return __double2ll_rn(s_fix * (double)w);
+    const double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+    const double y = s_fix * (double)w + kMagic;
+    return (long long)(__double_as_longlong(y) - __double_as_longlong(kMagic));
 }
 
 __device__ __forceinline__ int64_t fix_decay(int64_t g, double d)

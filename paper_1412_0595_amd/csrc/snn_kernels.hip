@@ -352,10 +352,11 @@ __device__ __forceinline__ void batch_to_tile(long long *acc, const Batch &B, co
 #pragma unroll
     for (int u = 0; u < kSlots; ++u) inc[u] = fix_increment(s, D.g[u]);
     for (int32_t p = 0; p < B.nph; ++p) {
-        // every slot is read (a read is harmless and keeps the reads free of
-        // branches); only the phase's own slots are written
+        // every slot is read, those of other phases at tile entry 0 (one
+        // broadcast read; it keeps the reads free of branches), and only the
+        // phase's own slots are written
 #pragma unroll
-        for (int u = 0; u < kSlots; ++u) v[u] = acc[D.c[u]];
+        for (int u = 0; u < kSlots; ++u) v[u] = acc[B.ph[u] == p ? D.c[u] : 0];
 #pragma unroll
         for (int u = 0; u < kSlots; ++u)
             if (B.ph[u] == p) acc[D.c[u]] = v[u] + inc[u];

@@ -479,13 +479,20 @@ int validate(const snn_config *cfg)
 // Largest conductance a post neuron can reach is below (sum of its column) *
 // g_scale / (1 - decay); keep it well inside the 2^63 * 2^-40 uS range.
 constexpr double kGLimit = 4194304.0;   // 2^22 uS
+// A single delivered increment g_scale * g must stay below 2^11 uS, so that
+// its fixed-point value is below 2^51, where the propagation kernels round it
+// to an integer with one floating-point addition.
+constexpr double kWLimit = 2048.0;      // 2^11 uS
 
-int check_range(const snn_net *net, const std::vector<double> &colmax_sum, const float *gs)
+int check_range(const snn_net *net, const std::vector<double> &colmax_sum, const std::vector<double> &wmax,
+                const float *gs)
 {
     for (size_t q = 0; q < net->projs.size(); ++q) {
         const double s = gs[net->projs[q].inst];
         if (!(colmax_sum[q] * s < kGLimit))
             return fail(SNN_ERANGE, "projection %zu: g_scale * column sum / (1 - decay) exceeds %g uS", q, kGLimit);
+        if (!(wmax[q] * s < kWLimit))
+            return fail(SNN_ERANGE, "projection %zu: g_scale * largest weight exceeds %g uS", q, kWLimit);
     }
     return SNN_OK;
 }
@@ -582,7 +589,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->gscale.resize(net->n_inst);
     net->n_hh = 0;
     net->plastic = false;
-    std::vector<double> colsum_bound;
+    std::vector<double> colsum_bound, w_bound;
     for (int b = 0; b < net->n_inst; ++b) {
         const snn_instance_desc &I = cfg->inst[b];
         net->gscale[b] = I.g_scale;
@@ -686,12 +693,15 @@ int snn_create(const snn_config *cfg, snn_net **out)
             for (double c : col) mx = std::max(mx, c);
             if (Q.stdp) mx = std::max(mx, (double)Q.g_max * (double)pre.n);
             colsum_bound.push_back(mx / (1.0 - decay));
+            double wm = Q.stdp ? (double)Q.g_max : 0.0;
+            for (int64_t k = 0; k < Q.nnz; ++k) wm = std::max(wm, (double)Q.g[k]);
+            w_bound.push_back(wm);
             net->proj_of[b].push_back(gi);
             net->projs.push_back(P);
             net->hprojs.push_back(std::move(H));
         }
     }
-    if ((rc = check_range(net, colsum_bound, net->gscale.data()))) return bail(rc);
+    if ((rc = check_range(net, colsum_bound, w_bound, net->gscale.data()))) return bail(rc);
     net->n_neurons_padded = base;
     net->n_waves = base / kWave;
     net->w_count = syn_total;
@@ -1205,7 +1215,7 @@ int snn_set_gscale(snn_net *net, const float *per_instance)
         if (!(per_instance[b] >= 0.0f) || !std::isfinite(per_instance[b]))
             return fail(SNN_EINVAL, "g_scale of instance %d must be finite and >= 0", b);
     // same range rule as at create, on the stored weights' column sums
-    std::vector<double> bound(net->projs.size(), 0.0);
+    std::vector<double> bound(net->projs.size(), 0.0), wbound(net->projs.size(), 0.0);
     for (size_t q = 0; q < net->projs.size(); ++q) {
         const HostProj &H = net->hprojs[q];
         std::vector<int32_t> col(H.nnz);
@@ -1214,6 +1224,9 @@ int snn_set_gscale(snn_net *net, const float *per_instance)
         if ((rc = d2h(net, w.data(), net->d_w + H.syn_base, 4 * (size_t)H.nnz))) return rc;
         std::vector<double> cs(std::max(H.n_post, 1), 0.0);
         for (int64_t k = 0; k < H.nnz; ++k) cs[col[k]] += w[k];
+        double wm = H.stdp ? (double)net->projs[q].g_max : 0.0;
+        for (int64_t k = 0; k < H.nnz; ++k) wm = std::max(wm, (double)w[k]);
+        wbound[q] = wm;
         double mx = 0.0;
         for (double c : cs) mx = std::max(mx, c);
         if (H.stdp) mx = std::max(mx, (double)net->projs[q].g_max * H.n_pre);
@@ -1223,7 +1236,7 @@ int snn_set_gscale(snn_net *net, const float *per_instance)
             if (net->segs[s].in_G[k] == H.G_base) decay = net->segs[s].in_decay[k];
         bound[q] = mx / (1.0 - decay);
     }
-    if ((rc = check_range(net, bound, per_instance))) return rc;
+    if ((rc = check_range(net, bound, wbound, per_instance))) return rc;
     std::copy(per_instance, per_instance + net->n_inst, net->gscale.begin());
     return h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst);
 }

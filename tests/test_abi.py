@@ -137,6 +137,18 @@ def test_conductance_range_rejected():
     assert rc == snn.SNN_ERANGE, msg
 
 
+def test_single_weight_range_rejected():
+    """One synapse with g_scale * g of 2^11 uS or more is rejected even when
+    the reachable conductance is in range (the kernels round every increment
+    with a method exact below 2^51 units of 2^-40 uS)."""
+    spec = copy.deepcopy(_tiny())
+    q = _first_nonempty(spec["instances"][0])
+    q["g"] = np.asarray(q["g"], np.float32).copy()
+    q["g"][0] = 3000.0
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_ERANGE and "largest weight" in msg, msg
+
+
 def test_valid_description_passes_validation():
     """A valid network passes every host check; without a GPU the first
     device call then fails cleanly with SNN_EDEVICE (on a GPU it succeeds)."""
