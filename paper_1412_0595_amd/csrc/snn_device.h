@@ -44,6 +44,14 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
     return x;
 }
 
+// Lane `l` (uniform) of a 64-bit value.
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, uint32_t l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // A 64-bit value known to be the same in every lane, moved to scalar registers.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 {

@@ -490,6 +490,7 @@ constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile w
 __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs a)
 {
     __shared__ long long s_acc[kPropWaves][kTileMax];
+    __shared__ int32_t s_rows[kPropWaves][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x >> 6;
     const int64_t t = a.st->t_prop;
@@ -548,6 +549,59 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         for (int i = lane; i < tw; i += kWave) acc[i] = 0;
         const Seg &pre = a.segs[P.pre_seg];
         const int32_t *wl = a.awl + (int64_t)prev * a.n_waves + pre.base / kWave + slot;
+        if (!P.stdp) {
+            // The group's spiking rows, gathered across its words into a row
+            // list in LDS, up to kWave rows per chunk: one lane per word reads
+            // the word's id and bits, each lane places its rows by counting
+            // the set bits below it, and one lane per listed row loads the
+            // row's slice bounds, so a chunk's bounds take one round trip and
+            // one batch pipeline covers all of its rows.
+            const uint64_t *wbits = a.bits + (int64_t)prev * a.n_waves + pre.base / kWave;
+            int32_t *rows = s_rows[wid];
+            for (uint32_t w0 = 0; w0 < nwords; w0 += kWave) {
+                const uint32_t nwc = min((uint32_t)kWave, nwords - w0);
+                const int32_t word_l = wl[w0 + min((uint32_t)lane, nwc - 1)];
+                const uint64_t bl = wbits[word_l];
+                const uint64_t bits_l = (uint32_t)lane < nwc ? bl : 0ull;
+                const uint32_t incl = wave_incl_sum((uint32_t)__popcll(bits_l), lane);
+                uint32_t ws = 0;
+                while (ws < nwc) {
+                    const uint32_t base = ws ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ws - 1) : 0u;
+                    // words ws .. we-1 hold at most kWave rows (a word holds
+                    // at most kWave, so we > ws)
+                    const uint64_t over =
+                        __ballot((uint32_t)lane >= ws && (uint32_t)lane < nwc && incl - base > (uint32_t)kWave);
+                    const uint32_t we = over ? (uint32_t)__builtin_ctzll(over) : nwc;
+                    const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)we - 1) - base;
+                    for (uint32_t wv = ws; wv < we; ++wv) {
+                        const uint64_t bw = readlane_u64(bits_l, wv);
+                        const int32_t wd = __builtin_amdgcn_readlane(word_l, (int)wv);
+                        const uint32_t off = (wv ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)wv - 1) : 0u) - base;
+                        if ((bw >> lane) & 1ull)
+                            rows[off + (uint32_t)__popcll(bw & ((1ull << lane) - 1ull))] = wd * kWave + lane;
+                    }
+                    if (R > 0) {
+                        const int32_t row = rows[min((uint32_t)lane, R - 1)];
+                        int32_t rb0, rb1;
+                        if (P.tp_base < 0) {
+                            rb0 = rp[row];
+                            rb1 = rp[row + 1];
+                        } else {
+                            rb0 = tp[(int64_t)row * stride + tile];
+                            rb1 = tp[(int64_t)row * stride + tile + 1];
+                        }
+                        const uint64_t rem = R >= (uint32_t)kWave ? ~0ull : ((1ull << R) - 1ull);
+                        word_to_tile(acc, col, w, rem, rb0, rb1, c0, s, lane);
+                    }
+                    ws = we;
+                }
+            }
+            int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
+            for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
+            if (lane == 0) *flag = 1;
+            continue;
+        }
+        // plastic rows: one word at a time, one row at a time
         for (uint32_t wi = 0; wi < nwords; ++wi) {
             uint64_t bits = bits0;
             if (wi > 0) {
@@ -564,10 +618,6 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                         b1 = tp[(int64_t)i * stride + tile + 1];
                     }
                 }
-            }
-            if (!P.stdp) {
-                word_to_tile(acc, col, w, bits, b0, b1, c0, s, lane);
-                continue;
             }
             while (bits) {
                 const int r = __builtin_ctzll(bits);
