@@ -15,14 +15,15 @@ constexpr int kMaxLtp = 2;   // plastic projections arriving at one population
 constexpr int kMinChunk = 64;
 constexpr int kTileMax = 1024;  // post neurons per propagation tile (LDS accumulator width)
 constexpr int kPropWaves = 4;   // wavefronts per propagation block (one LDS tile copy each)
-constexpr int kMinGroups = 32;  // partial tiles per (projection, post tile) the neuron update sums at least
-constexpr int kRowsPerGroup = 32;  // spiking rows per group aimed for when more groups are allowed
+constexpr int kMinGroups = 32;  // groups (partial tiles) per (projection, post tile) at least
+constexpr int kRowsPerGroup = 8;  // spiking rows per group aimed for when more groups are allowed
 
 // Active spike words of a pre population are processed in groups of
 // consecutive active-list slots: with na active words and `rows` spiking
 // rows at the previous step, a group holds ceil(na / n_groups) words, where
 // n_groups = clamp(rows / kRowsPerGroup, kMinGroups, words).  Each group
-// leaves one partial tile; the neuron update sums the groups' partials.
+// leaves one partial tile; a reduction pass after the propagation adds the
+// groups' partials of each tile into G.
 __host__ __device__ inline uint32_t group_words(uint32_t na, uint32_t rows, uint32_t words)
 {
     uint32_t g = rows / kRowsPerGroup;
@@ -62,11 +63,6 @@ struct Seg {
     int64_t in_G[kMaxIn];
     double in_erev[kMaxIn];
     double in_decay[kMaxIn];
-    int64_t in_P[kMaxIn];
-    int64_t in_F[kMaxIn];
-    int32_t in_tw[kMaxIn];
-    int32_t in_preseg[kMaxIn];
-    int32_t in_prewords[kMaxIn];
     // outgoing projections: id, row-start array (pool offset), post tiles
     int32_t out_proj[kMaxOut];
     int64_t out_rp[kMaxOut];
@@ -162,8 +158,6 @@ struct NeuronArgs {
     double hs;               // dt / substeps
     StepState *st;
     int32_t mode;            // kModeRows / kModeTiles
-    const int64_t *partial;  // delivered partial tiles of the previous step
-    const uint8_t *pflag;    // which groups wrote a partial tile
     uint32_t *awcnt;         // [2][n_segs]  active spike words
     uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
@@ -192,6 +186,8 @@ struct PropArgs {
     uint32_t *scnt;          // [2][n_segs], likewise
     const int32_t *awl;      // [2][n_waves]
     int32_t n_segs;
+    const int4 *units;       // tile mode: reduction units (projection, tile, first column, first group)
+    int64_t n_units;
 };
 
 struct LtpArgs {

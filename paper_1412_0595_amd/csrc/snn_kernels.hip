@@ -87,45 +87,11 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             double h = pair_load(a.hh, a.hl, gid);
             double n = pair_load(a.nh, a.nl, gid);
             const double v0 = v;
-            // delivered conductance: G (rows mode), or G plus the partial
-            // tiles of every group of pre spike words active at t - 1
+            // delivered conductance (both delivery modes leave it in G)
             int64_t g[kMaxIn];
-            const int prev = cur ^ 1;
 #pragma unroll
-            for (int q = 0; q < kMaxIn; ++q) {
-                if (q < S.n_in && a.mode == kModeRows) g[q] = a.G[S.in_G[q] + jj];
-                if (q < S.n_in && a.mode == kModeTiles) {
-                    int64_t acc = a.G[S.in_G[q] + jj];
-                    const int pseg = S.in_preseg[q];
-                    const uint32_t words = (uint32_t)S.in_prewords[q];
-                    const uint32_t na = min(a.awcnt[prev * a.n_segs + pseg], words);
-                    const uint32_t ng = na ? (na + group_words(na, a.scnt[prev * a.n_segs + pseg], words) - 1) /
-                                                 group_words(na, a.scnt[prev * a.n_segs + pseg], words)
-                                           : 0u;
-                    const int32_t tw = S.in_tw[q];
-                    const int32_t tile = jj / tw;
-                    // one partial tile per group of active words, stored
-                    // contiguously by group index
-                    const int64_t *pp = a.partial + S.in_P[q] + (int64_t)tile * S.in_prewords[q] * tw + (jj - tile * tw);
-                    const uint8_t *fl = a.pflag + S.in_F[q] + (int64_t)tile * S.in_prewords[q];
-                    // batches of 16 groups: flags and partials loaded
-                    // unconditionally at group indices clamped below ng (a
-                    // group without a partial has flag 0), then summed
-                    for (uint32_t u = 0; u < ng; u += 16) {
-                        uint32_t f[16];
-                        int64_t v[16];
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) {
-                            const uint32_t uu = min(u + (uint32_t)k, ng - 1);
-                            f[k] = fl[uu];
-                            v[k] = pp[(int64_t)uu * tw];
-                        }
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) acc += (u + (uint32_t)k < ng && f[k]) ? v[k] : 0;
-                    }
-                    g[q] = acc;
-                }
-            }
+            for (int q = 0; q < kMaxIn; ++q)
+                if (q < S.n_in) g[q] = a.G[S.in_G[q] + jj];
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
             const double iin = syn_current(S, g, v0);
@@ -649,6 +615,54 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
 }
 
 // ---------------------------------------------------------------------------
+// Tile mode, after the propagation: add every group's partial tile into G.
+// One wavefront per unit = (projection, post tile, 64 columns, 64 groups),
+// one lane per column; flags and partials are loaded 16 groups at a time at
+// group indices clamped below the group count (a group that delivered with
+// atomics instead has flag 0), and each column ends with one atomic add.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = a.st->t_neuron;             // set by the propagation just before
+    const int prev = (int)((t + 1) & 1);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < a.n_units; u += nw) {
+        const int32_t proj = __builtin_amdgcn_readfirstlane(a.units[u].x);
+        const int32_t tile = __builtin_amdgcn_readfirstlane(a.units[u].y);
+        const int32_t col0 = __builtin_amdgcn_readfirstlane(a.units[u].z);
+        const uint32_t chunk = (uint32_t)__builtin_amdgcn_readfirstlane(a.units[u].w);
+        const Proj &P = a.projs[proj];
+        const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        if (na == 0) continue;
+        const uint32_t gw = group_words(na, a.scnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        const uint32_t ng = (na + gw - 1) / gw;
+        if (chunk >= ng) continue;
+        const uint32_t ge = min(ng, chunk + (uint32_t)kWave);
+        const int32_t tw = P.tile_w;
+        const int32_t c = col0 + lane;                  // column within the tile
+        const int32_t cg = tile * tw + c;               // post neuron
+        const bool valid = c < tw && cg < P.n_post;
+        const int64_t *pp = a.partial + P.P_base + (int64_t)tile * P.pre_words * tw + (valid ? c : col0);
+        const uint8_t *fl = a.pflag + P.F_base + (int64_t)tile * P.pre_words;
+        int64_t sum = 0;
+        for (uint32_t g = chunk; g < ge; g += 16) {
+            uint32_t f[16];
+            int64_t v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t gg = min(g + (uint32_t)k, ge - 1);
+                f[k] = fl[gg];
+                v[k] = pp[(int64_t)gg * tw];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) sum += (g + (uint32_t)k < ge && f[k]) ? v[k] : 0;
+        }
+        if (valid && sum != 0) atomicAdd((unsigned long long *)(a.G + P.G_base + cg), (unsigned long long)sum);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // STDP potentiation over the columns of post neurons that spiked at t - 1
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
@@ -712,12 +726,30 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent
     return hipGetLastError();
 }
 
+// Delivery of one step.  Tile mode is two kernels, the tiled propagation and
+// the reduction of its partial tiles into G; an event pair then brackets both.
 hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (a.mode == kModeRows)
+    if (a.mode == kModeRows) {
         SNN_LAUNCH(k_propagate_rows, dim3(blocks), dim3(block), s, e0, e1, a);
-    else    // the tiled kernel runs kPropWaves wavefronts per block
+        return hipGetLastError();
+    }
+    // the tiled kernel runs kPropWaves wavefronts per block
+    if (a.n_units == 0) {
         SNN_LAUNCH(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), s, e0, e1, a);
+        return hipGetLastError();
+    }
+    hipEvent_t none = nullptr;
+    SNN_LAUNCH(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), s, e0, none, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t rb = std::min<int64_t>((a.n_units + 3) / 4, 4096);
+    if (e0) {
+        // the stop event of the pair goes on the second kernel
+        hipExtLaunchKernelGGL(k_reduce_partials, dim3((unsigned)rb), dim3(256), 0, s, nullptr, e1, 0, a);
+    } else {
+        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)rb), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

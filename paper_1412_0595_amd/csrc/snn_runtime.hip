@@ -121,6 +121,8 @@ struct snn_net {
     int32_t *d_rp, *d_cp, *d_col, *d_csc_row, *d_csc_pos, *d_tp;
     int64_t *d_partial;
     uint8_t *d_pflag;
+    int4 *d_units;           // tile-mode reduction units
+    int64_t n_units;
     uint32_t *awcnt;     // arena: [2][n_segs]
     uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
@@ -259,8 +261,6 @@ NeuronArgs neuron_args(snn_net *net)
     a.hs = net->dt / net->substeps;
     a.st = net->st;
     a.mode = net->launch.mode;
-    a.partial = net->d_partial;
-    a.pflag = net->d_pflag;
     a.awcnt = net->awcnt;
     a.scnt = net->scnt;
     a.awl = net->awl;
@@ -283,6 +283,8 @@ PropArgs prop_args(snn_net *net)
     p.gscale = net->d_gscale;
     p.partial = net->d_partial;
     p.pflag = net->d_pflag;
+    p.units = net->d_units;
+    p.n_units = net->n_units;
     p.G = net->G;
     p.bits = net->bits;
     p.n_waves = net->n_waves;
@@ -644,11 +646,6 @@ int snn_create(const snn_config *cfg, snn_net **out)
                 tp_total += (int64_t)pre.n * (P.n_tiles + 1);
             }
             const double decay = std::exp(-net->dt / (double)Q.tau_ms);
-            post.in_P[post.n_in] = P.P_base;
-            post.in_F[post.n_in] = P.F_base;
-            post.in_tw[post.n_in] = P.tile_w;
-            post.in_preseg[post.n_in] = P.pre_seg;
-            post.in_prewords[post.n_in] = P.pre_words;
             post.in_proj[post.n_in] = gi;
             post.in_G[post.n_in] = P.G_base;
             post.in_erev[post.n_in] = Q.e_rev_mV;
@@ -783,8 +780,22 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->d_tp = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(tp_total, 1));
     net->d_partial = (int64_t *)dev_alloc(net, 8 * std::max<int64_t>(P_total, 1));
     net->d_pflag = (uint8_t *)dev_alloc(net, std::max<int64_t>(F_total, 1));
+    // reduction units of the tile mode: (projection, post tile, first of 64
+    // columns, first of 64 groups) over every tile's columns and groups
+    std::vector<int4> units;
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        const Proj &P = net->projs[q];
+        for (int32_t tl = 0; tl < P.n_tiles; ++tl) {
+            const int32_t cols = std::min<int32_t>(P.tile_w, P.n_post - tl * P.tile_w);
+            for (int32_t c = 0; c < cols; c += kWave)
+                for (int32_t g = 0; g < P.pre_words; g += kWave) units.push_back(make_int4((int)q, tl, c, g));
+        }
+    }
+    net->n_units = (int64_t)units.size();
+    net->d_units = (int4 *)dev_alloc(net, sizeof(int4) * std::max<size_t>(units.size(), 1));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
-        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag)
+        !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
+        !net->d_units)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -817,6 +828,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
             for (int64_t w = S.base / kWave; w < (S.base + align_up(S.n, kWave)) / kWave; ++w) wave_seg[w] = (int32_t)s;
         }
         if ((rc = up(net->d_wave_seg, wave_seg.data(), 4 * W))) return bail(rc);
+        if ((rc = up(net->d_units, units.data(), sizeof(int4) * units.size()))) return bail(rc);
     }
     if ((rc = up(net->d_segs, net->segs.data(), sizeof(Seg) * net->segs.size()))) return bail(rc);
     if ((rc = up(net->d_projs, net->projs.data(), sizeof(Proj) * net->projs.size()))) return bail(rc);
