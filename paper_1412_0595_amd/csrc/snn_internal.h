@@ -23,7 +23,9 @@ constexpr int kRowsPerGroup = 8;  // spiking rows per group aimed for when more 
 // rows at the previous step, a group holds ceil(na / n_groups) words, where
 // n_groups = clamp(rows / kRowsPerGroup, kMinGroups, words).  Each group
 // leaves one partial tile; a reduction pass after the propagation adds the
-// groups' partials of each tile into G.
+// groups' partials of each tile into G.  The neuron update applies this rule
+// to the previous step's counts when it emits the work of a step (only a
+// group's first word emits items) and records the choice per population.
 __host__ __device__ inline uint32_t group_words(uint32_t na, uint32_t rows, uint32_t words)
 {
     uint32_t g = rows / kRowsPerGroup;
@@ -160,6 +162,7 @@ struct NeuronArgs {
     double hs;               // dt / substeps
     StepState *st;
     int32_t mode;            // kModeRows / kModeTiles
+    uint32_t *gwsel;         // [2][n_segs]  words per group chosen at emission
     uint32_t *awcnt;         // [2][n_segs]  active spike words
     uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
@@ -187,6 +190,7 @@ struct PropArgs {
     uint32_t *awcnt;         // [2][n_segs], the slot of this step is cleared here
     uint32_t *scnt;          // [2][n_segs], likewise
     const int32_t *awl;      // [2][n_waves]
+    const uint32_t *gwsel;   // [2][n_segs]  words per group of each pre population
     int32_t n_segs;
     const int4 *units;       // tile mode: reduction units (projection, tile, first column, first group)
     int64_t n_units;

@@ -10,7 +10,7 @@
 //  k_propagate_tiles (dense activity) persistent grid of independent
 //               wavefronts, one per work item =
 //               (projection, post tile, group of active 64-neuron spike words
-//               of the pre population).  The wavefront walks the row slices
+//               of the pre population; only a group's first word emits).  The wavefront walks the row slices
 //               of the group's spiking rows in the Compressed Row Storage
 //               arrays (Section 3), packed several rows to a batch of loads,
 //               and adds the weights into its own LDS tile (columns within a
@@ -133,13 +133,22 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             // the word is active: record it, and queue one propagation item
             // per (outgoing projection, post tile) for the next step
             if (lane == 0) {
+                const uint32_t words = (uint32_t)((S.n + kWave - 1) / kWave);
                 wslot = atomicAdd(&a.awcnt[cur * a.n_segs + sidx], 1u);
                 // a slot beyond the population's word count can only come
                 // from repeating one step's update (kernel timing): no items
-                if (wslot < (uint32_t)((S.n + kWave - 1) / kWave)) {
+                if (wslot < words) {
                     a.awl[(int64_t)cur * a.n_waves + S.base / kWave + wslot] = (int32_t)(gw - S.base / kWave);
                     atomicAdd(&a.scnt[cur * a.n_segs + sidx], (uint32_t)__popcll(ball));
-                    for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
+                    // words per group from the previous step's counts (the
+                    // same for every wave of the population); only the first
+                    // word of a group emits the group's items
+                    const int pv = cur ^ 1;
+                    const uint32_t gws = group_words(min(a.awcnt[pv * a.n_segs + sidx], words),
+                                                     a.scnt[pv * a.n_segs + sidx], words);
+                    a.gwsel[cur * a.n_segs + sidx] = gws;
+                    if (wslot % gws == 0)
+                        for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
                 }
             }
         }
@@ -482,7 +491,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) continue;   // malformed item
         // the item of the first slot of each group processes the whole group
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
-        const uint32_t gw = group_words(na, a.scnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
         if ((uint32_t)slot % gw != 0 || (uint32_t)slot >= na) continue;
         const uint32_t group = (uint32_t)slot / gw;
         const uint32_t nwords = min(gw, na - (uint32_t)slot);
@@ -647,7 +656,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
         const Proj &P = a.projs[proj];
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         if (na == 0) continue;
-        const uint32_t gw = group_words(na, a.scnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+        const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
         const uint32_t ng = (na + gw - 1) / gw;
         if (chunk >= ng) continue;
         const uint32_t ge = min(ng, chunk + (uint32_t)kWave);

@@ -126,6 +126,7 @@ struct snn_net {
     uint32_t *awcnt;     // arena: [2][n_segs]
     uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
+    uint32_t *gwsel;     // arena: [2][n_segs]  words per group chosen at emission
     float *d_w;
     float *d_gscale;
     int64_t w_count;
@@ -264,6 +265,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.awcnt = net->awcnt;
     a.scnt = net->scnt;
     a.awl = net->awl;
+    a.gwsel = net->gwsel;
     a.n_segs = (int32_t)net->segs.size();
     return a;
 }
@@ -293,6 +295,7 @@ PropArgs prop_args(snn_net *net)
     p.awcnt = net->awcnt;
     p.scnt = net->scnt;
     p.awl = net->awl;
+    p.gwsel = net->gwsel;
     p.n_segs = (int32_t)net->segs.size();
     return p;
 }
@@ -763,6 +766,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_awcnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_scnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_awl = part(2 * W * 4);
+    Part p_gws = part(2 * (int64_t)net->segs.size() * 4);
     net->arena_bytes = off;
     net->d_arena = (char *)dev_alloc(net, (size_t)off);
     net->d_segs = (Seg *)dev_alloc(net, sizeof(Seg) * net->segs.size());
@@ -813,6 +817,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->awcnt = (uint32_t *)(A + p_awcnt.off);
     net->scnt = (uint32_t *)(A + p_scnt.off);
     net->awl = (int32_t *)(A + p_awl.off);
+    net->gwsel = (uint32_t *)(A + p_gws.off);
 
     // ---- uploads
     auto up = [&](void *dst, const void *src, size_t bytes) -> int {
@@ -1119,10 +1124,20 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     std::vector<uint64_t> all(net->n_waves);
     if ((rc = d2h(net, all.data(), net->bits + slot * net->n_waves, 8 * (size_t)net->n_waves))) return rc;
     const size_t nseg = net->segs.size();
-    std::vector<uint32_t> cnt(nseg, 0), spk(nseg, 0);
+    std::vector<uint32_t> cnt(nseg, 0), spk(nseg, 0), gws(nseg, 1);
     std::vector<int32_t> awl(net->n_waves, 0);
     std::vector<Item> items;
     const int32_t ch = net->launch.chunk;
+    // tile mode: words per group from this step's own counts (the kernels
+    // use whatever the emission recorded), items from each group's first word
+    for (size_t g = 0; g < nseg; ++g) {
+        const Seg &G = net->segs[g];
+        const int64_t w0 = G.base / kWave, nwd = align_up(G.n, kWave) / kWave;
+        uint32_t na = 0, ns = 0;
+        for (int64_t w = 0; w < nwd; ++w)
+            if (all[w0 + w]) ++na, ns += (uint32_t)__builtin_popcountll(all[w0 + w]);
+        gws[g] = group_words(na, ns, (uint32_t)nwd);
+    }
     for (size_t g = 0; g < nseg; ++g) {
         const Seg &G = net->segs[g];
         const int64_t w0 = G.base / kWave, gw = align_up(G.n, kWave) / kWave;
@@ -1134,6 +1149,7 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
             spk[g] += (uint32_t)__builtin_popcountll(bits);
             for (int o = 0; o < G.n_out; ++o) {
                 if (net->launch.mode == kModeTiles) {
+                    if ((uint32_t)slot_w % gws[g] != 0) continue;
                     for (int32_t tl = 0; tl < G.out_tiles[o]; ++tl)
                         items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot_w, bits, 0});
                 } else {
@@ -1155,6 +1171,7 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     if ((rc = h2d(net, net->awcnt + (int64_t)(slot ^ 1) * nseg, zero.data(), 4 * nseg))) return rc;
     if ((rc = h2d(net, net->scnt + (int64_t)(slot ^ 1) * nseg, zero.data(), 4 * nseg))) return rc;
     if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
+    if ((rc = h2d(net, net->gwsel + (int64_t)slot * nseg, gws.data(), 4 * nseg))) return rc;
     st.qcnt[slot] = (uint32_t)items.size();
     if (ltp_seg >= 0) {
         const Seg &S = net->segs[ltp_seg];
