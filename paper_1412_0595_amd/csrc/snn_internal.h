@@ -117,8 +117,6 @@ struct StepState {
     uint32_t qcnt[2];    // propagation work items produced at step t (slot t & 1)
     uint32_t lcnt[2];    // potentiation work items produced at step t
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
-    uint32_t pclaim;     // tile-mode items claimed so far in the running propagation
-    uint32_t pdone;      // its wavefronts that found no item left; the last resets both
     uint32_t pad_;
 };
 // Per step slot and population, how many of its spike words held a spike

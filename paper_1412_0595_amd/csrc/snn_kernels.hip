@@ -472,16 +472,10 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
     const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
     const Item *q = a.queue + (int64_t)prev * a.qcap;
+    const uint32_t nw = gridDim.x * kPropWaves;
     long long *acc = s_acc[wid];
-    // Items are claimed one at a time from a counter, so a wavefront that
-    // finishes a short item takes the next one (items differ widely in size).
-    auto claim = [&]() -> uint32_t {
-        uint32_t v = 0;
-        if (lane == 0) v = atomicAdd(&a.st->pclaim, 1u);
-        return (uint32_t)__builtin_amdgcn_readfirstlane(v);
-    };
 
-    for (uint32_t it = claim(); it < n; it = claim()) {
+    for (uint32_t it = blockIdx.x * kPropWaves + wid; it < n; it += nw) {
         const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
         const int32_t word0 = __builtin_amdgcn_readfirstlane(q[it].row);
         const int32_t tile = __builtin_amdgcn_readfirstlane(q[it].k0);
@@ -618,12 +612,6 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
         for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
         if (lane == 0) *flag = 1;
-    }
-    // every wavefront ends here once the items ran out; the last one resets
-    // the claim counter for the next launch (no wavefront waits on another)
-    if (lane == 0 && atomicAdd(&a.st->pdone, 1u) == gridDim.x * kPropWaves - 1) {
-        a.st->pclaim = 0;
-        a.st->pdone = 0;
     }
     if (blockIdx.x == 0) {
         // active-word and spike counts of the slot the next neuron update fills
