@@ -310,7 +310,9 @@ __device__ __forceinline__ void load_batch(BatchData &D, const Batch &B, const i
 {
 #pragma unroll
     for (int u = 0; u < kSlots; ++u) {
-        const int32_t kk = min(B.sk[u] + lane, B.se[u] - 1);
+        // an unsigned 32-bit index lets the load use a scalar base and a
+        // 32-bit lane offset (one VGPR per address instead of two)
+        const uint32_t kk = (uint32_t)min(B.sk[u] + lane, B.se[u] - 1);
         D.c[u] = col[kk] - c0;
         D.g[u] = w[kk];
     }
