@@ -329,6 +329,10 @@ def main():
         "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_bytes),
         "neuron": dict(ms=prof["neuron"][0], n=prof["neuron"][1], bytes=neuron_bytes * prof["neuron"][1]),
     }
+    if kern["propagate"]["n"] == 0:
+        # fused delivery: the neuron update walks the rows itself
+        kern["neuron"]["bytes"] += prop_bytes
+        del kern["propagate"]
     if prof["potentiate"][1]:
         kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1], bytes=0)
     # dominant = the larger share of kernel time over the profiled steps

@@ -155,7 +155,11 @@ typedef struct {
     int32_t chunk;          /* synapses per work item of a row or column walk, multiple of 64 */
     int32_t mode;           /* delivery: 0 rows (a wavefront per row chunk, atomics into G;
                                sparse activity), 1 tiles (a wavefront per post tile and group of
-                               active spike words, LDS accumulation; dense activity) */
+                               active spike words, LDS accumulation; dense activity), 2 fused
+                               (no propagation kernel: each neuron-update block delivers its
+                               own spikes' row chunks with atomics into a double-buffered
+                               delivery buffer that the next update adds to G; only for
+                               networks without plastic projections) */
 } snn_launch;
 
 /* Fill p[0..6] with the Traub-Miles parameters (7.15 uS, 50 mV, 1.43 uS,
@@ -242,7 +246,11 @@ int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out);
  * n_pre + 1 entries (host int64[total projections, instance-major]). */
 int snn_memory_bytes(const snn_net *net, int64_t *per_proj_bytes);
 
-/* Current / new launch shape; snn_set_launch validates the ranges above. */
+/* Current / new launch shape; snn_set_launch validates the ranges above
+ * (SNN_EINVAL, also for mode 2 on a network with plastic projections).  A
+ * change of mode converts the work pending for the next step (delivers it
+ * now, or folds fused deliveries into G); results are unchanged.
+ * Synchronises when the mode changes. */
 int snn_get_launch(const snn_net *net, snn_launch *out);
 int snn_set_launch(snn_net *net, const snn_launch *in);
 
@@ -256,7 +264,8 @@ int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms);
  * `launches` back-to-back launches of that kernel alone on the net's
  * current state; the state is restored afterwards.  Propagation and
  * potentiation consume the same pending work items at every launch.
- * Synchronises. */
+ * SNN_ESTATE for the propagation (which 0) in mode 2 (fused), where the
+ * neuron update delivers.  Synchronises. */
 int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_per_launch);
 
 /* Advance the network by n_steps (1..100000) steps, exactly as snn_step

@@ -48,7 +48,12 @@ enum { kPoisson = 0, kHH = 1 };
 // rows = a work item per chunk of a spiking row, 64-bit atomics into G;
 // tiles = a work item per (projection, post tile, group of active spike
 // words), LDS tile accumulation and partial tiles summed by the neuron update.
-enum { kModeRows = 0, kModeTiles = 1 };
+enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
+// fused = no propagation kernel: each neuron-update block delivers its own
+// spikes' rows with 64-bit atomics into the delivery buffer D of the next
+// step (double-buffered), which the next update adds to G (networks without
+// plasticity).
+constexpr int kFusedCap = 512;     // chunks a block lists in LDS per round
 
 // One population of one instance; its neurons occupy the global ids
 // [base, base + n), base a multiple of 64, so a wavefront never spans two.
@@ -117,7 +122,7 @@ struct StepState {
     uint32_t qcnt[2];    // propagation work items produced at step t (slot t & 1)
     uint32_t lcnt[2];    // potentiation work items produced at step t
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
-    uint32_t pad_;
+    uint32_t fdone;      // fused mode: blocks of the running update that finished
 };
 // Per step slot and population, how many of its spike words held a spike
 // (active-word counts, [2][n_segs]) and which ([2][n_waves], population
@@ -159,7 +164,12 @@ struct NeuronArgs {
     int32_t substeps;
     double hs;               // dt / substeps
     StepState *st;
-    int32_t mode;            // kModeRows / kModeTiles
+    int32_t mode;            // kModeRows / kModeTiles / kModeFused
+    int64_t *D;              // fused: [2][G pool] deliveries for the next update
+    int64_t G_count;
+    const int32_t *col_pool;
+    const float *w_pool;
+    const float *gscale;
     uint32_t *gwsel;         // [2][n_segs]  words per group chosen at emission
     uint32_t *awcnt;         // [2][n_segs]  active spike words
     uint32_t *scnt;          // [2][n_segs]  spikes

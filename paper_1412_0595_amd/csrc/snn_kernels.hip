@@ -29,6 +29,66 @@
 
 namespace snn {
 
+__device__ __forceinline__ void slice_to_global(unsigned long long *G, const int32_t *col, const float *w,
+                                                int32_t k0, int32_t k1, double s, int lane);
+
+// ---------------------------------------------------------------------------
+// Fused delivery (end of the neuron update): the block lists the chunks of
+// its spiking neurons' outgoing rows in LDS (rounds of kFusedCap chunks; the
+// chunk count of the block is uniform, so every thread passes the same
+// barriers), its wavefronts take chunks from an LDS counter and add them with
+// 64-bit atomics into the delivery buffer of step t + 1.  Then each block
+// counts itself done; the last one advances the step counters, once every
+// block has read them (no block waits for another).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fused_delivery(const NeuronArgs &a, int64_t t, uint32_t (*s_woff)[2],
+                                               uint32_t &s_tot, uint32_t &s_pop, int4 *s_fl, int sidx, int32_t j,
+                                               uint32_t nq, uint32_t iq, int wid, int lane, int32_t ra0,
+                                               int32_t ra1, int32_t rb0, int32_t rb1)
+{
+    const uint32_t total = s_tot;
+    const int64_t dnext = (int64_t)((t + 1) & 1) * a.G_count;
+    const int32_t ch = a.chunk;
+    for (uint32_t r0 = 0; r0 < total; r0 += kFusedCap) {
+        if (nq) {
+            const Seg &S = a.segs[sidx];
+            uint32_t pos = s_woff[wid][0] + (iq - nq);      // this lane's first chunk in the block
+            auto list = [&](int o, int32_t q0, int32_t q1) {
+                for (int32_t k = q0; k < q1; k += ch, ++pos)
+                    if (pos >= r0 && pos < r0 + (uint32_t)kFusedCap)
+                        s_fl[pos - r0] = make_int4(S.out_proj[o], k, min(k + ch, q1), 0);
+            };
+            if (S.n_out > 0) list(0, ra0, ra1);
+            if (S.n_out > 1) list(1, rb0, rb1);
+            for (int o = 2; o < S.n_out; ++o) {
+                const int32_t *rp = a.rp_pool + S.out_rp[o];
+                list(o, rp[j], rp[j + 1]);
+            }
+        }
+        if (threadIdx.x == 0) s_pop = 0;
+        __syncthreads();
+        const uint32_t n_round = min((uint32_t)kFusedCap, total - r0);
+        for (;;) {
+            uint32_t idx = 0;
+            if (lane == 0) idx = atomicAdd(&s_pop, 1u);
+            idx = (uint32_t)__builtin_amdgcn_readfirstlane(idx);
+            if (idx >= n_round) break;
+            const int32_t proj = __builtin_amdgcn_readfirstlane(s_fl[idx].x);
+            const int32_t k0 = __builtin_amdgcn_readfirstlane(s_fl[idx].y);
+            const int32_t k1 = __builtin_amdgcn_readfirstlane(s_fl[idx].z);
+            const Proj &P = a.projs[proj];
+            slice_to_global((unsigned long long *)(a.D + dnext + P.G_base), a.col_pool + P.syn_base,
+                            a.w_pool + P.syn_base, k0, k1, (double)a.gscale[P.inst] * kFixOne, lane);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && atomicAdd(&a.st->fdone, 1u) == gridDim.x - 1) {
+        a.st->fdone = 0;
+        a.st->t_prop = t + 1;
+        a.st->t_neuron = t + 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Neuron update + spike compaction
 // ---------------------------------------------------------------------------
@@ -36,6 +96,8 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 {
     __shared__ uint32_t s_woff[16][2];
     __shared__ uint32_t s_base[2];
+    __shared__ uint32_t s_tot, s_pop;            // fused: chunks of the block, next to take
+    __shared__ int4 s_fl[kFusedCap];             // fused: (projection, k0, k1, -) per chunk
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x >> 6;
@@ -87,11 +149,16 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             double h = pair_load(a.hh, a.hl, gid);
             double n = pair_load(a.nh, a.nl, gid);
             const double v0 = v;
-            // delivered conductance (both delivery modes leave it in G)
+            // delivered conductance: in G (rows and tile modes), G plus this
+            // step's slot of the delivery buffer (fused mode)
+            const int64_t dcur = (int64_t)cur * a.G_count;
             int64_t g[kMaxIn];
 #pragma unroll
             for (int q = 0; q < kMaxIn; ++q)
-                if (q < S.n_in) g[q] = a.G[S.in_G[q] + jj];
+                if (q < S.n_in) {
+                    g[q] = a.G[S.in_G[q] + jj];
+                    if (a.mode == kModeFused) g[q] += a.D[dcur + S.in_G[q] + jj];
+                }
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
             const double iin = syn_current(S, g, v0);
@@ -100,7 +167,10 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             if (active) {
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
-                    if (q < S.n_in) a.G[S.in_G[q] + j] = fix_decay(g[q], S.in_decay[q]);
+                    if (q < S.n_in) {
+                        a.G[S.in_G[q] + j] = fix_decay(g[q], S.in_decay[q]);
+                        if (a.mode == kModeFused) a.D[dcur + S.in_G[q] + j] = 0;
+                    }
                 spike = (v0 < 0.0) && (v >= 0.0);
                 pair_split(v, a.vh[gid], a.vl[gid]);
                 pair_split(m, a.mh[gid], a.ml[gid]);
@@ -155,8 +225,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         if (ball != 0 && spike) {
             a.counts[gid] = cnt + 1;
             const uint32_t ch = (uint32_t)a.chunk;
-            if (a.mode == kModeRows) {
-                // one propagation item per chunk of each outgoing row
+            if (a.mode != kModeTiles) {
+                // one propagation item (fused: one chunk) per chunk of each
+                // outgoing row
                 if (S.n_out > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
                 if (S.n_out > 1) nq += ((uint32_t)(rb1 - rb0) + ch - 1) / ch;
                 for (int o = 2; o < S.n_out; ++o) {
@@ -190,14 +261,17 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             sq += tq;
             sl += tl;
         }
-        s_base[0] = sq ? atomicAdd(&a.st->qcnt[cur], sq) : 0u;
-        s_base[1] = sl ? atomicAdd(&a.st->lcnt[cur], sl) : 0u;
-        if (sq && (int64_t)s_base[0] + sq > a.qcap) atomicOr(&a.st->overflow, 1u);
-        if (sl && (int64_t)s_base[1] + sl > a.lcap) atomicOr(&a.st->overflow, 2u);
-        if (blockIdx.x == 0) {
-            a.st->qcnt[cur ^ 1] = 0;    // consumed by this step's propagation
-            a.st->lcnt[cur ^ 1] = 0;
-            a.st->t_prop = t + 1;
+        s_tot = sq;
+        if (a.mode != kModeFused) {
+            s_base[0] = sq ? atomicAdd(&a.st->qcnt[cur], sq) : 0u;
+            s_base[1] = sl ? atomicAdd(&a.st->lcnt[cur], sl) : 0u;
+            if (sq && (int64_t)s_base[0] + sq > a.qcap) atomicOr(&a.st->overflow, 1u);
+            if (sl && (int64_t)s_base[1] + sl > a.lcap) atomicOr(&a.st->overflow, 2u);
+            if (blockIdx.x == 0) {
+                a.st->qcnt[cur ^ 1] = 0;    // consumed by this step's propagation
+                a.st->lcnt[cur ^ 1] = 0;
+                a.st->t_prop = t + 1;
+            }
         }
     }
     __syncthreads();
@@ -248,6 +322,8 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 if (pos < a.lcap) ld[pos] = Item{S.ltp_proj[o], j, k, min(k + ch, k1), 0, 0};
         }
     }
+    if (a.mode == kModeFused) fused_delivery(a, t, s_woff, s_tot, s_pop, s_fl, sidx, j, nq, iq, wid, lane,
+                                             ra0, ra1, rb0, rb1);
 }
 
 // A batch of up to kSlots slots of kWave consecutive synapses each, packed

@@ -127,6 +127,7 @@ struct snn_net {
     uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
     uint32_t *gwsel;     // arena: [2][n_segs]  words per group chosen at emission
+    int64_t *D;          // arena: [2][G pool]  fused-mode deliveries for the next update
     float *d_w;
     float *d_gscale;
     int64_t w_count;
@@ -266,6 +267,11 @@ NeuronArgs neuron_args(snn_net *net)
     a.scnt = net->scnt;
     a.awl = net->awl;
     a.gwsel = net->gwsel;
+    a.D = net->D;
+    a.G_count = net->G_count;
+    a.col_pool = net->d_col;
+    a.w_pool = net->d_w;
+    a.gscale = net->d_gscale;
     a.n_segs = (int32_t)net->segs.size();
     return a;
 }
@@ -317,6 +323,8 @@ LtpArgs ltp_args(snn_net *net)
 // Enqueue one whole step on stream s.
 hipError_t enqueue_step(snn_net *net, hipStream_t s)
 {
+    // fused mode: the neuron update delivers its own spikes
+    if (net->launch.mode == kModeFused) return launch_neuron(neuron_args(net), net->launch.neuron_block, s);
     hipError_t e = launch_propagate(prop_args(net), net->launch.prop_blocks, net->launch.prop_block, s);
     if (e != hipSuccess) return e;
     if (net->plastic) {
@@ -767,6 +775,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_scnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_awl = part(2 * W * 4);
     Part p_gws = part(2 * (int64_t)net->segs.size() * 4);
+    Part p_D = part(net->plastic ? 8 : 2 * std::max<int64_t>(G_total, 1) * 8);   // fused mode only
     net->arena_bytes = off;
     net->d_arena = (char *)dev_alloc(net, (size_t)off);
     net->d_segs = (Seg *)dev_alloc(net, sizeof(Seg) * net->segs.size());
@@ -818,6 +827,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->scnt = (uint32_t *)(A + p_scnt.off);
     net->awl = (int32_t *)(A + p_awl.off);
     net->gwsel = (uint32_t *)(A + p_gws.off);
+    net->D = (int64_t *)(A + p_D.off);
 
     // ---- uploads
     auto up = [&](void *dst, const void *src, size_t bytes) -> int {
@@ -1196,6 +1206,51 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     return h2d(net, net->st, &st, sizeof st);
 }
 
+// Fused -> rows/tiles: the pending deliveries of S(t-1) sit in the fused
+// buffer slot that the update of step t reads; add them into G, clear the
+// slot, and leave the next propagation's queue empty.
+static int leave_fused(snn_net *net)
+{
+    int rc;
+    const int64_t n = net->G_count;
+    const int64_t dslot = net->t & 1;
+    if (n > 0) {
+        std::vector<int64_t> g(n), d(n);
+        if ((rc = d2h(net, g.data(), net->G, 8 * (size_t)n))) return rc;
+        if ((rc = d2h(net, d.data(), net->D + dslot * n, 8 * (size_t)n))) return rc;
+        for (int64_t i = 0; i < n; ++i) g[i] += d[i];
+        std::fill(d.begin(), d.end(), 0);
+        if ((rc = h2d(net, net->G, g.data(), 8 * (size_t)n))) return rc;
+        if ((rc = h2d(net, net->D + dslot * n, d.data(), 8 * (size_t)n))) return rc;
+    }
+    const int qslot = (int)((net->t + 1) & 1);
+    StepState st;
+    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
+    st.qcnt[qslot] = 0;
+    st.lcnt[qslot] = 0;
+    const size_t nseg = net->segs.size();
+    std::vector<uint32_t> zero(2 * nseg, 0);
+    if ((rc = h2d(net, net->awcnt, zero.data(), 4 * zero.size()))) return rc;
+    if ((rc = h2d(net, net->scnt, zero.data(), 4 * zero.size()))) return rc;
+    return h2d(net, net->st, &st, sizeof st);
+}
+
+// Deliver the queued work of S(t-1) now with the rows or tile kernels (the
+// mode the queue was laid out for); the fused buffer stays clear.
+static int deliver_queued(snn_net *net, int mode)
+{
+    const snn_launch keep = net->launch;
+    net->launch.mode = mode;
+    hipError_t e = launch_propagate(prop_args(net), net->launch.prop_blocks, net->launch.prop_block, net->stream);
+    net->launch = keep;
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) {
+        net->sticky = true;
+        return fail(SNN_EDEVICE, "delivery of the pending work failed: %s", hipGetErrorString(e));
+    }
+    return SNN_OK;
+}
+
 // Replace S(t-1) of one population: rewrite its bitmask words and rebuild
 // the pending work (propagation of every population, potentiation of this
 // population's columns).
@@ -1213,7 +1268,19 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
     for (int i = 0; i < S.n; ++i)
         if (in[i]) words[i / kWave] |= (uint64_t)1 << (i % kWave);
     if ((rc = h2d(net, net->bits + slot * net->n_waves + S.base / kWave, words.data(), 8 * (size_t)nw))) return rc;
-    return rebuild_pending(net, s, in);
+    if (net->launch.mode != kModeFused) return rebuild_pending(net, s, in);
+    // fused mode: drop the pending deliveries of the old S(t-1) and deliver
+    // the new S(t-1) of every population into G through a rows-mode queue
+    const int64_t n = net->G_count;
+    if (n > 0) {
+        std::vector<int64_t> zero(n, 0);
+        if ((rc = h2d(net, net->D + (net->t & 1) * n, zero.data(), 8 * (size_t)n))) return rc;
+    }
+    net->launch.mode = kModeRows;
+    rc = rebuild_pending(net, -1, nullptr);
+    net->launch.mode = kModeFused;
+    if (rc) return rc;
+    return deliver_queued(net, kModeRows);
 }
 
 int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out)
@@ -1309,11 +1376,22 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
     if (in->prop_blocks < 1 || in->prop_blocks > 65536) return fail(SNN_EINVAL, "prop_blocks must be in [1, 65536]");
     if (in->chunk < kMinChunk || in->chunk % kWave || in->chunk > (1 << 20))
         return fail(SNN_EINVAL, "chunk must be a multiple of 64 in [64, 2^20]");
-    if (in->mode != kModeRows && in->mode != kModeTiles) return fail(SNN_EINVAL, "mode must be 0 (rows) or 1 (tiles)");
-    const bool remake = in->mode != net->launch.mode;
+    if (in->mode != kModeRows && in->mode != kModeTiles && in->mode != kModeFused)
+        return fail(SNN_EINVAL, "mode must be 0 (rows), 1 (tiles) or 2 (fused)");
+    if (in->mode == kModeFused && net->plastic)
+        return fail(SNN_EINVAL, "mode 2 (fused) needs a network without plastic projections");
+    const int old = net->launch.mode;
     net->launch = *in;
     // the pending work of the next step was laid out for the old mode
-    if (remake && (rc = rebuild_pending(net, -1, nullptr))) return rc;
+    if (old != in->mode) {
+        if (in->mode == kModeFused)
+            rc = deliver_queued(net, old);
+        else if (old == kModeFused)
+            rc = leave_fused(net);
+        else
+            rc = rebuild_pending(net, -1, nullptr);
+        if (rc) return rc;
+    }
     if (net->graph_exec) {
         (void)hipGraphExecDestroy(net->graph_exec);
         net->graph_exec = nullptr;
@@ -1341,6 +1419,8 @@ int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_pe
     if (rc) return rc;
     if (which < 0 || which > 2) return fail(SNN_EINVAL, "which must be 0, 1 or 2");
     if (which == 1 && !net->plastic) return fail(SNN_ESTATE, "no plastic projection");
+    if (which == 0 && net->launch.mode == kModeFused)
+        return fail(SNN_ESTATE, "mode 2 (fused) has no propagation kernel");
     if (launches < 1 || launches > 1000000 || !ms_per_launch) return fail(SNN_EINVAL, "need 1 <= launches <= 1e6 and an output");
     PropArgs p = prop_args(net);
     LtpArgs l = ltp_args(net);
@@ -1369,7 +1449,8 @@ int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *
     if (rc) return rc;
     if (n_steps < 1 || n_steps > 100000 || !ms_total || !launches)
         return fail(SNN_EINVAL, "need 1 <= n_steps <= 100000 and two output arrays");
-    const int per_step = net->plastic ? 3 : 2;
+    const bool fused = net->launch.mode == kModeFused;
+    const int per_step = fused ? 1 : net->plastic ? 3 : 2;
     std::vector<hipEvent_t> ev((size_t)(2 * per_step * n_steps), nullptr);
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
@@ -1379,6 +1460,11 @@ int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *
     int64_t done = 0;
     for (; done < n_steps && e == hipSuccess; ++done) {
         hipEvent_t *E = ev.data() + 2 * per_step * done;
+        if (fused) {
+            e = launch_neuron(a, net->launch.neuron_block, net->stream, E[0], E[1]);
+            if (e == hipSuccess) net->t += 1;
+            continue;
+        }
         e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream, E[0], E[1]);
         if (e == hipSuccess && net->plastic)
             e = launch_potentiate(l, net->launch.prop_blocks, net->launch.prop_block, net->stream, E[4], E[5]);
@@ -1392,7 +1478,7 @@ int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *
         for (int k = 0; k < per_step && e == hipSuccess; ++k) {
             float ms = 0.0f;
             e = hipEventElapsedTime(&ms, E[2 * k], E[2 * k + 1]);
-            const int which = k == 0 ? 0 : k == 1 ? 2 : 1;
+            const int which = fused ? 2 : k == 0 ? 0 : k == 1 ? 2 : 1;
             ms_total[which] += (double)ms;
             launches[which] += 1;
         }
@@ -1685,13 +1771,13 @@ int snn_autotune_internal(snn_net *net, const char *cache)
     int rc = snn_time_steps(net, steps, &best_ms);   // also warms up
     if (rc) return rc;
     if ((rc = snn_time_steps(net, steps, &best_ms))) return rc;
-    const int md[] = {kModeRows, kModeTiles};
+    const int md[] = {kModeRows, kModeTiles, kModeFused};
     const int nb[] = {64, 128, 256, 512, 1024};
     const int pb[] = {256, 512, 1024, 2048, 4096, 8192};
     const int ck[] = {128, 256, 512, 1024, 2048};
     for (int dim = 0; dim < 4; ++dim) {
         const int *vals = dim == 0 ? md : dim == 1 ? nb : dim == 2 ? pb : ck;
-        const int nv = dim == 0 ? 2 : dim == 1 ? 5 : dim == 2 ? 6 : 5;
+        const int nv = dim == 0 ? (net->plastic ? 2 : 3) : dim == 1 ? 5 : dim == 2 ? 6 : 5;
         snn_launch cur_best = best;
         for (int k = 0; k < nv; ++k) {
             snn_launch L = best;

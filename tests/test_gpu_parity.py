@@ -328,6 +328,69 @@ def test_delivery_modes_agree_bitwise_with_switches(snn, workload, scale):
     b.close()
 
 
+def _same_network_state(a, b, spec):
+    inst = spec["instances"][0]
+    for p in range(len(inst["pops"])):
+        assert np.array_equal(a.spikes(0, p), b.spikes(0, p))
+        assert np.array_equal(a.last_spikes(0, p), b.last_spikes(0, p))
+        if inst["pops"][p]["kind"] == "hh":
+            for var in range(4):
+                assert np.array_equal(a.state(0, p, var), b.state(0, p, var))
+    for q in range(len(inst["projs"])):
+        assert np.array_equal(a.conductance(0, q), b.conductance(0, q))
+
+
+@pytest.mark.parametrize("workload,scale", [(1, 0.5), (2, 0.25)])
+def test_fused_mode_agrees_bitwise_through_switches(snn, workload, scale):
+    """Mode 2 (the neuron update delivers its own spikes into a double-buffered
+    delivery buffer) gives the same bits as row mode, also across switches in
+    every direction with work pending, with odd step counts (both buffer
+    slots) and several launch shapes."""
+    say(f"case: fused mode, workload {workload} at scale {scale}")
+    spec = netgen.make_config(workload, scale=scale)
+    ref = snn.Network(spec)
+    fus = snn.Network(spec)
+    fus.set_launch(mode=2)
+    plan = [(77, dict(mode=2)), (51, dict(mode=1)), (33, dict(mode=2, neuron_block=64, chunk=64)),
+            (41, dict(mode=0)), (29, dict(mode=2, neuron_block=1024, chunk=2048)), (64, dict(mode=2, chunk=512))]
+    for n, shape in plan:
+        ref.step(n)
+        fus.step(n)
+        _same_network_state(ref, fus, spec)
+        fus.set_launch(**shape)
+    ref.step(70)
+    fus.step(70)
+    _same_network_state(ref, fus, spec)
+    ref.close()
+    fus.close()
+
+
+def test_fused_mode_last_spikes_and_rejection(snn):
+    """Replacing S(t-1) in fused mode redoes its pending deliveries; a
+    network with plastic projections refuses mode 2."""
+    say("case: fused mode, set_last_spikes and plastic rejection")
+    spec = netgen.make_config(1, scale=0.5)
+    a = snn.Network(spec)
+    b = snn.Network(spec)
+    b.set_launch(mode=2)
+    a.step(40)
+    b.step(40)
+    rng = np.random.default_rng(3)
+    for p, pop in enumerate(spec["instances"][0]["pops"]):
+        f = (rng.random(pop["n"]) < 0.3).astype(np.uint8)
+        a.set_last_spikes(0, p, f)
+        b.set_last_spikes(0, p, f)
+    a.step(60)
+    b.step(60)
+    _same_network_state(a, b, spec)
+    a.close()
+    b.close()
+    plastic = snn.Network(netgen.make_config(3, scale=0.05))
+    with pytest.raises(RuntimeError, match="fused"):
+        plastic.set_launch(mode=2)
+    plastic.close()
+
+
 def test_vbar_accumulates_post_step_voltage(snn):
     say("case: vbar")
     spec = netgen.make_config(1, scale=0.3)
