@@ -1206,6 +1206,18 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     return h2d(net, net->st, &st, sizeof st);
 }
 
+// Both queue slots empty: fused steps neither fill nor reset them, so a count
+// left from before fused mode must not survive a switch in either direction.
+static int clear_queues(snn_net *net)
+{
+    int rc;
+    StepState st;
+    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
+    st.qcnt[0] = st.qcnt[1] = 0;
+    st.lcnt[0] = st.lcnt[1] = 0;
+    return h2d(net, net->st, &st, sizeof st);
+}
+
 // Fused -> rows/tiles: the pending deliveries of S(t-1) sit in the fused
 // buffer slot that the update of step t reads; add them into G, clear the
 // slot, and leave the next propagation's queue empty.
@@ -1223,32 +1235,38 @@ static int leave_fused(snn_net *net)
         if ((rc = h2d(net, net->G, g.data(), 8 * (size_t)n))) return rc;
         if ((rc = h2d(net, net->D + dslot * n, d.data(), 8 * (size_t)n))) return rc;
     }
-    const int qslot = (int)((net->t + 1) & 1);
-    StepState st;
-    if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
-    st.qcnt[qslot] = 0;
-    st.lcnt[qslot] = 0;
+    if ((rc = clear_queues(net))) return rc;
     const size_t nseg = net->segs.size();
     std::vector<uint32_t> zero(2 * nseg, 0);
     if ((rc = h2d(net, net->awcnt, zero.data(), 4 * zero.size()))) return rc;
-    if ((rc = h2d(net, net->scnt, zero.data(), 4 * zero.size()))) return rc;
-    return h2d(net, net->st, &st, sizeof st);
+    return h2d(net, net->scnt, zero.data(), 4 * zero.size());
 }
 
-// Deliver the queued work of S(t-1) now with the rows or tile kernels (the
-// mode the queue was laid out for); the fused buffer stays clear.
-static int deliver_queued(snn_net *net, int mode)
+// Entering fused mode (or replacing S(t-1) in it): the pending deliveries of
+// S(t-1) belong in the fused buffer slot that the update of step t reads.
+// Clear that slot, then run the queued work (laid out for `mode`, rows or
+// tiles) with that slot as its target instead of G, and empty the queues.
+static int deliver_queued_to_fused(snn_net *net, int mode)
 {
+    int rc;
+    const int64_t n = net->G_count;
+    int64_t *slot = net->D + (net->t & 1) * n;
+    if (n > 0) {
+        std::vector<int64_t> zero(n, 0);
+        if ((rc = h2d(net, slot, zero.data(), 8 * (size_t)n))) return rc;
+    }
     const snn_launch keep = net->launch;
     net->launch.mode = mode;
-    hipError_t e = launch_propagate(prop_args(net), net->launch.prop_blocks, net->launch.prop_block, net->stream);
+    PropArgs p = prop_args(net);
     net->launch = keep;
+    p.G = slot;
+    hipError_t e = launch_propagate(p, net->launch.prop_blocks, net->launch.prop_block, net->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
     if (e != hipSuccess) {
         net->sticky = true;
         return fail(SNN_EDEVICE, "delivery of the pending work failed: %s", hipGetErrorString(e));
     }
-    return SNN_OK;
+    return clear_queues(net);
 }
 
 // Replace S(t-1) of one population: rewrite its bitmask words and rebuild
@@ -1269,18 +1287,13 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
         if (in[i]) words[i / kWave] |= (uint64_t)1 << (i % kWave);
     if ((rc = h2d(net, net->bits + slot * net->n_waves + S.base / kWave, words.data(), 8 * (size_t)nw))) return rc;
     if (net->launch.mode != kModeFused) return rebuild_pending(net, s, in);
-    // fused mode: drop the pending deliveries of the old S(t-1) and deliver
-    // the new S(t-1) of every population into G through a rows-mode queue
-    const int64_t n = net->G_count;
-    if (n > 0) {
-        std::vector<int64_t> zero(n, 0);
-        if ((rc = h2d(net, net->D + (net->t & 1) * n, zero.data(), 8 * (size_t)n))) return rc;
-    }
+    // fused mode: the pending deliveries become those of the new S(t-1) of
+    // every population, laid out as a rows-mode queue and run into the slot
     net->launch.mode = kModeRows;
     rc = rebuild_pending(net, -1, nullptr);
     net->launch.mode = kModeFused;
     if (rc) return rc;
-    return deliver_queued(net, kModeRows);
+    return deliver_queued_to_fused(net, kModeRows);
 }
 
 int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out)
@@ -1385,7 +1398,7 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
     // the pending work of the next step was laid out for the old mode
     if (old != in->mode) {
         if (in->mode == kModeFused)
-            rc = deliver_queued(net, old);
+            rc = deliver_queued_to_fused(net, old);
         else if (old == kModeFused)
             rc = leave_fused(net);
         else

@@ -353,9 +353,10 @@ def test_fused_mode_agrees_bitwise_through_switches(snn, workload, scale):
     fus.set_launch(mode=2)
     plan = [(77, dict(mode=2)), (51, dict(mode=1)), (33, dict(mode=2, neuron_block=64, chunk=64)),
             (41, dict(mode=0)), (29, dict(mode=2, neuron_block=1024, chunk=2048)), (64, dict(mode=2, chunk=512))]
-    for n, shape in plan:
+    for i, (n, shape) in enumerate(plan):
         ref.step(n)
         fus.step(n)
+        say(f"  phase {i}: {n} steps in mode {fus.launch['mode']}, then {shape}")
         _same_network_state(ref, fus, spec)
         fus.set_launch(**shape)
     ref.step(70)
