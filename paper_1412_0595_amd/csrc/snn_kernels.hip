@@ -474,20 +474,62 @@ __device__ __forceinline__ void word_to_global(unsigned long long *G, const int3
     while (fill_batch(B, rem, k, k1, b0, b1)) atomics_from_batch(G, col, w, B.sk, B.se, B.ph, s, lane);
 }
 
-// One row slice [k0, k1) into G with atomics (rows mode), in full batches.
+// Loads of one full-width batch of the slice [kb, kb + 8*64) ∩ [., k1), at
+// indices clamped below k1 (always in bounds).
+struct SliceData {
+    int32_t c[kSlots];
+    float g[kSlots];
+};
+
+__device__ __forceinline__ void load_slice(SliceData &D, const int32_t *col, const float *w, int32_t kb, int32_t k1,
+                                           int lane)
+{
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const int32_t k = min(kb + u * kWave + lane, k1 - 1);
+        D.c[u] = col[k];
+        D.g[u] = w[k];
+    }
+}
+
+// The predicated atomics of a loaded batch; the empty asm consumes the loaded
+// registers first, so the wait covers this batch's loads only (the next
+// batch's, issued later, stay in flight).
+__device__ __forceinline__ void slice_atomics(unsigned long long *G, const SliceData &D, int32_t kb, int32_t k1,
+                                              double s, int lane)
+{
+    asm volatile("" ::"v"(D.c[0]), "v"(D.c[1]), "v"(D.c[2]), "v"(D.c[3]), "v"(D.c[4]), "v"(D.c[5]), "v"(D.c[6]),
+                 "v"(D.c[7]), "v"(D.g[0]), "v"(D.g[1]), "v"(D.g[2]), "v"(D.g[3]), "v"(D.g[4]), "v"(D.g[5]),
+                 "v"(D.g[6]), "v"(D.g[7]));
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u)
+        if (kb + u * kWave + lane < k1) atomicAdd(G + D.c[u], (unsigned long long)fix_increment(s, D.g[u]));
+}
+
+// One row slice [k0, k1) into G with atomics, in batches of 8 x 64 entries,
+// software-pipelined over two explicit buffers: the next batch's loads are in
+// flight while the current batch's atomics go out.  When there is no next
+// batch its buffer reloads the current range (in bounds, unused).
 __device__ __forceinline__ void slice_to_global(unsigned long long *G, const int32_t *col, const float *w,
                                                 int32_t k0, int32_t k1, double s, int lane)
 {
-    for (int32_t kb = k0; kb < k1; kb += kSlots * kWave) {
-        int32_t sk[kSlots], se[kSlots], ph[kSlots];
-#pragma unroll
-        for (int u = 0; u < kSlots; ++u) {
-            const bool used = kb + u * kWave < k1;
-            sk[u] = used ? kb + u * kWave : kb;
-            se[u] = k1;
-            ph[u] = used ? 0 : -1;
-        }
-        atomics_from_batch(G, col, w, sk, se, ph, s, lane);
+    if (k0 >= k1) return;
+    constexpr int32_t kStep = kSlots * kWave;
+    SliceData A, B;
+    int32_t ka = k0;
+    load_slice(A, col, w, ka, k1, lane);
+    for (;;) {
+        const int32_t kbn = ka + kStep;
+        const bool more_b = kbn < k1;
+        load_slice(B, col, w, more_b ? kbn : ka, k1, lane);
+        slice_atomics(G, A, ka, k1, s, lane);
+        if (!more_b) return;
+        const int32_t kan = kbn + kStep;
+        const bool more_a = kan < k1;
+        load_slice(A, col, w, more_a ? kan : kbn, k1, lane);
+        slice_atomics(G, B, kbn, k1, s, lane);
+        if (!more_a) return;
+        ka = kan;
     }
 }
 
