@@ -561,12 +561,29 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
         if (!P.stdp) {
             slice_to_global(G, col, w, k0, k1, s, lane);
         } else {
+            // batches of 8 x 64 entries at clamped indices: column and weight,
+            // then the post traces, then predicated atomics; the depressed
+            // weight is stored unpredicated (a clamped duplicate stores the
+            // same value as its slice's last entry)
             const float *y = a.trace + P.y_base;
-            for (int32_t k = k0 + lane; k < k1; k += kWave) {
-                const int32_t c = col[k];
-                const float gv = w[k];
-                atomicAdd(G + c, (unsigned long long)fix_increment(s, gv));
-                w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+            for (int32_t kb = k0; kb < k1; kb += kSlots * kWave) {
+                int32_t c[kSlots], kk[kSlots];
+                float g[kSlots], yv[kSlots];
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    kk[u] = min(kb + u * kWave + lane, k1 - 1);
+                    c[u] = col[kk[u]];
+                    g[u] = w[kk[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) yv[u] = y[c[u]];
+                asm volatile("" ::"v"(yv[0]), "v"(yv[1]), "v"(yv[2]), "v"(yv[3]), "v"(yv[4]), "v"(yv[5]),
+                             "v"(yv[6]), "v"(yv[7]));
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    w[kk[u]] = fmaxf(0.0f, g[u] - P.a_minus_gmax * yv[u]);
+                    if (kb + u * kWave + lane < k1) atomicAdd(G + c[u], (unsigned long long)fix_increment(s, g[u]));
+                }
             }
         }
     }
@@ -718,13 +735,30 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                 const int r = __builtin_ctzll(bits);
                 bits &= bits - 1;
                 const int32_t k0 = __shfl(b0, r, kWave), k1 = __shfl(b1, r, kWave);
-                {
-                    const float *y = a.trace + P.y_base;
-                    for (int32_t k = k0 + lane; k < k1; k += kWave) {
-                        const int32_t c = col[k];
-                        const float gv = w[k];
-                        acc[c - c0] += fix_increment(s, gv);
-                        w[k] = fmaxf(0.0f, gv - P.a_minus_gmax * y[c]);
+                // batches of 8 x 64 entries of the row at clamped indices; all
+                // tile entries read before any is written (distinct columns);
+                // a clamped duplicate writes the same sum and the same
+                // depressed weight as the row's last entry
+                const float *y = a.trace + P.y_base;
+                for (int32_t kb = k0; kb < k1; kb += kSlots * kWave) {
+                    int32_t c[kSlots], kk[kSlots];
+                    float g[kSlots], yv[kSlots];
+                    long long v[kSlots];
+#pragma unroll
+                    for (int u = 0; u < kSlots; ++u) {
+                        kk[u] = min(kb + u * kWave + lane, k1 - 1);
+                        c[u] = col[kk[u]];
+                        g[u] = w[kk[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSlots; ++u) {
+                        yv[u] = y[c[u]];
+                        v[u] = acc[c[u] - c0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSlots; ++u) {
+                        acc[c[u] - c0] = v[u] + fix_increment(s, g[u]);
+                        w[kk[u]] = fmaxf(0.0f, g[u] - P.a_minus_gmax * yv[u]);
                     }
                 }
             }
@@ -812,9 +846,26 @@ __global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
         const int32_t *pos = a.csc_pos + P.csc_base;
         float *w = a.w_pool + P.syn_base;
         const float *x = a.trace + P.x_base;
-        for (int32_t k = k0 + lane; k < k1; k += kWave) {
-            const int32_t at = pos[k];
-            w[at] = fminf(P.g_max, w[at] + P.a_plus_gmax * x[rows[k]]);
+        // batches of 8 x 64 column entries at clamped indices: positions and
+        // rows, then the weights and pre traces, then the stores (a column
+        // lists each synapse once; a clamped duplicate stores the same value
+        // as the chunk's last entry)
+        for (int32_t kb = k0; kb < k1; kb += 8 * kWave) {
+            int32_t at[8], r[8];
+            float wv[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = min(kb + u * kWave + lane, k1 - 1);
+                at[u] = pos[k];
+                r[u] = rows[k];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                wv[u] = w[at[u]];
+                xv[u] = x[r[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w[at[u]] = fminf(P.g_max, wv[u] + P.a_plus_gmax * xv[u]);
         }
     }
 }
