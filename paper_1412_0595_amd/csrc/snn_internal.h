@@ -15,8 +15,8 @@ constexpr int kMaxLtp = 2;   // plastic projections arriving at one population
 constexpr int kMinChunk = 64;
 constexpr int kTileMax = 1024;  // post neurons per propagation tile (LDS accumulator width)
 constexpr int kPropWaves = 4;   // wavefronts per propagation block (one LDS tile copy each)
-constexpr int kMinGroups = 32;  // groups (partial tiles) per (projection, post tile) at least
-constexpr int kRowsPerGroup = 8;  // spiking rows per group aimed for when more groups are allowed
+constexpr int kMinGroups = 16;  // groups (partial tiles) per (projection, post tile) at least
+constexpr int kRowsPerGroup = 16;  // spiking rows per group aimed for when more groups are allowed
 
 // Active spike words of a pre population are processed in groups of
 // consecutive active-list slots: with na active words and `rows` spiking
