@@ -54,7 +54,6 @@ enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
 // step (double-buffered), which the next update adds to G (networks without
 // plasticity).
 constexpr int kFusedCap = 512;     // chunks a block lists in LDS per round
-constexpr int kSegTab = 32;        // segments the neuron update finds from its kernel arguments
 
 // One population of one instance; its neurons occupy the global ids
 // [base, base + n), base a multiple of 64, so a wavefront never spans two.
@@ -74,9 +73,6 @@ struct Seg {
     // outgoing projections: id, row-start array (pool offset), post tiles
     int32_t out_proj[kMaxOut];
     int64_t out_rp[kMaxOut];
-    int64_t out_syn[kMaxOut];   // synapse pool offset of each outgoing projection
-    int64_t out_G[kMaxOut];     // its conductance pool offset
-    int32_t out_stdp[kMaxOut];  // whether it is plastic
     int32_t out_tiles[kMaxOut];
     // plastic projections arriving here: id and column-start array
     int32_t ltp_proj[kMaxLtp];
@@ -140,27 +136,14 @@ struct StepState {
 // [k0, k1) of the column of post neuron `row` of plastic projection `proj`.
 struct Item {
     int32_t proj, row, k0, k1;
-    uint64_t bits;      // tile mode: the spike word itself; row mode, row < 0: the synapse pool offset
-    uint64_t pad_;      // row mode, row < 0: conductance pool offset (low 32 bits), g_scale (high 32)
+    uint64_t bits;      // propagation: the spike word itself
+    uint64_t pad_;
 };
-// A row-mode item of a non-plastic projection is self-contained (row = -1):
-// the propagation needs no projection record.
-__host__ __device__ inline uint64_t pack_gbase_gscale(int64_t G_base, float gscale)
-{
-    uint32_t gs;
-    __builtin_memcpy(&gs, &gscale, 4);
-    return (uint64_t)(uint32_t)G_base | ((uint64_t)gs << 32);
-}
 
 struct NeuronArgs {
     const Seg *segs;
     const int32_t *wave_seg;
     int64_t n_waves;
-    // networks of at most kSegTab non-empty segments: first wave and index of
-    // each, in the kernel arguments (saves the per-wave table lookup)
-    int32_t n_st;
-    int32_t st_wave[kSegTab];
-    int32_t st_seg[kSegTab];
     float *vh, *vl, *mh, *ml, *hh, *hl, *nh, *nl;
     int64_t *G;
     int32_t *counts;

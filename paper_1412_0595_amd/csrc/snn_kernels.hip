@@ -114,20 +114,10 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     int32_t j = 0;
     uint32_t cnt = 0;              // prefetched spike count
     int32_t ra0 = 0, ra1 = 0, rb0 = 0, rb1 = 0;   // prefetched rows of outgoing projections 0 and 1
-    float gsc = 0.0f;              // prefetched g_scale of the instance
     float trv[kMaxTr] = {};        // prefetched traces
 
     if (gw < a.n_waves) {
-        if (a.n_st > 0) {
-            // the last listed segment starting at or before this wave
-            int k = 0;
-#pragma unroll
-            for (int q = 1; q < kSegTab; ++q)
-                if (q < a.n_st && a.st_wave[q] <= gw) k = q;
-            sidx = a.st_seg[k];
-        } else {
-            sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[gw]);
-        }
+        sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[gw]);
         const Seg &S = a.segs[sidx];
         const int64_t gid = gw * kWave + lane;
         j = (int32_t)(gid - S.base);
@@ -139,7 +129,6 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         // that data and store nothing.
         const int32_t jj = active ? j : S.n - 1;
         cnt = a.counts[gid];
-        gsc = a.gscale[S.inst];
         {
             // (used in rows mode; a missing projection reads rp_pool[0..1])
             const int32_t *rpa = a.rp_pool + (S.n_out > 0 ? S.out_rp[0] + jj : 0);
@@ -292,13 +281,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         const int32_t ch = a.chunk;
         int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
-        // items of non-plastic projections carry their addressing (row -1)
         auto emit = [&](int o, int32_t r0, int32_t r1) {
-            const bool self = !S.out_stdp[o];
-            const uint64_t syn = self ? (uint64_t)S.out_syn[o] : 0ull;
-            const uint64_t gg = self ? pack_gbase_gscale(S.out_G[o], gsc) : 0ull;
             for (int32_t k = r0; k < r1; k += ch, ++pos)
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], self ? -1 : j, k, min(k + ch, r1), syn, gg};
+                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, r1), 0, 0};
         };
         if (S.n_out > 0) emit(0, ra0, ra1);
         if (S.n_out > 1) emit(1, rb0, rb1);
@@ -565,19 +550,8 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 
     for (; it < n; it += nw) {
         const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
-        const int32_t row = __builtin_amdgcn_readfirstlane(q[it].row);
         const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
         const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
-        if (row < 0) {
-            // self-contained item of a non-plastic projection
-            if (k0 < 0 || k0 > k1) continue;              // malformed item
-            const int64_t syn = (int64_t)uniform_u64(q[it].bits);
-            const uint64_t pk = uniform_u64(q[it].pad_);
-            const float gs = __uint_as_float((uint32_t)(pk >> 32));
-            slice_to_global((unsigned long long *)(a.G + (int64_t)(uint32_t)pk), a.col_pool + syn, a.w_pool + syn,
-                            k0, k1, (double)gs * kFixOne, lane);
-            continue;
-        }
         const Proj &P = a.projs[proj];
         if (k0 < 0 || k1 > P.nnz || k0 > k1) continue;   // malformed item
         const double s = (double)a.gscale[P.inst] * kFixOne;

@@ -241,18 +241,6 @@ NeuronArgs neuron_args(snn_net *net)
     a.segs = net->d_segs;
     a.wave_seg = net->d_wave_seg;
     a.n_waves = net->n_waves;
-    int n_st = 0;
-    for (size_t q = 0; q < net->segs.size(); ++q)
-        if (net->segs[q].n > 0) ++n_st;
-    a.n_st = 0;
-    if (n_st <= kSegTab) {
-        for (size_t q = 0; q < net->segs.size(); ++q)
-            if (net->segs[q].n > 0) {
-                a.st_wave[a.n_st] = (int32_t)(net->segs[q].base / kWave);
-                a.st_seg[a.n_st] = (int32_t)q;
-                ++a.n_st;
-            }
-    }
     a.vh = net->vh; a.vl = net->vl; a.mh = net->mh; a.ml = net->ml;
     a.hh = net->hh; a.hl = net->hl; a.nh = net->nh; a.nl = net->nl;
     a.G = net->G;
@@ -676,9 +664,6 @@ int snn_create(const snn_config *cfg, snn_net **out)
             post.n_in++;
             pre.out_proj[pre.n_out] = gi;
             pre.out_rp[pre.n_out] = P.rp_base;
-            pre.out_syn[pre.n_out] = P.syn_base;
-            pre.out_G[pre.n_out] = P.G_base;
-            pre.out_stdp[pre.n_out] = P.stdp;
             pre.out_tiles[pre.n_out] = P.n_tiles;
             pre.n_out++;
             HostProj H{};
@@ -729,8 +714,6 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->n_waves = base / kWave;
     net->w_count = syn_total;
     net->G_count = G_total;
-    // self-contained row items carry the conductance offset in 32 bits
-    if (G_total >= ((int64_t)1 << 32)) return bail(fail(SNN_ERANGE, "more than 2^32 conductances"));
     net->trace_count = tr_total;
 
     // work-queue capacity: every spike word active at once (one item per
@@ -1181,14 +1164,10 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
                         items.push_back(Item{G.out_proj[o], (int32_t)w, tl, slot_w, bits, 0});
                 } else {
                     const HostProj &H = net->hprojs[G.out_proj[o]];
-                    const bool self = !H.stdp;
-                    const uint64_t syn = self ? (uint64_t)H.syn_base : 0ull;
-                    const uint64_t gg = self ? pack_gbase_gscale(H.G_base, net->gscale[H.inst]) : 0ull;
                     for (uint64_t b = bits; b; b &= b - 1) {
                         const int32_t i = (int32_t)(w * kWave + __builtin_ctzll(b));
                         for (int32_t k = H.row_ptr[i]; k < H.row_ptr[i + 1]; k += ch)
-                            items.push_back(Item{G.out_proj[o], self ? -1 : i, k, std::min(k + ch, H.row_ptr[i + 1]),
-                                                 syn, gg});
+                            items.push_back(Item{G.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1]), 0, 0});
                     }
                 }
             }
@@ -1368,18 +1347,7 @@ int snn_set_gscale(snn_net *net, const float *per_instance)
     }
     if ((rc = check_range(net, bound, wbound, per_instance))) return rc;
     std::copy(per_instance, per_instance + net->n_inst, net->gscale.begin());
-    if ((rc = h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst))) return rc;
-    // the pending deliveries of S(t-1) take the new g_scale: row items carry
-    // it, fused deliveries were already made with the old one
-    if (net->launch.mode == kModeRows) return rebuild_pending(net, -1, nullptr);
-    if (net->launch.mode == kModeFused) {
-        net->launch.mode = kModeRows;
-        rc = rebuild_pending(net, -1, nullptr);
-        net->launch.mode = kModeFused;
-        if (rc) return rc;
-        return deliver_queued_to_fused(net, kModeRows);
-    }
-    return SNN_OK;
+    return h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst);
 }
 
 int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out)
