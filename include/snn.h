@@ -235,7 +235,10 @@ int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out);
  * a step and a non-finite V at its end (host int32[n_instances]). */
 int snn_get_nan_counts(snn_net *net, int32_t *per_instance);
 
-/* Replace every instance's g_scale (host float[n_instances], finite, >= 0). */
+/* Replace every instance's g_scale (host float[n_instances], finite, >= 0).
+ * Every delivery from the next step on uses the new values, including that of
+ * the spikes of the last step taken.  SNN_ERANGE if a conductance could leave
+ * the fixed-point range (the same rule as at create).  Synchronises. */
 int snn_set_gscale(snn_net *net, const float *per_instance);
 
 /* Current weights of projection proj of instance inst (host float[nnz]). */

@@ -1347,7 +1347,15 @@ int snn_set_gscale(snn_net *net, const float *per_instance)
     }
     if ((rc = check_range(net, bound, wbound, per_instance))) return rc;
     std::copy(per_instance, per_instance + net->n_inst, net->gscale.begin());
-    return h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst);
+    if ((rc = h2d(net, net->d_gscale, per_instance, 4 * (size_t)net->n_inst))) return rc;
+    if (net->launch.mode != kModeFused) return SNN_OK;
+    // fused mode: the pending deliveries of S(t-1) were made with the old
+    // g_scale; the other modes deliver them at step t with the new one
+    net->launch.mode = kModeRows;
+    rc = rebuild_pending(net, -1, nullptr);
+    net->launch.mode = kModeFused;
+    if (rc) return rc;
+    return deliver_queued_to_fused(net, kModeRows);
 }
 
 int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out)

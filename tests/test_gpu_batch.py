@@ -103,6 +103,35 @@ def test_set_gscale_matches_oracle(snn):
     net.close()
 
 
+def test_delivery_modes_agree_on_a_batch(snn):
+    """Rows, tile and fused delivery give the same bits on a batch of uneven
+    instances (many segments and projections), also after g_scale changes
+    with spikes pending."""
+    say("case: delivery modes on a batch of 6 instances")
+    spec = netgen.make_config(4, n_instances=6, scale=0.1)
+    nets = []
+    for mode in (0, 1, 2):
+        n = snn.Network(spec)
+        n.set_launch(mode=mode)
+        n.step(90)
+        nets.append(n)
+    new = np.array([inst["g_scale"] * 1.7 for inst in spec["instances"]], np.float32)
+    for n in nets:
+        n.set_gscale(new)
+        n.step(75)
+    ref = nets[0]
+    for other in nets[1:]:
+        for b, inst in enumerate(spec["instances"]):
+            for p in range(len(inst["pops"])):
+                assert np.array_equal(ref.spikes(b, p), other.spikes(b, p)), (b, p)
+                if inst["pops"][p]["kind"] == "hh":
+                    assert np.array_equal(ref.state(b, p, snn.V), other.state(b, p, snn.V)), (b, p)
+            for q in range(len(inst["projs"])):
+                assert np.array_equal(ref.conductance(b, q), other.conductance(b, q)), (b, q)
+    for n in nets:
+        n.close()
+
+
 def test_stdp_matches_oracle(snn):
     """Workload-3 shape (plastic B->C, 30 Hz input) at reduced size: weights
     after 1000 steps agree with the FP64 oracle (the GPU keeps fp32 weights
