@@ -47,7 +47,7 @@ enum { kPoisson = 0, kHH = 1 };
 // Delivery strategies (bitwise the same result; chosen by measurement):
 // rows = a work item per chunk of a spiking row, 64-bit atomics into G;
 // tiles = a work item per (projection, post tile, group of active spike
-// words), LDS tile accumulation and partial tiles summed by the neuron update.
+// words), LDS tile accumulation, partial tiles added into G by a reduction.
 enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
 // fused = no propagation kernel: each neuron-update block delivers its own
 // spikes' rows with 64-bit atomics into the delivery buffer D of the next
@@ -62,10 +62,7 @@ struct Seg {
     int64_t base;
     int32_t inst, pop;
     int32_t n_in, n_out, n_tr, n_ltp;
-    // incoming projections: id, conductance array, reversal, decay per step,
-    // and where their delivered partial tiles are: partial pool offset, tile
-    // width, pre population (for its list of active spike words) and the
-    // number of spike words of the pre population
+    // incoming projections: id, conductance array, reversal, decay per step
     int32_t in_proj[kMaxIn];
     int64_t in_G[kMaxIn];
     double in_erev[kMaxIn];

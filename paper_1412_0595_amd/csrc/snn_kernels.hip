@@ -4,24 +4,25 @@
 //               discrete time steps) or Poisson draw, upward-crossing spike
 //               test, wavefront ballot into the spike bitmask, and compaction
 //               (wave scan + LDS block offsets + one atomic per block) of the
-//               propagation work of the next step.
+//               propagation work of the next step.  In fused mode the block
+//               instead delivers its own spikes' rows (fused_delivery).
 //  k_propagate_rows  (sparse activity) persistent grid, one wavefront per
 //               chunk of a spiking row; 64-bit atomics into G.
 //  k_propagate_tiles (dense activity) persistent grid of independent
-//               wavefronts, one per work item =
-//               (projection, post tile, group of active 64-neuron spike words
-//               of the pre population; only a group's first word emits).  The wavefront walks the row slices
+//               wavefronts, one per work item = (projection, post tile, group
+//               of active 64-neuron spike words of the pre population; only a
+//               group's first word emits).  The wavefront walks the row slices
 //               of the group's spiking rows in the Compressed Row Storage
 //               arrays (Section 3), packed several rows to a batch of loads,
-//               and adds the weights into its own LDS tile (columns within a
-//               row are distinct, so no atomics), then writes the tile out as
-//               the group's partial.
+//               adds the weights into its own LDS tile (columns within a row
+//               are distinct, so no atomics) and writes the tile out as the
+//               group's partial.
+//  k_reduce_partials  (tile mode) adds the groups' partial tiles into G.
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //
-// Conductances are int64 multiples of 2^-40 uS: the neuron update adds the
-// partial tiles of every active spike word to its conductance, and integer
-// sums are the same in any order.
+// Conductances are int64 multiples of 2^-40 uS, so integer sums of the
+// deliveries are the same in any order and in every delivery mode.
 #include <algorithm>
 #include <hip/hip_ext.h>
 
@@ -594,8 +595,8 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 // CSR propagation (+ depression on plastic rows), tile mode: tiled by post neuron.
 // Every wavefront is an independent worker with its own LDS tile.  A sparse
 // item (few synapses for the tile width) adds its synapses to G with global
-// atomics instead; its group's flag tells the neuron update that no partial
-// tile was written.
+// atomics instead; its group's flag tells the reduction that no partial tile
+// was written.
 // ---------------------------------------------------------------------------
 constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
 
