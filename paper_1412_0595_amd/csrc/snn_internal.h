@@ -54,6 +54,45 @@ enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
 // step (double-buffered), which the next update adds to G (networks without
 // plasticity).
 constexpr int kFusedCap = 512;     // chunks a block lists in LDS per round
+// Tile mode, dense activity: when at least kPullNum/kPullDen of a population
+// spiked, its non-plastic projections are delivered by pulling instead.  Each
+// such projection keeps a column-ordered copy in sliced-ELL form: its columns
+// sorted by length, 64 to a slice, lane l of a slice holding the l-th
+// column's k-th entry (pre index, weight) at slice base + 64 k + l, short
+// columns padded with (row 0, weight 0).  A pull unit is up to kPullDepth
+// consecutive k of one slice: one wavefront, one lane per column, summing
+// the weights of spiking rows.  The unit of a slice of one depth chunk adds
+// its sums into G itself, one plain read-modify-write per column (no other
+// work touches a pulled projection's conductances in that step); the units
+// of deeper slices store one partial sum per column (a coalesced store) and
+// the reduction adds them into G in groups of up to 64 units per wavefront:
+// a plain read-modify-write per column when one group covers the slice, else
+// one atomic per group and column.
+constexpr int kPullNum = 7, kPullDen = 8;
+constexpr int kPullDepth = 64;
+
+struct PullUnit {
+    int64_t e0;         // copy offset of the unit's entry (k0, lane 0)
+    int64_t g_base;     // conductance pool offset of the projection
+    int32_t col_off;    // offset of the slice's 64 post neurons in the column table
+    int32_t depth;      // entries per lane (<= kPullDepth)
+    int32_t pre_seg;    // pre population, and of it:
+    int32_t inst;       //   instance (g_scale),
+    int32_t wbase;      //   first spike word (global word index),
+    int32_t nwords;     //   spike words
+    int32_t direct;     // 1: the slice's only unit, which adds its sums into G
+    int32_t ncols;      // post neurons in the slice (64 but in a projection's last slice)
+};
+
+struct PullSlice {       // one reduction group of a slice
+    int64_t g_base;     // conductance pool offset of the projection
+    int32_t u0;         // its first pull unit (the others follow, one per depth chunk)
+    int32_t n_units;    // <= 64
+    int32_t col_off;    // offset of the slice's 64 post neurons in the column table
+    int32_t pre_seg;
+    int32_t atomic;     // 1: other groups share the slice's columns
+    int32_t pad_;
+};
 
 // One population of one instance; its neurons occupy the global ids
 // [base, base + n), base a multiple of 64, so a wavefront never spans two.
@@ -70,6 +109,8 @@ struct Seg {
     // outgoing projections: id, row-start array (pool offset), post tiles
     int32_t out_proj[kMaxOut];
     int64_t out_rp[kMaxOut];
+    int32_t pullable;   // 1: it has outgoing non-plastic projections (tile mode may pull them)
+    int32_t pad3_;
     int32_t out_tiles[kMaxOut];
     // plastic projections arriving here: id and column-start array
     int32_t ltp_proj[kMaxLtp];
@@ -100,6 +141,7 @@ struct Proj {
     int32_t tile_w, n_tiles;
     int64_t tp_base;    // -1: one tile, the row pointers bound it
     int64_t P_base;     // partial pool offset: [tile][group][tile_w] int64
+    int64_t pull_base;  // first slice of the column-ordered copy (non-plastic), else -1
     int64_t F_base;     // partial flag offset: [tile][group] bytes (1: a partial tile was written)
     int32_t pre_words;  // spike words of the pre population (ceil(n_pre / 64))
     int32_t pad2_;
@@ -120,6 +162,8 @@ struct StepState {
     uint32_t lcnt[2];    // potentiation work items produced at step t
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
     uint32_t fdone;      // fused mode: blocks of the running update that finished
+    uint32_t npull[2];   // tile mode: populations to pull, per step slot
+    uint32_t pad_[2];
 };
 // Per step slot and population, how many of its spike words held a spike
 // (active-word counts, [2][n_segs]) and which ([2][n_waves], population
@@ -168,6 +212,7 @@ struct NeuronArgs {
     const float *w_pool;
     const float *gscale;
     uint32_t *gwsel;         // [2][n_segs]  words per group chosen at emission
+    uint32_t *pullf;         // [2][n_segs]  1: the population's projections are pulled
     uint32_t *awcnt;         // [2][n_segs]  active spike words
     uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
@@ -196,9 +241,17 @@ struct PropArgs {
     uint32_t *scnt;          // [2][n_segs], likewise
     const int32_t *awl;      // [2][n_waves]
     const uint32_t *gwsel;   // [2][n_segs]  words per group of each pre population
+    uint32_t *pullf;         // [2][n_segs]  pull flags (the slot of this step is cleared here)
     int32_t n_segs;
     const int4 *units;       // tile mode: reduction units (projection, tile, first column, first group)
     int64_t n_units;
+    const PullUnit *pull_units;
+    int64_t n_pull_units;
+    int64_t *pull_part;      // [unit][64] partial sums of the pull units
+    const PullSlice *pull_slices;
+    int64_t n_pull_slices;
+    const int32_t *pull_col; // [slice][64] post neuron of each lane, -1 for padding
+    const int2 *pull_rw;     // sliced-ELL entries: (pre index, weight bits)
 };
 
 struct LtpArgs {
@@ -269,6 +322,7 @@ hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_
                             hipEvent_t e1 = nullptr);
 hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);
+hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n, hipStream_t s);
 hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s);
 
 }  // namespace snn

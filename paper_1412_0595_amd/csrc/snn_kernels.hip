@@ -210,7 +210,15 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 // from repeating one step's update (kernel timing): no items
                 if (wslot < words) {
                     a.awl[(int64_t)cur * a.n_waves + S.base / kWave + wslot] = (int32_t)(gw - S.base / kWave);
-                    atomicAdd(&a.scnt[cur * a.n_segs + sidx], (uint32_t)__popcll(ball));
+                    const uint32_t pc = (uint32_t)__popcll(ball);
+                    const uint32_t before = atomicAdd(&a.scnt[cur * a.n_segs + sidx], pc);
+                    // the wave that takes the population's spike count over
+                    // the pull threshold marks the population for pulling
+                    const uint32_t thr = ((uint32_t)S.n * kPullNum + kPullDen - 1) / kPullDen;
+                    if (S.pullable && before < thr && before + pc >= thr) {
+                        a.pullf[cur * a.n_segs + sidx] = 1u;
+                        atomicAdd(&a.st->npull[cur], 1u);
+                    }
                     // words per group from the previous step's counts (the
                     // same for every wave of the population); only the first
                     // word of a group emits the group's items
@@ -600,12 +608,111 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 // ---------------------------------------------------------------------------
 constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
 
+// Pull units.  A unit holds, for 64 post neurons (one per lane), up to
+// kPullDepth entries (pre index and weight, 8 bytes) of each one's column;
+// entries are loaded kPullBatch deep at a time (coalesced: 64 lanes read 512
+// contiguous bytes per depth), then the pre spike word of each entry's row
+// is looked up, from LDS when the pre population's words fit the wavefront's
+// tile, else from global memory.  Each lane adds the fixed-point increments
+// of its spiking rows and stores the sum as the unit's partial for its post
+// neuron, which the reduction adds into G (the only unit of a slice adds
+// them into G itself).  Padding entries carry weight 0, so they add nothing.  Integer sums: the result equals that of pushing the same
+// spikes.  A wavefront works through its units as a pipeline: while one
+// unit's first entries are in flight, the next unit's record and (for a
+// population of at most 64 words) its spike words are loaded.
+constexpr int kPullBatch = 16;
+
+struct PullHdr {
+    int64_t e0, g_base;
+    int32_t col_off, depth, pre_seg, inst, wbase, nwords, direct, ncols;
+};
+
+__device__ __forceinline__ PullHdr pull_hdr(const PropArgs &a, int64_t u)
+{
+    const PullUnit &U = a.pull_units[u];
+    return PullHdr{U.e0, U.g_base, U.col_off, U.depth, U.pre_seg, U.inst, U.wbase, U.nwords, U.direct, U.ncols};
+}
+
+template <bool kLds, class F>
+__device__ __forceinline__ long long pull_entries(const int2 *rw, int32_t depth, const uint64_t *wb, double s,
+                                                  F &&after_first_loads)
+{
+    long long sum = 0;
+    for (int32_t k = 0; k < depth; k += kPullBatch) {
+        int2 e[kPullBatch];
+#pragma unroll
+        for (int v = 0; v < kPullBatch; ++v) e[v] = rw[(int64_t)min(k + v, depth - 1) * kWave];
+        if (k == 0) after_first_loads();
+        uint64_t bw[kPullBatch];
+#pragma unroll
+        for (int v = 0; v < kPullBatch; ++v) bw[v] = wb[e[v].x >> 6];
+#pragma unroll
+        for (int v = 0; v < kPullBatch; ++v)
+            if (k + v < depth && ((bw[v] >> (e[v].x & (kWave - 1))) & 1ull))
+                sum += fix_increment(s, __int_as_float(e[v].y));
+    }
+    return sum;
+}
+
+// The pull units u = g, g + nw, g + 2 nw, ... of wavefront g whose pre
+// populations are flagged; `sb`: the wavefront's LDS tile (kTileMax words).
+__device__ __forceinline__ void pull_phase(const PropArgs &a, int64_t g, int64_t nw, int prev, int lane, uint64_t *sb)
+{
+    const uint64_t *bits = a.bits + (int64_t)prev * a.n_waves;
+    int32_t loaded = -1;   // population whose spike words sb holds
+    for (int64_t r = 0; g + r * nw < a.n_pull_units; r += kWave) {
+        const int64_t uc = g + (r + lane) * nw;
+        const int32_t seg = a.pull_units[min(uc, a.n_pull_units - 1)].pre_seg;
+        const uint32_t f = a.pullf[prev * a.n_segs + seg];
+        uint64_t m = __ballot(uc < a.n_pull_units && f != 0u);
+        if (!m) continue;
+        int64_t u = g + (r + __builtin_ctzll(m)) * nw;
+        m &= m - 1;
+        PullHdr h = pull_hdr(a, u);
+        uint64_t word = h.nwords <= kWave ? bits[h.wbase + min(lane, h.nwords - 1)] : 0ull;
+        for (;;) {
+            const bool more = m != 0;
+            const int64_t un = more ? g + (r + __builtin_ctzll(m)) * nw : u;
+            m &= m - 1;
+            const PullHdr hn = pull_hdr(a, un);
+            if (h.pre_seg != loaded && h.nwords <= kTileMax) {
+                if (h.nwords <= kWave) {
+                    if (lane < h.nwords) sb[lane] = word;
+                } else {
+                    for (int32_t i = lane; i < h.nwords; i += kWave) sb[i] = bits[h.wbase + i];
+                }
+                loaded = h.pre_seg;
+            }
+            // the next unit's words, unless the tile will already hold them
+            auto prefetch = [&]() {
+                if (more && hn.nwords <= kWave && hn.pre_seg != h.pre_seg)
+                    word = bits[hn.wbase + min(lane, hn.nwords - 1)];
+            };
+            const double s = (double)a.gscale[h.inst] * kFixOne;
+            // lanes past a partial slice's columns re-read lane 0's entries
+            // (same cache lines: no padding traffic); their sums are dropped
+            const int2 *rw = a.pull_rw + h.e0 + (lane < h.ncols ? lane : 0);
+            const long long sum = h.nwords <= kTileMax ? pull_entries<true>(rw, h.depth, sb, s, prefetch)
+                                                       : pull_entries<false>(rw, h.depth, bits + h.wbase, s, prefetch);
+            if (h.direct) {
+                const int32_t col = a.pull_col[(int64_t)h.col_off + lane];
+                if (col >= 0 && sum != 0) a.G[h.g_base + col] += sum;
+            } else {
+                a.pull_part[u * kWave + lane] = sum;
+            }
+            if (!more) break;
+            u = un;
+            h = hn;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs a)
 {
     __shared__ long long s_acc[kPropWaves][kTileMax];
     __shared__ int32_t s_rows[kPropWaves][kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform: scalar indexing
     const int64_t t = a.st->t_prop;
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
     const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
@@ -621,6 +728,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         const uint64_t bits0 = uniform_u64(q[it].bits);
         const Proj &P = a.projs[proj];
         if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) continue;   // malformed item
+        if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;         // pulled instead
         // the item of the first slot of each group processes the whole group
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
@@ -768,13 +876,22 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
         if (lane == 0) *flag = 1;
     }
+    if (a.st->npull[prev] != 0 && a.n_pull_units > 0) {
+        // pull units: wavefront g takes units g, g + nw, g + 2 nw, ... (so
+        // the units of the pulled populations spread over every wavefront)
+        pull_phase(a, (int64_t)blockIdx.x * kPropWaves + wid, nw, prev, lane, (uint64_t *)acc);
+    }
     if (blockIdx.x == 0) {
         // active-word and spike counts of the slot the next neuron update fills
         for (int i = threadIdx.x; i < a.n_segs; i += blockDim.x) {
             a.awcnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
             a.scnt[(int64_t)(t & 1) * a.n_segs + i] = 0;
+            a.pullf[(int64_t)(t & 1) * a.n_segs + i] = 0;
         }
-        if (threadIdx.x == 0) a.st->t_neuron = t;
+        if (threadIdx.x == 0) {
+            a.st->npull[t & 1] = 0;
+            a.st->t_neuron = t;
+        }
     }
 }
 
@@ -797,6 +914,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
         const int32_t col0 = __builtin_amdgcn_readfirstlane(a.units[u].z);
         const uint32_t chunk = (uint32_t)__builtin_amdgcn_readfirstlane(a.units[u].w);
         const Proj &P = a.projs[proj];
+        if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;   // pulled: no partials
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         if (na == 0) continue;
         const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
@@ -823,6 +941,41 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
             for (int k = 0; k < 16; ++k) sum += (g + (uint32_t)k < ge && f[k]) ? v[k] : 0;
         }
         if (valid && sum != 0) atomicAdd((unsigned long long *)(a.G + P.G_base + cg), (unsigned long long)sum);
+    }
+    if (a.st->npull[prev] != 0 && a.n_pull_slices > 0) {
+        // reduction groups of pulled slices: wavefront g takes groups g,
+        // g + nw, ..., checks 64 at a time (one per lane) against their pre
+        // populations' flags, and for each pulled group adds its units'
+        // partial sums into G, one lane per post neuron
+        const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+        for (int64_t r = 0; g + r * nw < a.n_pull_slices; r += kWave) {
+            const int64_t sl = g + (r + lane) * nw;
+            const int32_t seg = a.pull_slices[min(sl, a.n_pull_slices - 1)].pre_seg;
+            const uint32_t f = a.pullf[prev * a.n_segs + seg];
+            uint64_t m = __ballot(sl < a.n_pull_slices && f != 0u);
+            while (m) {
+                const int l = __builtin_ctzll(m);
+                m &= m - 1;
+                const PullSlice &S = a.pull_slices[g + (r + l) * nw];
+                const int64_t g_base = S.g_base;
+                const int32_t u0 = S.u0, nu = S.n_units, atomic = S.atomic;
+                const int32_t col = a.pull_col[(int64_t)S.col_off + lane];
+                int64_t sum = 0;
+                for (int32_t c = 0; c < nu; c += 8) {
+                    int64_t v[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] = a.pull_part[(int64_t)(u0 + min(c + k, nu - 1)) * kWave + lane];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) sum += c + k < nu ? v[k] : 0;
+                }
+                if (col >= 0 && sum != 0) {
+                    if (atomic)
+                        atomicAdd((unsigned long long *)(a.G + g_base + col), (unsigned long long)sum);
+                    else
+                        a.G[g_base + col] += sum;
+                }
+            }
+        }
     }
 }
 
@@ -871,6 +1024,16 @@ __global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
     }
 }
 
+// rw[i].y = bits of w[perm[i]], 0 where perm[i] < 0: refresh the weights of
+// a column-ordered copy.
+__global__ void k_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = perm[i];
+        rw[i].y = __float_as_int(p >= 0 ? w[p] : 0.0f);
+    }
+}
+
 // Flag (bit 0) any weight that is not finite or is negative.
 __global__ void k_check_weights(const float *w, int64_t n, uint32_t *flag)
 {
@@ -878,6 +1041,14 @@ __global__ void k_check_weights(const float *w, int64_t n, uint32_t *flag)
         const float x = w[i];
         if (!(x >= 0.0f) || !isfinite(x)) atomicOr(flag, 1u);
     }
+}
+
+hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_gather_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, perm, rw, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s)
@@ -916,7 +1087,7 @@ hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_
         return hipGetLastError();
     }
     // the tiled kernel runs kPropWaves wavefronts per block
-    if (a.n_units == 0) {
+    if (a.n_units == 0 && a.n_pull_slices == 0) {
         SNN_LAUNCH(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), s, e0, e1, a);
         return hipGetLastError();
     }
@@ -924,7 +1095,7 @@ hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_
     SNN_LAUNCH(k_propagate_tiles, dim3(blocks), dim3(kPropWaves * kWave), s, e0, none, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t rb = std::min<int64_t>((a.n_units + 3) / 4, 4096);
+    const int64_t rb = std::min<int64_t>((std::max(a.n_units, a.n_pull_slices) + 3) / 4, 4096);
     if (e0) {
         // the stop event of the pair goes on the second kernel
         hipExtLaunchKernelGGL(k_reduce_partials, dim3((unsigned)rb), dim3(256), 0, s, nullptr, e1, 0, a);

@@ -123,6 +123,16 @@ struct snn_net {
     uint8_t *d_pflag;
     int4 *d_units;           // tile-mode reduction units
     int64_t n_units;
+    PullUnit *d_pull_units;  // tile-mode pull units
+    int64_t n_pull_units;
+    int64_t *d_pull_part;    // [unit][64] their partial sums
+    PullSlice *d_pull_slices;
+    int64_t n_pull_slices;
+    int32_t *d_pull_col;     // [slice][64] post neuron of each lane (-1: padding)
+    int2 *d_pull_rw;         // sliced-ELL copies of non-plastic projections: (pre index, weight bits)
+    int32_t *d_pull_perm;    // and the weight's position in the weight pool (-1: padding)
+    int64_t pull_count;
+    uint32_t *pullf;     // arena: [2][n_segs]  populations delivered by pulling
     uint32_t *awcnt;     // arena: [2][n_segs]
     uint32_t *scnt;      // arena: [2][n_segs]
     int32_t *awl;        // arena: [2][n_waves]
@@ -267,6 +277,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.scnt = net->scnt;
     a.awl = net->awl;
     a.gwsel = net->gwsel;
+    a.pullf = net->pullf;
     a.D = net->D;
     a.G_count = net->G_count;
     a.col_pool = net->d_col;
@@ -302,6 +313,14 @@ PropArgs prop_args(snn_net *net)
     p.scnt = net->scnt;
     p.awl = net->awl;
     p.gwsel = net->gwsel;
+    p.pullf = net->pullf;
+    p.pull_units = net->d_pull_units;
+    p.n_pull_units = net->n_pull_units;
+    p.pull_part = net->d_pull_part;
+    p.pull_slices = net->d_pull_slices;
+    p.n_pull_slices = net->n_pull_slices;
+    p.pull_col = net->d_pull_col;
+    p.pull_rw = net->d_pull_rw;
     p.n_segs = (int32_t)net->segs.size();
     return p;
 }
@@ -651,6 +670,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
             P_total += (int64_t)P.n_tiles * P.pre_words * P.tile_w;
             P.F_base = F_total;
             F_total += (int64_t)P.n_tiles * P.pre_words;
+            P.pull_base = -1;
             P.tp_base = -1;
             if (P.n_tiles > 1) {
                 P.tp_base = tp_total;
@@ -710,6 +730,63 @@ int snn_create(const snn_config *cfg, snn_net **out)
         }
     }
     if ((rc = check_range(net, colsum_bound, w_bound, net->gscale.data()))) return bail(rc);
+    // sliced-ELL copies of the non-plastic projections (weight-pool positions
+    // must fit the int32 permutation): columns by decreasing length, 64 to a
+    // slice, and one pull unit per kPullDepth entries of a slice's depth
+    std::vector<std::vector<int32_t>> pcol(net->projs.size()), pord(net->projs.size());
+    std::vector<int64_t> pull_slices;   // copy offset of each slice's entry (0, lane 0)
+    std::vector<PullSlice> pull_red;
+    std::vector<PullUnit> pull_units;
+    int64_t pull_total = 0;
+    if (syn_total < ((int64_t)1 << 31)) {
+        for (int b = 0, gq = 0; b < net->n_inst; ++b) {
+            const snn_instance_desc &I = cfg->inst[b];
+            for (int q = 0; q < I.n_projs; ++q, ++gq) {
+                const snn_proj_desc &Q = I.projs[q];
+                Proj &P = net->projs[gq];
+                if (Q.stdp || Q.nnz == 0) continue;
+                std::vector<int32_t> &cp = pcol[gq], &ord = pord[gq];
+                cp.assign(P.n_post + 1, 0);
+                for (int64_t k = 0; k < Q.nnz; ++k) cp[Q.col_idx[k] + 1]++;
+                for (int32_t j = 0; j < P.n_post; ++j) cp[j + 1] += cp[j];
+                ord.resize(P.n_post);
+                for (int32_t j = 0; j < P.n_post; ++j) ord[j] = j;
+                std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+                    return cp[x + 1] - cp[x] > cp[y + 1] - cp[y];
+                });
+                P.pull_base = (int64_t)pull_slices.size();
+                const Seg &pre = net->segs[P.pre_seg];
+                for (int32_t j0 = 0; j0 < P.n_post; j0 += kWave) {
+                    const int32_t maxlen = cp[ord[j0] + 1] - cp[ord[j0]];
+                    const int64_t sl = (int64_t)pull_slices.size();
+                    pull_slices.push_back(pull_total);
+                    // depth split into equal chunks of at most kPullDepth;
+                    // reduction groups of up to 64 chunks
+                    const int32_t nch = (maxlen + kPullDepth - 1) / kPullDepth;
+                    for (int32_t c0 = 0; nch > 1 && c0 < nch; c0 += kWave)
+                        pull_red.push_back(PullSlice{P.G_base, (int32_t)pull_units.size() + c0, std::min(kWave, nch - c0),
+                                                     (int32_t)(sl * kWave), P.pre_seg, nch > kWave ? 1 : 0, 0});
+                    for (int32_t c = 0; c < nch; ++c) {
+                        const int32_t k0 = (int32_t)((int64_t)c * maxlen / nch), k1 = (int32_t)((int64_t)(c + 1) * maxlen / nch);
+                        PullUnit U{};
+                        U.e0 = pull_total + (int64_t)k0 * kWave;
+                        U.g_base = P.G_base;
+                        U.col_off = (int32_t)(sl * kWave);
+                        U.depth = k1 - k0;
+                        U.pre_seg = P.pre_seg;
+                        U.inst = P.inst;
+                        U.wbase = (int32_t)(pre.base / kWave);
+                        U.nwords = (int32_t)(align_up(pre.n, kWave) / kWave);
+                        U.direct = nch == 1 ? 1 : 0;
+                        U.ncols = std::min(kWave, P.n_post - j0);
+                        pull_units.push_back(U);
+                    }
+                    pull_total += (int64_t)maxlen * kWave;
+                }
+                net->segs[P.pre_seg].pullable = 1;
+            }
+        }
+    }
     net->n_neurons_padded = base;
     net->n_waves = base / kWave;
     net->w_count = syn_total;
@@ -775,6 +852,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_scnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_awl = part(2 * W * 4);
     Part p_gws = part(2 * (int64_t)net->segs.size() * 4);
+    Part p_pullf = part(2 * (int64_t)net->segs.size() * 4);
     Part p_D = part(net->plastic ? 8 : 2 * std::max<int64_t>(G_total, 1) * 8);   // fused mode only
     net->arena_bytes = off;
     net->d_arena = (char *)dev_alloc(net, (size_t)off);
@@ -806,9 +884,19 @@ int snn_create(const snn_config *cfg, snn_net **out)
     }
     net->n_units = (int64_t)units.size();
     net->d_units = (int4 *)dev_alloc(net, sizeof(int4) * std::max<size_t>(units.size(), 1));
+    net->pull_count = pull_total;
+    net->n_pull_units = (int64_t)pull_units.size();
+    net->d_pull_units = (PullUnit *)dev_alloc(net, sizeof(PullUnit) * std::max<size_t>(pull_units.size(), 1));
+    net->d_pull_part = (int64_t *)dev_alloc(net, 8 * (size_t)kWave * std::max<size_t>(pull_units.size(), 1));
+    net->n_pull_slices = (int64_t)pull_red.size();
+    net->d_pull_slices = (PullSlice *)dev_alloc(net, sizeof(PullSlice) * std::max<size_t>(pull_red.size(), 1));
+    net->d_pull_col = (int32_t *)dev_alloc(net, 4 * (size_t)kWave * std::max<size_t>(pull_slices.size(), 1));
+    net->d_pull_rw = (int2 *)dev_alloc(net, 8 * std::max<int64_t>(pull_total, 1));
+    net->d_pull_perm = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(pull_total, 1));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
         !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
-        !net->d_units)
+        !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_rw ||
+        !net->d_pull_perm)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -827,6 +915,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->scnt = (uint32_t *)(A + p_scnt.off);
     net->awl = (int32_t *)(A + p_awl.off);
     net->gwsel = (uint32_t *)(A + p_gws.off);
+    net->pullf = (uint32_t *)(A + p_pullf.off);
     net->D = (int64_t *)(A + p_D.off);
 
     // ---- uploads
@@ -844,6 +933,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
         }
         if ((rc = up(net->d_wave_seg, wave_seg.data(), 4 * W))) return bail(rc);
         if ((rc = up(net->d_units, units.data(), sizeof(int4) * units.size()))) return bail(rc);
+        if ((rc = up(net->d_pull_units, pull_units.data(), sizeof(PullUnit) * pull_units.size()))) return bail(rc);
+        if ((rc = up(net->d_pull_slices, pull_red.data(), sizeof(PullSlice) * pull_red.size()))) return bail(rc);
     }
     if ((rc = up(net->d_segs, net->segs.data(), sizeof(Seg) * net->segs.size()))) return bail(rc);
     if ((rc = up(net->d_projs, net->projs.data(), sizeof(Proj) * net->projs.size()))) return bail(rc);
@@ -870,6 +961,40 @@ int snn_create(const snn_config *cfg, snn_net **out)
                     tp[(size_t)i * (P.n_tiles + 1) + P.n_tiles] = Q.row_ptr[i + 1];
                 }
                 if ((rc = up(net->d_tp + P.tp_base, tp.data(), 4 * tp.size()))) return bail(rc);
+            }
+            if (P.pull_base >= 0) {
+                // sliced-ELL copy: lane l of slice j holds column ord[64 j + l],
+                // its entries in ascending row order at k = 0, 1, ...
+                const std::vector<int32_t> &cp = pcol[gq], &ord = pord[gq];
+                std::vector<int32_t> fill(cp.begin(), cp.end() - 1), rows(Q.nnz), at(Q.nnz);
+                for (int32_t i = 0; i < P.n_pre; ++i)
+                    for (int32_t k = Q.row_ptr[i]; k < Q.row_ptr[i + 1]; ++k) {
+                        const int32_t e = fill[Q.col_idx[k]]++;
+                        rows[e] = i;
+                        at[e] = k;
+                    }
+                const int32_t n_sl = (P.n_post + kWave - 1) / kWave;
+                const int64_t e0 = pull_slices[P.pull_base];
+                const int64_t e1 = P.pull_base + n_sl < (int64_t)pull_slices.size() ? pull_slices[P.pull_base + n_sl]
+                                                                                     : pull_total;
+                std::vector<int2> erw(e1 - e0, make_int2(0, 0));
+                std::vector<int32_t> ep(e1 - e0, -1), lc((size_t)n_sl * kWave, -1);
+                for (int32_t j = 0; j < P.n_post; ++j) {
+                    const int32_t c = ord[j], sl = j / kWave, l = j % kWave;
+                    lc[j] = c;
+                    const int64_t b0 = pull_slices[P.pull_base + sl] - e0;
+                    for (int32_t k = 0; k < cp[c + 1] - cp[c]; ++k) {
+                        const int64_t e = b0 + (int64_t)k * kWave + l;
+                        float g = Q.g[at[cp[c] + k]];
+                        int32_t gb;
+                        std::memcpy(&gb, &g, 4);
+                        erw[e] = make_int2(rows[cp[c] + k], gb);
+                        ep[e] = (int32_t)(P.syn_base + at[cp[c] + k]);
+                    }
+                }
+                if ((rc = up(net->d_pull_rw + e0, erw.data(), 8 * erw.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_perm + e0, ep.data(), 4 * ep.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_col + P.pull_base * kWave, lc.data(), 4 * lc.size()))) return bail(rc);
             }
             if (Q.stdp) {
                 // column view: entries of column j in ascending row order
@@ -1182,6 +1307,21 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     if ((rc = h2d(net, net->scnt + (int64_t)(slot ^ 1) * nseg, zero.data(), 4 * nseg))) return rc;
     if ((rc = h2d(net, net->awl + (int64_t)slot * net->n_waves, awl.data(), 4 * (size_t)net->n_waves))) return rc;
     if ((rc = h2d(net, net->gwsel + (int64_t)slot * nseg, gws.data(), 4 * nseg))) return rc;
+    // tile mode: populations at or above the pull threshold are pulled
+    std::vector<uint32_t> pf(2 * nseg, 0);
+    uint32_t np = 0;
+    if (net->launch.mode == kModeTiles)
+        for (size_t g = 0; g < nseg; ++g) {
+            const Seg &G = net->segs[g];
+            const uint32_t thr = ((uint32_t)G.n * kPullNum + kPullDen - 1) / kPullDen;
+            if (G.pullable && spk[g] >= thr) {
+                pf[(size_t)slot * nseg + g] = 1;
+                ++np;
+            }
+        }
+    if ((rc = h2d(net, net->pullf, pf.data(), 4 * pf.size()))) return rc;
+    st.npull[slot] = np;
+    st.npull[slot ^ 1] = 0;
     st.qcnt[slot] = (uint32_t)items.size();
     if (ltp_seg >= 0) {
         const Seg &S = net->segs[ltp_seg];
@@ -1206,8 +1346,9 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     return h2d(net, net->st, &st, sizeof st);
 }
 
-// Both queue slots empty: fused steps neither fill nor reset them, so a count
-// left from before fused mode must not survive a switch in either direction.
+// Both queue slots empty and no population marked for pulling: fused steps
+// neither fill nor reset them, so a count left from before fused mode must not
+// survive a switch in either direction.
 static int clear_queues(snn_net *net)
 {
     int rc;
@@ -1215,6 +1356,9 @@ static int clear_queues(snn_net *net)
     if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
     st.qcnt[0] = st.qcnt[1] = 0;
     st.lcnt[0] = st.lcnt[1] = 0;
+    st.npull[0] = st.npull[1] = 0;
+    std::vector<uint32_t> zero(2 * net->segs.size(), 0);
+    if ((rc = h2d(net, net->pullf, zero.data(), 4 * zero.size()))) return rc;
     return h2d(net, net->st, &st, sizeof st);
 }
 
@@ -1557,6 +1701,7 @@ int snn_set_weights_device(snn_net *net, const float *src)
     HIP_OK(hipStreamSynchronize(net->stream));
     if (flag) return fail(SNN_EINVAL, "weights must be finite and >= 0");
     HIP_OK(hipMemcpyAsync(net->d_w, src, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream));
+    HIP_OK(launch_gather_weights(net->d_w, net->d_pull_perm, net->d_pull_rw, net->pull_count, net->stream));
     return SNN_OK;
 }
 

@@ -328,6 +328,66 @@ def test_delivery_modes_agree_bitwise_with_switches(snn, workload, scale):
     b.close()
 
 
+def test_pull_delivery_agrees_bitwise(snn):
+    """Tile mode delivers the projections of a population with at least 7/8 of
+    its neurons spiking by pulling (sliced-ELL column copies, one lane per
+    column); the bits equal row mode's, through steps on both sides of the
+    threshold, forced all-spiking populations, new weights and a new
+    g_scale."""
+    say("case: pull delivery against row mode")
+    rng = np.random.default_rng(11)
+    # A fires with probability 0.875 per step: its count straddles 7/8 of
+    # 2000; A->B columns hold about 1000 entries (16 depth chunks); B spans
+    # two post tiles and C ends in a partial slice
+    inst = netgen.layered_instance(rng, 2000, 1500, 300, rate_hz=8750.0, p_ab=0.5, p_bc=0.3,
+                                   g_scale=0.05, seed=(5 << 20) + 1)
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    T = 120
+    a = snn.Network(spec, raster_steps=T)
+    b = snn.Network(spec)
+    b.set_launch(mode=1)
+    a.step(T)
+    b.step(T)
+    thr = (2000 * 7 + 7) // 8
+    per_step = np.array([len(r) for r in a.raster(0, 0, 0, T)])
+    say(f"  A spikes per step: min {per_step.min()} max {per_step.max()}, "
+        f"{np.mean(per_step >= thr) * 100:.0f}% of steps pulled")
+    assert 0 < np.sum(per_step >= thr) < T
+    _same_network_state(a, b, spec)
+    # every B and C neuron spiked at t - 1: their projections are pulled
+    for p in (1, 2):
+        ones = np.ones(inst["pops"][p]["n"], np.uint8)
+        a.set_last_spikes(0, p, ones)
+        b.set_last_spikes(0, p, ones)
+    a.step(3)
+    b.step(3)
+    _same_network_state(a, b, spec)
+    # new weights (the column-ordered copies follow) and a new g_scale
+    import torch
+    w = torch.empty(a.weight_count, dtype=torch.float32, device="cuda")
+    a.get_weights_device(w)
+    w = w * torch.linspace(0.5, 1.5, w.numel(), device="cuda")
+    a.set_weights_device(w)
+    b.set_weights_device(w)
+    a.set_gscale(np.array([0.07], np.float32))
+    b.set_gscale(np.array([0.07], np.float32))
+    for p in (1, 2):
+        ones = np.ones(inst["pops"][p]["n"], np.uint8)
+        a.set_last_spikes(0, p, ones)
+        b.set_last_spikes(0, p, ones)
+    a.step(57)
+    b.step(57)
+    _same_network_state(a, b, spec)
+    # switching with pulled work pending
+    a.set_launch(mode=1)
+    b.set_launch(mode=0)
+    a.step(31)
+    b.step(31)
+    _same_network_state(a, b, spec)
+    a.close()
+    b.close()
+
+
 def _same_network_state(a, b, spec):
     inst = spec["instances"][0]
     for p in range(len(inst["pops"])):
