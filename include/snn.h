@@ -296,8 +296,12 @@ int snn_weight_offset(const snn_net *net, int32_t inst, int32_t proj, int64_t *o
 
 /* Copy the whole weight pool to / from caller-owned device memory
  * (float[snn_weight_count]) on the net's stream.  The write checks on the
- * device that every weight is finite and >= 0 (SNN_EINVAL otherwise,
- * nothing copied) and synchronises for that check. */
+ * device that every weight is finite and >= 0 (SNN_EINVAL otherwise) and
+ * applies the range rules of snn_create with the current g_scale
+ * (SNN_ERANGE); on either error nothing is copied.  It synchronises for
+ * those checks.  New weights apply to every delivery from the next step,
+ * including that of the last step's spikes (in mode 2 the pending
+ * deliveries are redone). */
 int snn_get_weights_device(snn_net *net, float *dst_dev);
 int snn_set_weights_device(snn_net *net, const float *src_dev);
 

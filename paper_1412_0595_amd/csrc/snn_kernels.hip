@@ -1034,12 +1034,28 @@ __global__ void k_gather_weights(const float *w, const int32_t *perm, int2 *rw, 
     }
 }
 
-// Flag (bit 0) any weight that is not finite or is negative.
-__global__ void k_check_weights(const float *w, int64_t n, uint32_t *flag)
+// Flag (bit 0) any weight that is not finite or is negative; wmax[q] gets
+// the bits of projection q's largest weight (block row q of the grid).
+__global__ void k_check_weights(const float *w, const Proj *projs, uint32_t *flag, uint32_t *wmax)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float x = w[i];
-        if (!(x >= 0.0f) || !isfinite(x)) atomicOr(flag, 1u);
+    const Proj &P = projs[blockIdx.y];
+    float m = 0.0f;
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.nnz; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = w[P.syn_base + i];
+        if (!(x >= 0.0f) || !isfinite(x))
+            bad = 1;
+        else
+            m = fmaxf(m, x);
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        m = fmaxf(m, __shfl_xor(m, d, kWave));
+        bad |= __shfl_xor(bad, d, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (bad) atomicOr(flag, 1u);
+        if (m > 0.0f) atomicMax(&wmax[blockIdx.y], __float_as_uint(m));   // non-negative floats order as their bits
     }
 }
 
@@ -1051,11 +1067,12 @@ hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, 
     return hipGetLastError();
 }
 
-hipError_t launch_check_weights(const float *w, int64_t n, uint32_t *flag, hipStream_t s)
+hipError_t launch_check_weights(const float *w, const Proj *projs, int32_t n_projs, int64_t max_nnz, uint32_t *flag,
+                                uint32_t *wmax, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_check_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, n, flag);
+    if (n_projs == 0 || max_nnz == 0) return hipSuccess;
+    const int64_t bx = std::min<int64_t>((max_nnz + 2047) / 2048, 512);
+    hipLaunchKernelGGL(k_check_weights, dim3((unsigned)bx, (unsigned)n_projs), dim3(256), 0, s, w, projs, flag, wmax);
     return hipGetLastError();
 }
 

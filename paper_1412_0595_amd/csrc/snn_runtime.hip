@@ -84,6 +84,8 @@ struct HostProj {            // host copy of what state access needs
     std::vector<int32_t> row_ptr;
     std::vector<int32_t> col_ptr;   // plastic only
     int stdp;
+    int32_t max_col_len;            // longest column (synapses onto one post neuron)
+    double decay;                   // conductance decay per step
 };
 
 struct snn_net {
@@ -179,6 +181,8 @@ struct snn_net {
     int64_t n_gitems;
     double *d_tape_x, *d_tape_g, *d_lg, *d_lam;
     uint32_t *d_flag;
+    uint32_t *d_wmax;        // per projection: bits of the largest weight (weight checks)
+    int64_t max_nnz;
 
     // launch shape and graph
     snn_launch launch;
@@ -716,7 +720,13 @@ int snn_create(const snn_config *cfg, snn_net **out)
             }
             // bound on the conductance reachable with g_scale = 1
             std::vector<double> col(post.n > 0 ? post.n : 1, 0.0);
-            for (int64_t k = 0; k < Q.nnz; ++k) col[Q.col_idx[k]] += Q.g[k];
+            std::vector<int32_t> len(post.n > 0 ? post.n : 1, 0);
+            for (int64_t k = 0; k < Q.nnz; ++k) {
+                col[Q.col_idx[k]] += Q.g[k];
+                len[Q.col_idx[k]]++;
+            }
+            H.max_col_len = *std::max_element(len.begin(), len.end());
+            H.decay = decay;
             double mx = 0.0;
             for (double c : col) mx = std::max(mx, c);
             if (Q.stdp) mx = std::max(mx, (double)Q.g_max * (double)pre.n);
@@ -1042,7 +1052,10 @@ int snn_create(const snn_config *cfg, snn_net **out)
     }
     net->d_init_state = (float *)dev_alloc(net, 4 * 8 * (size_t)N);
     net->d_flag = (uint32_t *)dev_alloc(net, 256);
-    if (!net->d_init_state || !net->d_flag) return bail(fail(SNN_ENOMEM, "device allocation failed"));
+    net->d_wmax = (uint32_t *)dev_alloc(net, 4 * std::max<size_t>(net->projs.size(), 1));
+    net->max_nnz = 0;
+    for (const HostProj &H : net->hprojs) net->max_nnz = std::max(net->max_nnz, H.nnz);
+    if (!net->d_init_state || !net->d_flag || !net->d_wmax) return bail(fail(SNN_ENOMEM, "device allocation failed"));
     if (hipMemcpy(net->d_init_state, net->vh, 4 * 8 * (size_t)N, hipMemcpyDeviceToDevice) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail(SNN_EDEVICE, "state copy failed"));
@@ -1694,15 +1707,52 @@ int snn_set_weights_device(snn_net *net, const float *src)
     int rc = check_net(net);
     if (rc) return rc;
     if (!src) return fail(SNN_EINVAL, "src is NULL");
+    const size_t np = net->projs.size();
     uint32_t flag = 0;
+    std::vector<uint32_t> wbits(np, 0);
     HIP_OK(hipMemsetAsync(net->d_flag, 0, 4, net->stream));
-    HIP_OK(launch_check_weights(src, net->w_count, net->d_flag, net->stream));
+    HIP_OK(hipMemsetAsync(net->d_wmax, 0, 4 * std::max<size_t>(np, 1), net->stream));
+    HIP_OK(launch_check_weights(src, net->d_projs, (int32_t)np, net->max_nnz, net->d_flag, net->d_wmax, net->stream));
     HIP_OK(hipMemcpyAsync(&flag, net->d_flag, 4, hipMemcpyDeviceToHost, net->stream));
+    if (np) HIP_OK(hipMemcpyAsync(wbits.data(), net->d_wmax, 4 * np, hipMemcpyDeviceToHost, net->stream));
     HIP_OK(hipStreamSynchronize(net->stream));
     if (flag) return fail(SNN_EINVAL, "weights must be finite and >= 0");
+    // the range rules of snn_create: a single increment below kWLimit, and
+    // g_scale * column sum / (1 - decay) below kGLimit, checked first on the
+    // bound longest column * largest weight, exactly only where that fails
+    for (size_t q = 0; q < np; ++q) {
+        const HostProj &H = net->hprojs[q];
+        const Proj &P = net->projs[q];
+        float wmf;
+        std::memcpy(&wmf, &wbits[q], 4);
+        const double gs = net->gscale[H.inst];
+        const double wm = std::max(H.stdp ? (double)P.g_max : 0.0, (double)wmf);
+        if (!(wm * gs < kWLimit))
+            return fail(SNN_ERANGE, "projection %zu: g_scale * largest weight exceeds %g uS", q, kWLimit);
+        double bound = (double)H.max_col_len * wm;
+        if (H.stdp) bound = std::max(bound, (double)P.g_max * H.n_pre);
+        if (bound * gs / (1.0 - H.decay) < kGLimit) continue;
+        std::vector<int32_t> col(H.nnz);
+        std::vector<float> w(H.nnz);
+        if ((rc = d2h(net, col.data(), net->d_col + H.syn_base, 4 * (size_t)H.nnz))) return rc;
+        if ((rc = d2h(net, w.data(), src + H.syn_base, 4 * (size_t)H.nnz))) return rc;
+        std::vector<double> cs(std::max(H.n_post, 1), 0.0);
+        for (int64_t k = 0; k < H.nnz; ++k) cs[col[k]] += w[k];
+        double mx = *std::max_element(cs.begin(), cs.end());
+        if (H.stdp) mx = std::max(mx, (double)P.g_max * H.n_pre);
+        if (!(mx * gs / (1.0 - H.decay) < kGLimit))
+            return fail(SNN_ERANGE, "projection %zu: g_scale * column sum / (1 - decay) exceeds %g uS", q, kGLimit);
+    }
     HIP_OK(hipMemcpyAsync(net->d_w, src, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream));
     HIP_OK(launch_gather_weights(net->d_w, net->d_pull_perm, net->d_pull_rw, net->pull_count, net->stream));
-    return SNN_OK;
+    if (net->launch.mode != kModeFused) return SNN_OK;
+    // fused mode: the pending deliveries of S(t-1) were made with the old
+    // weights; the other modes deliver them at step t with the new ones
+    net->launch.mode = kModeRows;
+    rc = rebuild_pending(net, -1, nullptr);
+    net->launch.mode = kModeFused;
+    if (rc) return rc;
+    return deliver_queued_to_fused(net, kModeRows);
 }
 
 int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_every, double *vbar)

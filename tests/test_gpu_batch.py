@@ -105,8 +105,9 @@ def test_set_gscale_matches_oracle(snn):
 
 def test_delivery_modes_agree_on_a_batch(snn):
     """Rows, tile and fused delivery give the same bits on a batch of uneven
-    instances (many segments and projections), also after g_scale changes
-    with spikes pending."""
+    instances (many segments and projections), also after g_scale and weight
+    changes with spikes pending."""
+    import torch
     say("case: delivery modes on a batch of 6 instances")
     spec = netgen.make_config(4, n_instances=6, scale=0.1)
     nets = []
@@ -119,6 +120,12 @@ def test_delivery_modes_agree_on_a_batch(snn):
     for n in nets:
         n.set_gscale(new)
         n.step(75)
+    w = torch.empty(nets[0].weight_count, dtype=torch.float32, device="cuda")
+    nets[0].get_weights_device(w)
+    w = w * torch.linspace(1.3, 0.6, w.numel(), device="cuda")
+    for n in nets:
+        n.set_weights_device(w)
+        n.step(41)
     ref = nets[0]
     for other in nets[1:]:
         for b, inst in enumerate(spec["instances"]):
@@ -130,6 +137,46 @@ def test_delivery_modes_agree_on_a_batch(snn):
                 assert np.array_equal(ref.conductance(b, q), other.conductance(b, q)), (b, q)
     for n in nets:
         n.close()
+
+
+def test_set_weights_device_checks(snn):
+    """New weights go through the same checks as at creation: non-finite or
+    negative weights (EINVAL), g_scale * weight >= 2^11 uS or g_scale *
+    column sum / (1 - decay) >= 2^22 uS (ERANGE); a rejected pool leaves the
+    weights as they were.  A large single weight on a long column passes
+    when the exact column sums are in range."""
+    import torch
+    say("case: set_weights_device range checks")
+    rng = np.random.default_rng(5)
+    # A -> B all to all: columns of 3000 synapses
+    inst = netgen.layered_instance(rng, 3000, 40, 20, p_ab=1.0, seed=9)
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    net = snn.Network(spec)
+    w0 = torch.empty(net.weight_count, dtype=torch.float32, device="cuda")
+    net.get_weights_device(w0)
+    off = net.weight_offset(0, 0)
+    nnz = inst["projs"][0]["col_idx"].size
+    bad = w0.clone()
+    bad[off + 3] = float("nan")
+    with pytest.raises(RuntimeError, match="finite"):
+        net.set_weights_device(bad)
+    bad = w0.clone()
+    bad[off + 5] = 2048.0
+    with pytest.raises(RuntimeError, match="largest weight"):
+        net.set_weights_device(bad)
+    bad = w0.clone()
+    bad[off:off + nnz] = 1500.0     # 3000 * 1500 uS per column: beyond 2^22 uS
+    with pytest.raises(RuntimeError, match="column sum"):
+        net.set_weights_device(bad)
+    back = torch.empty_like(w0)
+    net.get_weights_device(back)
+    assert torch.equal(back, w0)
+    ok = w0.clone()
+    ok[off + 7] = 1500.0            # longest column * 1500 fails the bound, the exact sums pass
+    net.set_weights_device(ok)
+    net.get_weights_device(back)
+    assert torch.equal(back, ok)
+    net.close()
 
 
 def test_stdp_matches_oracle(snn):
