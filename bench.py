@@ -201,12 +201,36 @@ def spike_totals(net, spec):
             for b, inst in enumerate(spec["instances"])]
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Achievable device-to-device copy bandwidth on this GPU (bytes read plus
+    bytes written per second), the practical ceiling a streaming kernel is
+    compared with besides the HBM peak."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def sweep(args):
     """Propagation kernel alone on a workload's connectivity with seeded
     synthetic spike sets: every input (A) row and a fraction of the hidden (B)
     rows spiking; one hipEvent pair around back-to-back launches."""
     import numpy as np
     from paper_1412_0595_amd import netgen, snn
+    copy_gbs = copy_bandwidth()
+    print(json.dumps({"sweep": "copy", "bytes": 1 << 30, "copy_GBs": copy_gbs,
+                      "frac_of_hbm": copy_gbs / HBM_PEAK_GBS}), flush=True)
     spec = netgen.make_config(args.sweep_workload, n_instances=args.instances)
     for inst in spec["instances"]:
         for q in inst["projs"]:
@@ -236,7 +260,7 @@ def sweep(args):
             print(json.dumps({"sweep": "propagation", "workload": args.sweep_workload, "hidden_fraction": frac,
                               "events_per_launch": ev, "rows": rows, "ms_per_launch": ms, "launch": net.launch,
                               "events_per_s": ev / (ms * 1e-3), "achieved_GBs": gbs,
-                              "frac_of_hbm": gbs / HBM_PEAK_GBS}), flush=True)
+                              "frac_of_hbm": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}), flush=True)
     net.close()
 
 

@@ -378,12 +378,22 @@ def test_pull_delivery_agrees_bitwise(snn):
     a.step(57)
     b.step(57)
     _same_network_state(a, b, spec)
-    # switching with pulled work pending
-    a.set_launch(mode=1)
-    b.set_launch(mode=0)
-    a.step(31)
-    b.step(31)
-    _same_network_state(a, b, spec)
+    # switches with pulled work pending (all B and C neurons spiked at t - 1):
+    # rows <-> tiles, then tiles -> fused (the pending pull runs into the
+    # fused delivery buffer) against rows -> fused, then back
+    plan = [(dict(mode=1), dict(mode=0), 31), (dict(mode=2), dict(mode=2), 17),
+            (dict(mode=1), dict(mode=0), 23)]
+    for la, lb, n in plan:
+        for p in (1, 2):
+            ones = np.ones(inst["pops"][p]["n"], np.uint8)
+            a.set_last_spikes(0, p, ones)
+            b.set_last_spikes(0, p, ones)
+        a.set_launch(**la)
+        b.set_launch(**lb)
+        say(f"  modes {a.launch['mode']} / {b.launch['mode']}, {n} steps")
+        a.step(n)
+        b.step(n)
+        _same_network_state(a, b, spec)
     a.close()
     b.close()
 
