@@ -155,7 +155,10 @@ typedef struct {
     int32_t chunk;          /* synapses per work item of a row or column walk, multiple of 64 */
     int32_t mode;           /* delivery: 0 rows (a wavefront per row chunk, atomics into G;
                                sparse activity), 1 tiles (a wavefront per post tile and group of
-                               active spike words, LDS accumulation; dense activity), 2 fused
+                               active spike words, LDS accumulation; dense activity; the
+                               non-plastic projections of a population with at least 7/8 of
+                               its neurons spiking at t-1 are pulled instead: one lane per post
+                               neuron sums its column from a column-ordered copy), 2 fused
                                (no propagation kernel: each neuron-update block delivers its
                                own spikes' row chunks with atomics into a double-buffered
                                delivery buffer that the next update adds to G; only for
@@ -169,7 +172,14 @@ void snn_default_hh(double *p);
 /* Validate the description, copy every host array to the device and set
  * every Traub-Miles neuron to its resting point (the root of the
  * steady-state membrane current in [-80, -60] mV), conductances and traces
- * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL. */
+ * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL.
+ * Device memory beyond the state: the CRS arrays (8 B per synapse plus row
+ * starts); for every non-plastic projection a column-ordered copy used by
+ * tile mode's pull delivery (12 B per synapse plus padding of its 64-column
+ * slices to their longest column), built only while the weight pool has
+ * fewer than 2^31 synapses; for plastic projections the column view of
+ * potentiation (8 B per synapse); the tile-mode partial tiles (8 B per post
+ * tile column and pre spike word); the work queues. */
 int snn_create(const snn_config *cfg, snn_net **out);
 
 /* Release every device buffer.  NULL is ignored. */
