@@ -398,6 +398,47 @@ def test_pull_delivery_agrees_bitwise(snn):
     b.close()
 
 
+def test_pull_delivery_paths(snn):
+    """The pull delivery's other paths against row mode, bitwise: spike words
+    looked up in global memory (a pulled population of 70 000 neurons), copied
+    into LDS in a loop (65 to 1024 words), single-chunk slices adding into G
+    directly, deep slices reduced in one group and in several groups with
+    atomics (columns of 5000 entries), and a partial last slice."""
+    say("case: pull delivery paths")
+    rng = np.random.default_rng(21)
+    pops = [dict(name="A", kind="poisson", n=70000, rate_hz=9500.0, i_ext=0.0),
+            dict(name="B", kind="hh", n=5000, rate_hz=0.0, i_ext=0.0),
+            dict(name="C", kind="hh", n=100, rate_hz=0.0, i_ext=0.0),
+            dict(name="D", kind="poisson", n=6000, rate_hz=9500.0, i_ext=0.0)]
+    projs = []
+    for pre, post, p, tau, erev in [(0, 1, 0.0005, netgen.TAU_AB, netgen.E_EXC), (3, 1, 0.02, netgen.TAU_AB, netgen.E_EXC),
+                                    (1, 2, 1.0, netgen.TAU_BC, netgen.E_EXC), (2, 2, 1.0, netgen.TAU_CC, netgen.E_INH)]:
+        n_pre, n_post = pops[pre]["n"], pops[post]["n"]
+        rp, ci = netgen.bernoulli_csr(rng, n_pre, n_post, p, no_self=(pre == post))
+        projs.append(dict(pre=pre, post=post, row_ptr=rp, col_idx=ci,
+                          g=netgen.uniform_weights(rng, ci.size, 0.05 / (n_pre * p)),
+                          e_rev=erev, tau=tau, stdp=None))
+    inst = dict(g_scale=0.05, seed=(6 << 20) + 3, pops=pops, projs=projs)
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    a = snn.Network(spec)
+    b = snn.Network(spec)
+    b.set_launch(mode=1)
+    for n in (40, 20, 20):
+        a.step(n)
+        b.step(n)
+        _same_network_state(a, b, spec)
+        for p in (1, 2):       # every B and C neuron spiked at t - 1
+            ones = np.ones(pops[p]["n"], np.uint8)
+            a.set_last_spikes(0, p, ones)
+            b.set_last_spikes(0, p, ones)
+    a.step(5)
+    b.step(5)
+    _same_network_state(a, b, spec)
+    assert a.nan_counts()[0] == 0
+    a.close()
+    b.close()
+
+
 def _same_network_state(a, b, spec):
     inst = spec["instances"][0]
     for p in range(len(inst["pops"])):
