@@ -214,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                     const uint32_t before = atomicAdd(&a.scnt[cur * a.n_segs + sidx], pc);
                     // the wave that takes the population's spike count over
                     // the pull threshold marks the population for pulling
-                    const uint32_t thr = ((uint32_t)S.n * kPullNum + kPullDen - 1) / kPullDen;
+                    const uint32_t thr = (uint32_t)(((uint64_t)S.n * kPullNum + kPullDen - 1) / kPullDen);
                     if (S.pullable && before < thr && before + pc >= thr) {
                         a.pullf[cur * a.n_segs + sidx] = 1u;
                         atomicAdd(&a.st->npull[cur], 1u);

@@ -1326,7 +1326,7 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     if (net->launch.mode == kModeTiles)
         for (size_t g = 0; g < nseg; ++g) {
             const Seg &G = net->segs[g];
-            const uint32_t thr = ((uint32_t)G.n * kPullNum + kPullDen - 1) / kPullDen;
+            const uint32_t thr = (uint32_t)(((uint64_t)G.n * kPullNum + kPullDen - 1) / kPullDen);
             if (G.pullable && spk[g] >= thr) {
                 pf[(size_t)slot * nseg + g] = 1;
                 ++np;
