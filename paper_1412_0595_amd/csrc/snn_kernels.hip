@@ -101,7 +101,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     __shared__ int4 s_fl[kFusedCap];             // fused: (projection, k0, k1, -) per chunk
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform: scalar loads below
     const int nwb = blockDim.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * nwb + wid;
     const int64_t t = a.st->t_neuron;
@@ -111,29 +111,43 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     uint32_t nq = 0, nl = 0;       // work items this lane emits
     uint32_t wslot = 0;            // slot of this wave's word in the active list
     uint64_t wball = 0;            // this wave's spike word
-    int sidx = 0;
     int32_t j = 0;
     uint32_t cnt = 0;              // prefetched spike count
     int32_t ra0 = 0, ra1 = 0, rb0 = 0, rb1 = 0;   // prefetched rows of outgoing projections 0 and 1
     float trv[kMaxTr] = {};        // prefetched traces
 
+    // The population record's fields that the update reads, loaded together
+    // before the first branch: one round trip (read at first use, behind
+    // branches, each would cost one).  Waves past the last neuron read the
+    // last wave's record and store nothing.
+    const int sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[min(gw, a.n_waves - 1)]);
+    const Seg &S = a.segs[sidx];
+    const int64_t s_b = S.base;
+    const int32_t s_n = S.n, s_kind = S.kind, s_nout = S.n_out, s_nin = S.n_in, s_ntr = S.n_tr, s_nltp = S.n_ltp;
+    const int32_t s_rec = S.record_vbar, s_op0 = S.out_proj[0], s_op1 = S.out_proj[1];
+    const int64_t s_rp0 = S.out_rp[0], s_rp1 = S.out_rp[1];
+    int64_t s_inG[kMaxIn];
+#pragma unroll
+    for (int q = 0; q < kMaxIn; ++q) s_inG[q] = S.in_G[q];
+    asm volatile("" ::"s"(s_b), "s"(s_n), "s"(s_kind), "s"(s_nout), "s"(s_nin), "s"(s_ntr), "s"(s_nltp), "s"(s_rec));
+    asm volatile("" ::"s"(s_op0), "s"(s_op1), "s"(s_rp0), "s"(s_rp1), "s"(s_inG[0]), "s"(s_inG[1]), "s"(s_inG[2]),
+                 "s"(s_inG[3]));
+
     if (gw < a.n_waves) {
-        sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[gw]);
-        const Seg &S = a.segs[sidx];
         const int64_t gid = gw * kWave + lane;
-        j = (int32_t)(gid - S.base);
-        const bool active = j < S.n;
+        j = (int32_t)(gid - s_b);
+        const bool active = j < s_n;
         // Every load of the update is issued up front and unconditionally,
         // so that they share one memory round trip: padded arrays at gid,
         // unpadded ones (conductances, traces, row starts) at jj, the index
         // clamped into the population.  Lanes past the population compute on
         // that data and store nothing.
-        const int32_t jj = active ? j : S.n - 1;
+        const int32_t jj = active ? j : s_n - 1;
         cnt = a.counts[gid];
         {
             // (used in rows mode; a missing projection reads rp_pool[0..1])
-            const int32_t *rpa = a.rp_pool + (S.n_out > 0 ? S.out_rp[0] + jj : 0);
-            const int32_t *rpb = a.rp_pool + (S.n_out > 1 ? S.out_rp[1] + jj : 0);
+            const int32_t *rpa = a.rp_pool + (s_nout > 0 ? s_rp0 + jj : 0);
+            const int32_t *rpb = a.rp_pool + (s_nout > 1 ? s_rp1 + jj : 0);
             ra0 = rpa[0];
             ra1 = rpa[1];
             rb0 = rpb[0];
@@ -141,10 +155,10 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         }
 #pragma unroll
         for (int q = 0; q < kMaxTr; ++q)
-            if (q < S.n_tr) trv[q] = a.trace[S.tr_base[q] + jj];
+            if (q < s_ntr) trv[q] = a.trace[S.tr_base[q] + jj];
 
-        if (S.kind == kHH) {
-            const double vs = S.record_vbar ? a.vsum[gid] : 0.0;
+        if (s_kind == kHH) {
+            const double vs = s_rec ? a.vsum[gid] : 0.0;
             double v = pair_load(a.vh, a.vl, gid);
             double m = pair_load(a.mh, a.ml, gid);
             double h = pair_load(a.hh, a.hl, gid);
@@ -156,9 +170,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             int64_t g[kMaxIn];
 #pragma unroll
             for (int q = 0; q < kMaxIn; ++q)
-                if (q < S.n_in) {
-                    g[q] = a.G[S.in_G[q] + jj];
-                    if (a.mode == kModeFused) g[q] += a.D[dcur + S.in_G[q] + jj];
+                if (q < s_nin) {
+                    g[q] = a.G[s_inG[q] + jj];
+                    if (a.mode == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
                 }
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
@@ -168,9 +182,9 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             if (active) {
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
-                    if (q < S.n_in) {
-                        a.G[S.in_G[q] + j] = fix_decay(g[q], S.in_decay[q]);
-                        if (a.mode == kModeFused) a.D[dcur + S.in_G[q] + j] = 0;
+                    if (q < s_nin) {
+                        a.G[s_inG[q] + j] = fix_decay(g[q], S.in_decay[q]);
+                        if (a.mode == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
                     }
                 spike = (v0 < 0.0) && (v >= 0.0);
                 pair_split(v, a.vh[gid], a.vl[gid]);
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 pair_split(h, a.hh[gid], a.hl[gid]);
                 pair_split(n, a.nh[gid], a.nl[gid]);
                 if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[S.inst], 1);
-                if (S.record_vbar) a.vsum[gid] = vs + v;
+                if (s_rec) a.vsum[gid] = vs + v;
             }
         } else {
             if (active) {
@@ -198,23 +212,23 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         if (active) {
 #pragma unroll
             for (int q = 0; q < kMaxTr; ++q)
-                if (q < S.n_tr) a.trace[S.tr_base[q] + j] = trv[q] * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
+                if (q < s_ntr) a.trace[S.tr_base[q] + j] = trv[q] * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
         }
         if (ball != 0 && a.mode == kModeTiles) {
             // the word is active: record it, and queue one propagation item
             // per (outgoing projection, post tile) for the next step
             if (lane == 0) {
-                const uint32_t words = (uint32_t)((S.n + kWave - 1) / kWave);
+                const uint32_t words = (uint32_t)((s_n + kWave - 1) / kWave);
                 wslot = atomicAdd(&a.awcnt[cur * a.n_segs + sidx], 1u);
                 // a slot beyond the population's word count can only come
                 // from repeating one step's update (kernel timing): no items
                 if (wslot < words) {
-                    a.awl[(int64_t)cur * a.n_waves + S.base / kWave + wslot] = (int32_t)(gw - S.base / kWave);
+                    a.awl[(int64_t)cur * a.n_waves + s_b / kWave + wslot] = (int32_t)(gw - s_b / kWave);
                     const uint32_t pc = (uint32_t)__popcll(ball);
                     const uint32_t before = atomicAdd(&a.scnt[cur * a.n_segs + sidx], pc);
                     // the wave that takes the population's spike count over
                     // the pull threshold marks the population for pulling
-                    const uint32_t thr = (uint32_t)(((uint64_t)S.n * kPullNum + kPullDen - 1) / kPullDen);
+                    const uint32_t thr = (uint32_t)(((uint64_t)s_n * kPullNum + kPullDen - 1) / kPullDen);
                     if (S.pullable && before < thr && before + pc >= thr) {
                         a.pullf[cur * a.n_segs + sidx] = 1u;
                         atomicAdd(&a.st->npull[cur], 1u);
@@ -227,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                                                      a.scnt[pv * a.n_segs + sidx], words);
                     a.gwsel[cur * a.n_segs + sidx] = gws;
                     if (wslot % gws == 0)
-                        for (int o = 0; o < S.n_out; ++o) nq += (uint32_t)S.out_tiles[o];
+                        for (int o = 0; o < s_nout; ++o) nq += (uint32_t)S.out_tiles[o];
                 }
             }
         }
@@ -237,14 +251,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             if (a.mode != kModeTiles) {
                 // one propagation item (fused: one chunk) per chunk of each
                 // outgoing row
-                if (S.n_out > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
-                if (S.n_out > 1) nq += ((uint32_t)(rb1 - rb0) + ch - 1) / ch;
-                for (int o = 2; o < S.n_out; ++o) {
+                if (s_nout > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
+                if (s_nout > 1) nq += ((uint32_t)(rb1 - rb0) + ch - 1) / ch;
+                for (int o = 2; o < s_nout; ++o) {
                     const int32_t *rp = a.rp_pool + S.out_rp[o];
                     nq += ((uint32_t)(rp[j + 1] - rp[j]) + ch - 1) / ch;
                 }
             }
-            for (int o = 0; o < S.n_ltp; ++o) {
+            for (int o = 0; o < s_nltp; ++o) {
                 const int32_t *cp = a.cp_pool + S.ltp_cp[o];
                 const uint32_t len = (uint32_t)(cp[j + 1] - cp[j]);
                 nl += (len + ch - 1) / ch;
@@ -286,31 +300,29 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     __syncthreads();
 
     if (a.mode == kModeRows && nq) {
-        const Seg &S = a.segs[sidx];
         const int32_t ch = a.chunk;
         int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
-        auto emit = [&](int o, int32_t r0, int32_t r1) {
+        auto emit = [&](int32_t proj, int32_t r0, int32_t r1) {
             for (int32_t k = r0; k < r1; k += ch, ++pos)
-                if (pos < a.qcap) qd[pos] = Item{S.out_proj[o], j, k, min(k + ch, r1), 0, 0};
+                if (pos < a.qcap) qd[pos] = Item{proj, j, k, min(k + ch, r1), 0, 0};
         };
-        if (S.n_out > 0) emit(0, ra0, ra1);
-        if (S.n_out > 1) emit(1, rb0, rb1);
-        for (int o = 2; o < S.n_out; ++o) {
+        if (s_nout > 0) emit(s_op0, ra0, ra1);
+        if (s_nout > 1) emit(s_op1, rb0, rb1);
+        for (int o = 2; o < s_nout; ++o) {
             const int32_t *rp = a.rp_pool + S.out_rp[o];
-            emit(o, rp[j], rp[j + 1]);
+            emit(S.out_proj[o], rp[j], rp[j + 1]);
         }
     }
     // tile mode: lane 0 counted the wave's items, all lanes write
     const uint32_t wave_nq = a.mode == kModeTiles ? __shfl(nq, 0, kWave) : 0u;
     if (wave_nq) {
-        const Seg &S = a.segs[sidx];
         const int64_t base = (int64_t)s_base[0] + s_woff[wid][0];
-        const int32_t word = (int32_t)(gw - S.base / kWave);
+        const int32_t word = (int32_t)(gw - s_b / kWave);
         const int32_t slot = (int32_t)__shfl(wslot, 0, kWave);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
         int32_t off = 0;
-        for (int o = 0; o < S.n_out; ++o) {
+        for (int o = 0; o < s_nout; ++o) {
             const int32_t nt = S.out_tiles[o];
             for (int32_t tl = lane; tl < nt; tl += kWave) {
                 const int64_t pos = base + off + tl;
@@ -320,11 +332,10 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         }
     }
     if (nl) {
-        const Seg &S = a.segs[sidx];
         const int32_t ch = a.chunk;
         int64_t pos = (int64_t)s_base[1] + s_woff[wid][1] + (il - nl);
         Item *ld = a.lqueue + (int64_t)cur * a.lcap;
-        for (int o = 0; o < S.n_ltp; ++o) {
+        for (int o = 0; o < s_nltp; ++o) {
             const int32_t *cp = a.cp_pool + S.ltp_cp[o];
             const int32_t k1 = cp[j + 1];
             for (int32_t k = cp[j]; k < k1; k += ch, ++pos)
