@@ -16,8 +16,14 @@
 //               arrays (Section 3), packed several rows to a batch of loads,
 //               adds the weights into its own LDS tile (columns within a row
 //               are distinct, so no atomics) and writes the tile out as the
-//               group's partial.
-//  k_reduce_partials  (tile mode) adds the groups' partial tiles into G.
+//               group's partial.  A population with at least 7/8 of its
+//               neurons spiking is pulled instead: after their items the
+//               wavefronts take units of the sliced-ELL column copies of its
+//               non-plastic projections, one lane per post neuron.
+//  k_reduce_partials  (tile mode) adds the groups' partial tiles, and the
+//               pull units' partial sums of deep slices, into G.
+//  k_gather_weights, k_check_weights  weight-pool maintenance (refresh of
+//               the column copies; finiteness and per-projection maxima).
 //  k_potentiate persistent grid, one wavefront per slice of the column of a
 //               post neuron that spiked (STDP potentiation).
 //

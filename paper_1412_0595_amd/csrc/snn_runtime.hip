@@ -742,7 +742,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
     if ((rc = check_range(net, colsum_bound, w_bound, net->gscale.data()))) return bail(rc);
     // sliced-ELL copies of the non-plastic projections (weight-pool positions
     // must fit the int32 permutation): columns by decreasing length, 64 to a
-    // slice, and one pull unit per kPullDepth entries of a slice's depth
+    // slice, a slice's depth split evenly into pull units of at most
+    // kPullDepth entries per column
     std::vector<std::vector<int32_t>> pcol(net->projs.size()), pord(net->projs.size());
     std::vector<int64_t> pull_slices;   // copy offset of each slice's entry (0, lane 0)
     std::vector<PullSlice> pull_red;
