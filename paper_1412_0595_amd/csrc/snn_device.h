@@ -101,9 +101,14 @@ __device__ __forceinline__ HHRates hh_rates(double v)
 {
     HHRates r;
     r.am = 1.28 * phi((-52.0 - v) * 0.25);
-    r.bm = 1.4 * phi((v + 25.0) * 0.2);
+    // bm and bh share one exponential: with x = (v + 25) / 5 and
+    // E = e^x - 1, e^(-x) = 1 / (1 + E), so 4 / (e^(-x) + 1) = 4 (1 + E) / (2 + E)
+    // (E overflowing means e^(-x) = 0, where bh is 4)
+    const double x2 = (v + 25.0) * 0.2;
+    const double e2 = expm1(x2);
+    r.bm = 1.4 * (x2 == 0.0 ? 1.0 : x2 / e2);
+    r.bh = e2 < 1e300 ? 4.0 * (1.0 + e2) / (2.0 + e2) : 4.0;
     r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
-    r.bh = 4.0 / (exp((-25.0 - v) * 0.2) + 1.0);
     r.an = 0.16 * phi((-50.0 - v) * 0.2);
     r.bn = 0.5 * exp((-55.0 - v) * 0.025);
     return r;
