@@ -26,13 +26,6 @@ __device__ __forceinline__ uint32_t philox_first_word(uint32_t x0, uint32_t x1, 
     return x0;
 }
 
-// phi(x) = x / (e^x - 1) with its limit 1 at x = 0; expm1 keeps it accurate
-// near 0, and a NaN argument gives NaN.
-__device__ __forceinline__ double phi(double x)
-{
-    return x == 0.0 ? 1.0 : x / expm1(x);
-}
-
 // Wave-wide inclusive sum (64 lanes).
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, int lane)
 {
@@ -97,19 +90,45 @@ struct HHRates {
     double am, bm, ah, bh, an, bn;
 };
 
+// am, bm and an are c x / (e^x - 1) (limit c at x = 0; expm1 keeps the
+// quotient accurate near 0).  bm and bh share one exponential: with
+// x2 = (v + 25) / 5 and E = e^x2 - 1, e^(-x2) = 1 / (1 + E), so
+// bh = 4 / (e^(-x2) + 1) = 4 (1 + E) / (2 + E) (E overflowing means e^(-x2) = 0,
+// where bh is 4).  The four quotients take one division: the reciprocal of
+// the product of the denominators, then products of the others.  A zero
+// denominator (x = 0 only) enters the product as 1; where the product is not
+// a finite nonzero number (V far outside the physiological range, or NaN)
+// the lane divides four times instead (the choice is the lane's own, so a
+// neuron's rates do not depend on the other neurons of its wavefront).  A
+// NaN voltage gives NaN rates.
 __device__ __forceinline__ HHRates hh_rates(double v)
 {
     HHRates r;
-    r.am = 1.28 * phi((-52.0 - v) * 0.25);
-    // bm and bh share one exponential: with x = (v + 25) / 5 and
-    // E = e^x - 1, e^(-x) = 1 / (1 + E), so 4 / (e^(-x) + 1) = 4 (1 + E) / (2 + E)
-    // (E overflowing means e^(-x) = 0, where bh is 4)
-    const double x2 = (v + 25.0) * 0.2;
-    const double e2 = expm1(x2);
-    r.bm = 1.4 * (x2 == 0.0 ? 1.0 : x2 / e2);
-    r.bh = e2 < 1e300 ? 4.0 * (1.0 + e2) / (2.0 + e2) : 4.0;
+    const double x1 = (-52.0 - v) * 0.25, x2 = (v + 25.0) * 0.2, x3 = (-50.0 - v) * 0.2;
+    const double e1 = expm1(x1), e2 = expm1(x2), e3 = expm1(x3);
+    const double f1 = x1 == 0.0 ? 1.0 : e1, f2 = x2 == 0.0 ? 1.0 : e2, f3 = x3 == 0.0 ? 1.0 : e3;
+    const double f4 = 2.0 + e2;
+    const double p12 = f1 * f2, p123 = p12 * f3, prod = p123 * f4;
+    double i1, i2, i3, i4;
+    if (isfinite(prod) && prod != 0.0) {
+        const double q = 1.0 / prod;
+        i4 = q * p123;
+        const double q123 = q * f4;
+        i3 = q123 * p12;
+        const double q12 = q123 * f3;
+        i2 = q12 * f1;
+        i1 = q12 * f2;
+    } else {
+        i1 = 1.0 / f1;
+        i2 = 1.0 / f2;
+        i3 = 1.0 / f3;
+        i4 = 1.0 / f4;
+    }
+    r.am = 1.28 * (x1 == 0.0 ? 1.0 : x1 * i1);
+    r.bm = 1.4 * (x2 == 0.0 ? 1.0 : x2 * i2);
+    r.an = 0.16 * (x3 == 0.0 ? 1.0 : x3 * i3);
+    r.bh = e2 < 1e300 ? 4.0 * (1.0 + e2) * i4 : 4.0;
     r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
-    r.an = 0.16 * phi((-50.0 - v) * 0.2);
     r.bn = 0.5 * exp((-55.0 - v) * 0.025);
     return r;
 }
