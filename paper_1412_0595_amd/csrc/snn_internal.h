@@ -170,7 +170,8 @@ struct StepState {
 // words at the population's own word offset).
 
 // A work item.  Row mode: synapses [k0, k1) of row `row` of projection
-// `proj`.  Tile mode: projection `proj`, post tile k0, spike word
+// `proj`, whose instance is `aux` (so that its g_scale is read alongside
+// the projection record).  Tile mode: projection `proj`, post tile k0, spike word
 // `row` of the pre population (64 pre neurons) with its bits, and the
 // word's slot k1 in the active list (the item of a group's first slot
 // processes the group).  Potentiation: synapses
@@ -178,7 +179,7 @@ struct StepState {
 struct Item {
     int32_t proj, row, k0, k1;
     uint64_t bits;      // propagation: the spike word itself
-    uint64_t pad_;
+    uint64_t aux;       // row mode: instance of the projection
 };
 
 struct NeuronArgs {
@@ -243,6 +244,7 @@ struct PropArgs {
     const uint32_t *gwsel;   // [2][n_segs]  words per group of each pre population
     uint32_t *pullf;         // [2][n_segs]  pull flags (the slot of this step is cleared here)
     int32_t n_segs;
+    int32_t n_inst;
     const int4 *units;       // tile mode: reduction units (projection, tile, first column, first group)
     int64_t n_units;
     const PullUnit *pull_units;

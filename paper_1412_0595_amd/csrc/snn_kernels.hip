@@ -130,14 +130,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     const Seg &S = a.segs[sidx];
     const int64_t s_b = S.base;
     const int32_t s_n = S.n, s_kind = S.kind, s_nout = S.n_out, s_nin = S.n_in, s_ntr = S.n_tr, s_nltp = S.n_ltp;
-    const int32_t s_rec = S.record_vbar, s_op0 = S.out_proj[0], s_op1 = S.out_proj[1];
+    const int32_t s_rec = S.record_vbar, s_op0 = S.out_proj[0], s_op1 = S.out_proj[1], s_inst = S.inst;
     const int64_t s_rp0 = S.out_rp[0], s_rp1 = S.out_rp[1];
     int64_t s_inG[kMaxIn];
 #pragma unroll
     for (int q = 0; q < kMaxIn; ++q) s_inG[q] = S.in_G[q];
     asm volatile("" ::"s"(s_b), "s"(s_n), "s"(s_kind), "s"(s_nout), "s"(s_nin), "s"(s_ntr), "s"(s_nltp), "s"(s_rec));
     asm volatile("" ::"s"(s_op0), "s"(s_op1), "s"(s_rp0), "s"(s_rp1), "s"(s_inG[0]), "s"(s_inG[1]), "s"(s_inG[2]),
-                 "s"(s_inG[3]));
+                 "s"(s_inG[3]), "s"(s_inst));
 
     if (gw < a.n_waves) {
         const int64_t gid = gw * kWave + lane;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 pair_split(m, a.mh[gid], a.ml[gid]);
                 pair_split(h, a.hh[gid], a.hl[gid]);
                 pair_split(n, a.nh[gid], a.nl[gid]);
-                if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[S.inst], 1);
+                if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[s_inst], 1);
                 if (s_rec) a.vsum[gid] = vs + v;
             }
         } else {
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         Item *qd = a.queue + (int64_t)cur * a.qcap;
         auto emit = [&](int32_t proj, int32_t r0, int32_t r1) {
             for (int32_t k = r0; k < r1; k += ch, ++pos)
-                if (pos < a.qcap) qd[pos] = Item{proj, j, k, min(k + ch, r1), 0, 0};
+                if (pos < a.qcap) qd[pos] = Item{proj, j, k, min(k + ch, r1), 0, (uint64_t)s_inst};
         };
         if (s_nout > 0) emit(s_op0, ra0, ra1);
         if (s_nout > 1) emit(s_op1, rb0, rb1);
@@ -564,27 +564,65 @@ __device__ __forceinline__ void slice_to_global(unsigned long long *G, const int
 // spiking row; 64-bit atomics add the fixed-point weights into G (+ the
 // depression of plastic rows).  Suited to sparse activity.
 // ---------------------------------------------------------------------------
+// Read-only tables of the row-mode propagation, through the constant address
+// space: nothing writes them while the kernel runs (the queue was filled by
+// the step's neuron update, a previous dispatch), so the compiler may read
+// them with scalar loads, several in one batch.
+using CItem = const __attribute__((address_space(4))) Item;
+using CProj = const __attribute__((address_space(4))) Proj;
+using CFloat = const __attribute__((address_space(4))) float;
+
 __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t = a.st->t_prop;
-    const int prev = (int)((t + 1) & 1);          // slot of step t - 1
-    const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
-    const Item *q = a.queue + (int64_t)prev * a.qcap;
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    uint32_t it = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t it0 = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    CItem *queue = (CItem *)a.queue;
+    CProj *projs = (CProj *)a.projs;
+    CFloat *gscale = (CFloat *)a.gscale;
+    // The wavefront's first item in both slots, the step counter and both
+    // slots' item counts are read together (one round trip); the slot of
+    // step t - 1 is picked after.
+    const int64_t i0 = min((int64_t)it0, a.qcap - 1);
+    CItem &F0 = queue[i0];
+    CItem &F1 = queue[a.qcap + i0];
+    const int32_t f0p = F0.proj, f0a = F0.k0, f0b = F0.k1, f0i = (int32_t)F0.aux;
+    const int32_t f1p = F1.proj, f1a = F1.k0, f1b = F1.k1, f1i = (int32_t)F1.aux;
+    const int64_t t = a.st->t_prop;
+    const uint32_t c0 = a.st->qcnt[0], c1 = a.st->qcnt[1];
+    asm volatile("" ::"s"(t), "s"(c0), "s"(c1), "s"(f0p), "s"(f0a), "s"(f0b), "s"(f0i), "s"(f1p), "s"(f1a), "s"(f1b),
+                 "s"(f1i), "s"(projs), "s"(gscale), "s"(a.col_pool), "s"(a.w_pool), "s"(a.G));
+    const int prev = (int)((t + 1) & 1);          // slot of step t - 1
+    const uint32_t n = min((uint32_t)a.qcap, prev ? c1 : c0);
+    CItem *q = queue + (int64_t)prev * a.qcap;
 
-    for (; it < n; it += nw) {
-        const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
-        const int32_t k0 = __builtin_amdgcn_readfirstlane(q[it].k0);
-        const int32_t k1 = __builtin_amdgcn_readfirstlane(q[it].k1);
-        const Proj &P = a.projs[proj];
-        if (k0 < 0 || k1 > P.nnz || k0 > k1) continue;   // malformed item
-        const double s = (double)a.gscale[P.inst] * kFixOne;
-        const int32_t *col = a.col_pool + P.syn_base;
-        float *w = a.w_pool + P.syn_base;
-        unsigned long long *G = (unsigned long long *)(a.G + P.G_base);
-        if (!P.stdp) {
+    for (uint32_t it = it0; it < n; it += nw) {
+        int32_t proj, k0, k1, inst;
+        if (it == it0) {
+            proj = prev ? f1p : f0p;
+            k0 = prev ? f1a : f0a;
+            k1 = prev ? f1b : f0b;
+            inst = prev ? f1i : f0i;
+        } else {
+            proj = q[it].proj;
+            k0 = q[it].k0;
+            k1 = q[it].k1;
+            inst = (int32_t)q[it].aux;
+        }
+        if (inst < 0 || inst >= a.n_inst) continue;   // malformed item
+        // the projection record's fields and the instance's g_scale, read
+        // together
+        CProj &P = projs[proj];
+        const int64_t nnz = P.nnz, syn_base = P.syn_base, G_base = P.G_base;
+        const int32_t p_inst = P.inst, stdp = P.stdp;
+        const float gs = gscale[inst];
+        asm volatile("" ::"s"(nnz), "s"(syn_base), "s"(G_base), "s"(p_inst), "s"(stdp), "s"(gs));
+        if (k0 < 0 || k1 > nnz || k0 > k1 || p_inst != inst) continue;   // malformed item
+        const double s = (double)gs * kFixOne;
+        const int32_t *col = a.col_pool + syn_base;
+        float *w = a.w_pool + syn_base;
+        unsigned long long *G = (unsigned long long *)(a.G + G_base);
+        if (!stdp) {
             slice_to_global(G, col, w, k0, k1, s, lane);
         } else {
             // batches of 8 x 64 entries at clamped indices: column and weight,

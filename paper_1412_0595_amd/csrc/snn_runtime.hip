@@ -318,6 +318,7 @@ PropArgs prop_args(snn_net *net)
     p.awl = net->awl;
     p.gwsel = net->gwsel;
     p.pullf = net->pullf;
+    p.n_inst = net->n_inst;
     p.pull_units = net->d_pull_units;
     p.n_pull_units = net->n_pull_units;
     p.pull_part = net->d_pull_part;
@@ -1306,7 +1307,8 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
                     for (uint64_t b = bits; b; b &= b - 1) {
                         const int32_t i = (int32_t)(w * kWave + __builtin_ctzll(b));
                         for (int32_t k = H.row_ptr[i]; k < H.row_ptr[i + 1]; k += ch)
-                            items.push_back(Item{G.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1]), 0, 0});
+                            items.push_back(Item{G.out_proj[o], i, k, std::min(k + ch, H.row_ptr[i + 1]), 0,
+                                                 (uint64_t)G.inst});
                     }
                 }
             }
