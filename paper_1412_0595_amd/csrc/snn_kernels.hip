@@ -559,18 +559,22 @@ __device__ __forceinline__ void slice_to_global(unsigned long long *G, const int
     }
 }
 
+// Read-only tables of the propagation kernels, through the constant address
+// space: nothing writes them while a kernel runs (the queue was filled by the
+// step's neuron update, a previous dispatch), so the compiler may read them
+// with scalar loads, several in one batch.
+using CItem = const __attribute__((address_space(4))) Item;
+using CProj = const __attribute__((address_space(4))) Proj;
+using CFloat = const __attribute__((address_space(4))) float;
+using CPullUnit = const __attribute__((address_space(4))) PullUnit;
+using CPullSlice = const __attribute__((address_space(4))) PullSlice;
+using CInt4 = const __attribute__((address_space(4))) int4;
+
 // ---------------------------------------------------------------------------
 // CSR propagation, row mode: one wavefront per work item = a chunk of one
 // spiking row; 64-bit atomics add the fixed-point weights into G (+ the
 // depression of plastic rows).  Suited to sparse activity.
 // ---------------------------------------------------------------------------
-// Read-only tables of the row-mode propagation, through the constant address
-// space: nothing writes them while the kernel runs (the queue was filled by
-// the step's neuron update, a previous dispatch), so the compiler may read
-// them with scalar loads, several in one batch.
-using CItem = const __attribute__((address_space(4))) Item;
-using CProj = const __attribute__((address_space(4))) Proj;
-using CFloat = const __attribute__((address_space(4))) float;
 
 __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 {
@@ -684,7 +688,7 @@ struct PullHdr {
 
 __device__ __forceinline__ PullHdr pull_hdr(const PropArgs &a, int64_t u)
 {
-    const PullUnit &U = a.pull_units[u];
+    CPullUnit &U = ((CPullUnit *)a.pull_units)[u];
     return PullHdr{U.e0, U.g_base, U.col_off, U.depth, U.pre_seg, U.inst, U.wbase, U.nwords, U.direct, U.ncols};
 }
 
@@ -776,12 +780,10 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
     long long *acc = s_acc[wid];
 
     for (uint32_t it = blockIdx.x * kPropWaves + wid; it < n; it += nw) {
-        const int32_t proj = __builtin_amdgcn_readfirstlane(q[it].proj);
-        const int32_t word0 = __builtin_amdgcn_readfirstlane(q[it].row);
-        const int32_t tile = __builtin_amdgcn_readfirstlane(q[it].k0);
-        const int32_t slot = __builtin_amdgcn_readfirstlane(q[it].k1);
-        const uint64_t bits0 = uniform_u64(q[it].bits);
-        const Proj &P = a.projs[proj];
+        CItem &I = ((CItem *)q)[it];
+        const int32_t proj = I.proj, word0 = I.row, tile = I.k0, slot = I.k1;
+        const uint64_t bits0 = I.bits;
+        CProj &P = ((CProj *)a.projs)[proj];
         if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) continue;   // malformed item
         if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;         // pulled instead
         // the item of the first slot of each group processes the whole group
@@ -963,12 +965,12 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
     const int64_t t = a.st->t_neuron;             // set by the propagation just before
     const int prev = (int)((t + 1) & 1);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; u < a.n_units; u += nw) {
-        const int32_t proj = __builtin_amdgcn_readfirstlane(a.units[u].x);
-        const int32_t tile = __builtin_amdgcn_readfirstlane(a.units[u].y);
-        const int32_t col0 = __builtin_amdgcn_readfirstlane(a.units[u].z);
-        const uint32_t chunk = (uint32_t)__builtin_amdgcn_readfirstlane(a.units[u].w);
-        const Proj &P = a.projs[proj];
+    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+         u < a.n_units; u += nw) {
+        CInt4 &U = ((CInt4 *)a.units)[u];
+        const int32_t proj = U.x, tile = U.y, col0 = U.z;
+        const uint32_t chunk = (uint32_t)U.w;
+        CProj &P = ((CProj *)a.projs)[proj];
         if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;   // pulled: no partials
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         if (na == 0) continue;
@@ -1011,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
             while (m) {
                 const int l = __builtin_ctzll(m);
                 m &= m - 1;
-                const PullSlice &S = a.pull_slices[g + (r + l) * nw];
+                CPullSlice &S = ((CPullSlice *)a.pull_slices)[g + (r + l) * nw];
                 const int64_t g_base = S.g_base;
                 const int32_t u0 = S.u0, nu = S.n_units, atomic = S.atomic;
                 const int32_t col = a.pull_col[(int64_t)S.col_off + lane];
