@@ -24,16 +24,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X fp64 vector peak (FMA = 2 flops)
 
-# Algorithmic traffic per unit (bytes), stated in the design notes:
+# Algorithmic traffic per unit (bytes):
 #  - propagation: 8 B per synaptic event (col_idx + weight) + 16 B per
 #    spiking row (its work item and its two row-start entries)
 #  - neuron update: per Traub-Miles neuron-step, 4 double-float state
 #    variables read and written (64 B) + 16 B per incoming projection
 #    (64-bit conductance read and written)
+#  - potentiation: per column entry of a post neuron that spiked, its CRS
+#    position and pre index (8 B), the weight read and written (8 B) and the
+#    pre-synaptic trace read (4 B)
 PROP_BYTES_PER_EVENT = 8
 PROP_BYTES_PER_ROW = 16
 NEURON_STATE_BYTES = 64
 NEURON_G_BYTES = 16
+POT_BYTES_PER_ENTRY = 20
 
 WORKLOADS = {
     1: "A=100 Poisson @20 Hz, B=1000 HH, C=100 HH; A->B p=0.5, B->C and C->C all-to-all; dt=0.1 ms, 3 Euler substeps",
@@ -358,7 +362,20 @@ def main():
         kern["neuron"]["bytes"] += prop_bytes
         del kern["propagate"]
     if prof["potentiate"][1]:
-        kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1], bytes=0)
+        # the potentiation launches walk the columns of the post neurons whose
+        # spikes were pending at the start or emitted in the window, less
+        # those still pending at its end
+        pot_entries = 0
+        for b, inst in enumerate(spec["instances"]):
+            for q in inst["projs"]:
+                if not q.get("stdp"):
+                    continue
+                k = q["post"]
+                cdeg = np.bincount(np.asarray(q["col_idx"]), minlength=inst["pops"][k]["n"]).astype(np.int64)
+                delivered = pend0[b][k] + (cb[b][k] - ca[b][k]) - net.last_spikes(b, k).astype(np.int64)
+                pot_entries += int((delivered * cdeg).sum())
+        kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1],
+                                  bytes=POT_BYTES_PER_ENTRY * pot_entries)
     # dominant = the larger share of kernel time over the profiled steps
     dom = max(kern, key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
