@@ -170,6 +170,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--instances", type=int, default=None, help="trim a batched workload")
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned launch shapes per network signature (read, and written after tuning)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=2000)
@@ -298,7 +300,7 @@ def main():
     spec = netgen.make_config(args.workload, n_instances=args.instances)
     n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
     n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
-    cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    cache = args.tune_cache
     t_make = time.perf_counter()
     net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=cache)
     t_make = time.perf_counter() - t_make
