@@ -341,6 +341,39 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
 int snn_backward(snn_net *net, const double *dL_dvbar_dev, float *dL_dg_dev, double *dL_dgscale_dev,
                  int64_t *mismatch);
 
+/* ---------------- Conductance-scale calibration (Section 5.1) ----------------
+ * Host routines over the per-run table of a conductance-scaling sweep (one
+ * row per run: nConn, gScale, avgSpike, NaN count), as in Fig. 1.  They keep
+ * no net, touch no GPU and allocate only host scratch. */
+
+/* Fig. 1's selection.  n_conn, g_scale, avg_spike: host double[n_runs];
+ * n_nans: host int32[n_runs] (the run's NaN count, snn_get_nan_counts);
+ * ref_run: index of the reference run, whose avgSpike is the target level.
+ * For every distinct nConn in ascending order, writes the nConn to
+ * group_n_conn[g] and to picked[g] the index of the run with a zero NaN count
+ * and a finite avgSpike closest to the reference level (ties: smaller gScale,
+ * then the earlier run), or -1 when the nConn has no such run; *n_groups
+ * receives the number of distinct nConn.  group_n_conn and picked are host
+ * arrays of at least n_runs entries.  SNN_EINVAL if n_runs < 1, a pointer is
+ * NULL, ref_run is out of range or has NaNs, or an nConn or gScale is not
+ * finite. */
+int snn_gscale_select(int64_t n_runs, const double *n_conn, const double *g_scale, const double *avg_spike,
+                      const int32_t *n_nans, int64_t ref_run, int64_t *n_groups, double *group_n_conn,
+                      int64_t *picked);
+
+/* Least-squares fit of the inverse scaling law gScale = k1 / (k2 + nConn) + k3
+ * (Section 5.1, Tables 1 and 2) to n_points points (host double[n_points]
+ * each): minimises the unweighted sum of squared gScale residuals over k2 >
+ * -min(nConn), so the curve has no pole over the data.  Writes k[0..2] =
+ * k1, k2, k3 (host double[3]) and, if mape_percent is not NULL, the mean
+ * absolute percentage error of the fitted law over the points.  SNN_EINVAL
+ * for fewer than three distinct nConn, a NULL array, a non-finite value or a
+ * gScale <= 0; SNN_ERANGE when the best k2 lies at the end of the searched
+ * range (the pole on the smallest nConn, or k2 running to infinity because
+ * the points lie on a straight line). */
+int snn_gscale_fit(int64_t n_points, const double *n_conn, const double *g_scale, double *k,
+                   double *mape_percent);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *snn_last_error(void);
 

@@ -328,4 +328,9 @@ hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, 
 hipError_t launch_check_weights(const float *w, const Proj *projs, int32_t n_projs, int64_t max_nnz, uint32_t *flag,
                                 uint32_t *wmax, hipStream_t s);
 
+
+// Records msg as the calling thread's last error (snn_last_error) and
+// returns code; for host routines that keep no net.
+int set_error(int code, const char *msg);
+
 }  // namespace snn

@@ -31,6 +31,12 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+int snn::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+namespace {
+
 // --------------------------- Traub-Miles rest point --------------------------
 // Steady-state gate value a / (a + b) and the membrane current with all gates
 // at steady state; the resting potential is its root in [-80, -60] mV.

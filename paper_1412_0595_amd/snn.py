@@ -27,7 +27,7 @@ EXPORTS = [
     "snn_set_last_spikes", "snn_get_vbar", "snn_get_nan_counts", "snn_set_gscale", "snn_get_weights",
     "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel", "snn_profile_steps",
     "snn_last_error", "snn_reset", "snn_weight_count", "snn_weight_offset", "snn_get_weights_device",
-    "snn_set_weights_device", "snn_forward_record", "snn_backward",
+    "snn_set_weights_device", "snn_forward_record", "snn_backward", "snn_gscale_select", "snn_gscale_fit",
 ]
 
 
@@ -121,6 +121,8 @@ def load():
         "snn_set_weights_device": (C.c_int, [vp, vp]),
         "snn_forward_record": (C.c_int, [vp, i32, i64, i32, vp]),
         "snn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
+        "snn_gscale_select": (C.c_int, [i64, vp, vp, vp, vp, i64, vp, vp, vp]),
+        "snn_gscale_fit": (C.c_int, [i64, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -445,3 +447,32 @@ def create_status(spec, **kw):
     if rc == SNN_OK:
         L.snn_destroy(h)
     return rc, msg
+
+
+def gscale_select(n_conn, g_scale, avg_spike, n_nans, ref_run):
+    """Fig. 1's selection over a sweep's per-run table (snn_gscale_select):
+    returns (distinct nConn ascending, picked run index per nConn or -1)."""
+    x = np.ascontiguousarray(n_conn, np.float64)
+    n = x.size
+    g = np.ascontiguousarray(g_scale, np.float64)
+    a = np.ascontiguousarray(avg_spike, np.float64)
+    z = np.ascontiguousarray(n_nans, np.int32)
+    assert g.size == n and a.size == n and z.size == n
+    groups = np.zeros(max(n, 1), np.float64)
+    picked = np.zeros(max(n, 1), np.int64)
+    ng = C.c_int64(0)
+    _check(load().snn_gscale_select(n, _p(x), _p(g), _p(a), _p(z), int(ref_run), C.byref(ng),
+                                    _p(groups), _p(picked)))
+    return groups[:ng.value].copy(), picked[:ng.value].copy()
+
+
+def gscale_fit(n_conn, g_scale):
+    """Least-squares k1, k2, k3 of gScale = k1 / (k2 + nConn) + k3 and the
+    fit's MAPE in percent (snn_gscale_fit)."""
+    x = np.ascontiguousarray(n_conn, np.float64)
+    y = np.ascontiguousarray(g_scale, np.float64)
+    assert x.size == y.size
+    k = np.zeros(3, np.float64)
+    mape = C.c_double(0.0)
+    _check(load().snn_gscale_fit(x.size, _p(x), _p(y), _p(k), C.byref(mape)))
+    return k, mape.value

@@ -1,0 +1,100 @@
+"""The library's conductance-scale calibration (snn_gscale_select and
+snn_gscale_fit, Section 5.1 and Fig. 1) against the FP64 calibration oracle.
+Both are host routines, so these run without a GPU: selections bit-exact,
+fitted coefficients to 1e-6 relative."""
+import numpy as np
+import pytest
+
+from oracle import calibrate as cal
+from paper_1412_0595_amd import snn
+
+
+def sweep_table(seed, n_conn_values, g_values, nan_frac=0.1, quantum=None):
+    rng = np.random.default_rng(seed)
+    x, g = np.meshgrid(n_conn_values, g_values, indexing="ij")
+    x, g = x.ravel().astype(np.float64), g.ravel().astype(np.float64)
+    perm = rng.permutation(x.size)
+    x, g = x[perm], g[perm]
+    a = 40.0 * g * x / 300.0 * rng.uniform(0.8, 1.2, x.size)
+    if quantum:
+        a = np.round(a / quantum) * quantum
+    z = (rng.random(x.size) < nan_frac).astype(np.int32) * rng.integers(1, 50, x.size).astype(np.int32)
+    ref = int(np.flatnonzero(z == 0)[0])
+    return x, g, a, z, ref
+
+
+@pytest.mark.parametrize("seed,quantum", [(1, None), (2, None), (3, 5.0), (4, 20.0)])
+def test_selection_matches_oracle(seed, quantum):
+    x, g, a, z, ref = sweep_table(seed, np.arange(100.0, 1001.0, 50.0), np.geomspace(0.1, 10.0, 24),
+                                  quantum=quantum)
+    a[seed::37] = np.nan
+    z[ref] = 0
+    a[ref] = 40.0
+    got = snn.gscale_select(x, g, a, z, ref)
+    want = cal.select(x, g, a, z, ref)
+    np.testing.assert_array_equal(got[0], want[0])
+    np.testing.assert_array_equal(got[1], want[1])
+
+
+def test_selection_group_without_clean_runs():
+    x = np.array([1.0, 1.0, 2.0, 3.0, 3.0])
+    a = np.array([5.0, 6.0, 5.0, 4.0, 7.0])
+    z = np.array([0, 0, 0, 1, 2], np.int32)
+    groups, picked = snn.gscale_select(x, np.ones(5), a, z, 2)
+    assert list(groups) == [1.0, 2.0, 3.0] and list(picked) == [0, 2, -1]
+
+
+def test_selection_errors():
+    with pytest.raises(snn.SNNError, match="reference run has NaNs"):
+        snn.gscale_select([1.0, 2.0], [1.0, 1.0], [1.0, 2.0], [3, 0], 0)
+    with pytest.raises(snn.SNNError, match="out of range"):
+        snn.gscale_select([1.0, 2.0], [1.0, 1.0], [1.0, 2.0], [0, 0], 2)
+    with pytest.raises(snn.SNNError, match="finite"):
+        snn.gscale_select([1.0, np.inf], [1.0, 1.0], [1.0, 2.0], [0, 0], 0)
+
+
+def laws():
+    return [((1.318e3, 1.099e2, -2.800e-1), np.arange(100.0, 1001.0, 50.0)),
+            ((1.118e-1, 9.810, 4.972e-5), np.arange(20.0, 501.0, 20.0)),
+            ((1.354e3, -6.338, 1.672e-3), np.arange(20.0, 501.0, 20.0)),
+            ((30.0, 0.0, 0.01), np.array([40.0, 60.0, 80.0, 120.0, 200.0]))]
+
+
+@pytest.mark.parametrize("i", range(4))
+@pytest.mark.parametrize("noise", [0.0, 0.02, 0.1])
+def test_fit_matches_oracle(i, noise):
+    k, x = laws()[i]
+    rng = np.random.default_rng(10 * i + int(100 * noise))
+    y = (k[0] / (k[1] + x) + k[2]) * (1.0 + noise * rng.standard_normal(x.size))
+    if np.any(y <= 0):
+        pytest.skip("noise drew a non-positive gScale")
+    got, mape = snn.gscale_fit(x, y)
+    want = cal.fit(x, y)
+    # no worse a sum of squares than the oracle's (up to rounding of the residuals)
+    assert cal.sse(got, x, y) <= cal.sse(want, x, y) * (1 + 1e-9) + 1e-24 * float(np.dot(y, y))
+    np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-9 * np.abs(want).max())
+    assert mape == pytest.approx(cal.mape(want, x, y), rel=1e-6, abs=1e-9)
+    if noise == 0.0:
+        np.testing.assert_allclose(got, k, rtol=1e-7, atol=1e-12)
+
+
+def test_fit_order_of_points_does_not_matter():
+    k, x = laws()[0]
+    rng = np.random.default_rng(7)
+    y = (k[0] / (k[1] + x) + k[2]) * (1.0 + 0.05 * rng.standard_normal(x.size))
+    p = rng.permutation(x.size)
+    a, _ = snn.gscale_fit(x, y)
+    b, _ = snn.gscale_fit(x[p], y[p])
+    np.testing.assert_allclose(a, b, rtol=1e-9)
+
+
+def test_fit_errors():
+    with pytest.raises(snn.SNNError, match="three distinct"):
+        snn.gscale_fit([100.0, 100.0, 200.0, 200.0], [1.0, 1.1, 0.5, 0.6])
+    with pytest.raises(snn.SNNError, match="> 0"):
+        snn.gscale_fit([100.0, 200.0, 300.0], [1.0, 0.0, 0.5])
+    with pytest.raises(snn.SNNError, match="finite"):
+        snn.gscale_fit([100.0, 200.0, np.nan], [1.0, 0.7, 0.5])
+    # points on a straight line: the law's best k2 runs to infinity
+    with pytest.raises(snn.SNNError, match="straight line"):
+        snn.gscale_fit([100.0, 200.0, 300.0, 400.0], [4.0, 3.0, 2.0, 1.0])
