@@ -77,14 +77,16 @@ def uniform_weights(rng, nnz, scale):
 
 
 def layered_instance(rng, n_a, n_b, n_c, *, rate_hz=20.0, p_ab=0.5, p_bc=1.0,
-                     g_scale=1.0, seed=0, stdp_bc=False, i_ext=0.0):
-    """One A(Poisson) -> B(HH) -> C(HH) network with C->C all-to-all inhibition."""
+                     g_scale=1.0, seed=0, stdp_bc=False, i_ext=0.0, ab_norm=None):
+    """One A(Poisson) -> B(HH) -> C(HH) network with C->C all-to-all inhibition.
+    A->B weights are U[0,1) * G0_AB / ab_norm, ab_norm = n_A * p_AB (the
+    expected in-degree) unless given."""
     pops = [dict(name="A", kind="poisson", n=int(n_a), rate_hz=float(rate_hz), i_ext=0.0),
             dict(name="B", kind="hh", n=int(n_b), rate_hz=0.0, i_ext=float(i_ext)),
             dict(name="C", kind="hh", n=int(n_c), rate_hz=0.0, i_ext=float(i_ext))]
     rp, ci = bernoulli_csr(rng, n_a, n_b, p_ab)
     ab = dict(pre=0, post=1, row_ptr=rp, col_idx=ci,
-              g=uniform_weights(rng, ci.size, G0_AB / (n_a * p_ab)),
+              g=uniform_weights(rng, ci.size, G0_AB / (n_a * p_ab if ab_norm is None else ab_norm)),
               e_rev=E_EXC, tau=TAU_AB, stdp=None)
     rp, ci = bernoulli_csr(rng, n_b, n_c, p_bc)
     g1 = G1_BC / (n_b * p_bc)
@@ -163,6 +165,29 @@ def make_config(k, *, n_instances=None, scale=1.0):
         spec["ckpt_every"] = 100
     else:
         raise ValueError(f"unknown workload {k}")
+    return spec
+
+
+def calibration_config(n_conn_values, g_scales, *, n_b=1000, n_c=100, p_ab=0.2, ref_n_conn=100.0,
+                       rate_hz=20.0, steps=5000, key=6000):
+    """A conductance-scaling sweep laid out for the calibration of Section 5.1
+    (Fig. 1): one instance per (nConn, gScale) pair, nConn being the expected
+    number of A inputs per B neuron (n_A = nConn / p_AB).  A->B weights are
+    normalised by the fixed ref_n_conn, so the drive of B grows with nConn
+    and gScale has to shrink to hold B's spiking level.  All gScale values of
+    one nConn share its connectivity and Poisson stream.  Returns the spec
+    with per-instance "n_conn" and the index of every instance under
+    "grid" as (nConn index, gScale index)."""
+    spec = dict(dt=0.1, substeps=3, instances=[], steps=int(steps), n_conn=[], grid=[])
+    for i, x in enumerate(n_conn_values):
+        n_a = int(round(float(x) / p_ab))
+        base = layered_instance(np.random.default_rng(key + 1 + i), n_a, n_b, n_c, rate_hz=rate_hz,
+                                p_ab=p_ab, p_bc=0.5, seed=instance_seed(key + 2, i), ab_norm=ref_n_conn)
+        for j, g in enumerate(g_scales):
+            inst = dict(base, g_scale=float(g))
+            spec["instances"].append(inst)
+            spec["n_conn"].append(float(x))
+            spec["grid"].append((i, j))
     return spec
 
 

@@ -1,0 +1,67 @@
+"""The calibration of Section 5.1 (Fig. 1) end to end: a (nConn, gScale)
+sweep stepped as one batched network on the GPU, its per-run table against
+the FP64 oracle's, and the library's selection and law fit against the
+calibration oracle's on the same table."""
+import numpy as np
+import pytest
+
+from oracle import calibrate as ocal
+from oracle import oracle as O
+from paper_1412_0595_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0595_amd import snn as S
+    S.load()
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_calibration_sweep_matches_oracle(snn):
+    from paper_1412_0595_amd import calibrate as cal
+    T = 1000
+    spec = netgen.calibration_config([20, 30, 40, 60, 80], 10.0 ** np.linspace(-1.0, 1.0, 17), n_b=200, n_c=20,
+                                     ref_n_conn=20.0, steps=T)
+    say(f"case: calibration sweep of {len(spec['instances'])} runs, {T} steps, batched on the GPU")
+    ref = cal.reference_run(spec, 20.0, 1.0)
+    net = snn.Network(spec)
+    net.step(T)
+    res = cal.calibrate(net, spec, ref)
+    # the per-run table against the oracle run by run
+    o_avg, o_nan, differing, total = [], [], 0, 0
+    for k, inst in enumerate(spec["instances"]):
+        orc = O.OracleNet(inst)
+        orc.step(T)
+        c = orc.counts(1)
+        g = net.spikes(k, 1)
+        differing += int(np.sum(c != g))
+        total += c.size
+        o_avg.append(c.mean())
+        o_nan.append(orc.nan_count)
+    net.close()
+    say(f"  B neurons with a different spike count: {differing} of {total}; NaN counts {res['n_nans'].sum()}")
+    assert differing <= total // 1000
+    assert list(res["n_nans"]) == o_nan
+    # selection and fit: bit-exact picks and 1e-6 coefficients on the same table
+    groups, picked = ocal.select(res["n_conn"], res["g_scale"], res["avg_spike"], res["n_nans"], ref)
+    np.testing.assert_array_equal(res["groups"], groups)
+    np.testing.assert_array_equal(res["picked"], picked)
+    ok = picked >= 0
+    k = ocal.fit(groups[ok], res["g_scale"][picked[ok]])
+    say(f"  picked gScale {res['g_scale'][picked].round(3).tolist()}; k {res['k'].tolist()} MAPE {res['mape']:.2f}%")
+    np.testing.assert_allclose(res["k"], k, rtol=1e-6, atol=1e-9 * np.abs(k).max())
+    assert res["mape"] == pytest.approx(ocal.mape(k, groups[ok], res["g_scale"][picked[ok]]), rel=1e-6)
+    # where the oracle's own table agrees, so does its selection
+    if np.array_equal(np.asarray(o_avg), res["avg_spike"]):
+        np.testing.assert_array_equal(ocal.select(res["n_conn"], res["g_scale"], o_avg, o_nan, ref)[1], picked)
+    # the calibrated gScale falls as nConn grows (more inputs, each as strong)
+    assert np.all(np.diff(res["g_scale"][picked]) <= 0)
