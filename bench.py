@@ -162,6 +162,68 @@ def adjoint_bench(args):
     print(json.dumps(rec))
 
 
+def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
+    """Roofline of the dominant kernel over `profile_steps` further live steps
+    (advances the network)."""
+    import numpy as np
+    # Per-kernel launch duration: `profile_steps` further live steps, each
+    # kernel launched directly with a start/stop hipEvent pair that the HIP
+    # runtime stamps with that dispatch's own begin and end.  The algorithmic
+    # bytes of those launches are counted exactly: the propagation launches
+    # deliver the spikes pending at the start plus those emitted during the
+    # window, less those still pending at its end.
+    pend0 = [[net.last_spikes(b, p).astype(np.int64) for p in range(len(spec["instances"][b]["pops"]))]
+             for b in range(len(spec["instances"]))]
+    ca = spike_totals(net, spec)
+    prof = net.profile_steps(profile_steps)
+    cb = spike_totals(net, spec)
+    pend_events = 0
+    pend_rows = 0
+    for b in range(len(spec["instances"])):
+        for p in range(len(spec["instances"][b]["pops"])):
+            delivered = pend0[b][p] + (cb[b][p] - ca[b][p]) - net.last_spikes(b, p).astype(np.int64)
+            n_out = sum(1 for q in spec["instances"][b]["projs"] if q["pre"] == p)
+            pend_events += int((delivered * deg[b][p]).sum())
+            pend_rows += int(delivered.sum()) * n_out
+    n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
+               for inst in spec["instances"] for k in range(len(inst["pops"])))
+    neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
+    prop_bytes = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
+    kern = {
+        "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_bytes),
+        "neuron": dict(ms=prof["neuron"][0], n=prof["neuron"][1], bytes=neuron_bytes * prof["neuron"][1]),
+    }
+    if kern["propagate"]["n"] == 0:
+        # fused delivery: the neuron update walks the rows itself
+        kern["neuron"]["bytes"] += prop_bytes
+        del kern["propagate"]
+    if prof["potentiate"][1]:
+        # the potentiation launches walk the columns of the post neurons whose
+        # spikes were pending at the start or emitted in the window, less
+        # those still pending at its end
+        pot_entries = 0
+        for b, inst in enumerate(spec["instances"]):
+            for q in inst["projs"]:
+                if not q.get("stdp"):
+                    continue
+                k = q["post"]
+                cdeg = np.bincount(np.asarray(q["col_idx"]), minlength=inst["pops"][k]["n"]).astype(np.int64)
+                delivered = pend0[b][k] + (cb[b][k] - ca[b][k]) - net.last_spikes(b, k).astype(np.int64)
+                pot_entries += int((delivered * cdeg).sum())
+        kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1],
+                                  bytes=POT_BYTES_PER_ENTRY * pot_entries)
+    # dominant = the larger share of kernel time over the profiled steps
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
+    roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+            "traffic": profiled_traffic("k_" + dom, workload) if workload is not None else None,
+            "profiled_steps": profile_steps,
+            "ms_per_launch": {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()},
+            "bytes_per_launch": {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}}
+    return roof
+
+
 def calibrate_bench(args):
     """The calibration of Section 5.1 (Fig. 1) end to end: the sweep over
     nConn = 100..1000 (step 50) x 25 gScale values in [0.1, 10] stepped as one
@@ -192,6 +254,9 @@ def calibrate_bench(args):
     t_fit = time.perf_counter()
     res = cal.calibrate(net, spec, ref)
     t_fit = time.perf_counter() - t_fit
+    # after the table is read: the profiled steps continue the runs
+    roof = live_roofline(net, spec, n_hh, out_degree_table(spec), args.profile_steps, None)
+    launch = net.launch
     net.close()
     picked = res["picked"]
     rec = {"metric": "calibration sweep (Fig. 1) neuron-steps/s", "value": n_hh * args.steps / (ms * 1e-3),
@@ -205,7 +270,7 @@ def calibrate_bench(args):
            "n_nans_total": int(res["n_nans"].sum()),
            "points": [[float(x), float(res["g_scale"][i]) if i >= 0 else None]
                       for x, i in zip(res["groups"], picked)],
-           "k": [float(v) for v in res["k"]], "mape_percent": res["mape"]}
+           "k": [float(v) for v in res["k"]], "mape_percent": res["mape"], "launch": launch, "roofline": roof}
     if not args.no_cpu:
         from oracle import oracle
         inst = spec["instances"][len(spec["instances"]) // 2]
@@ -397,61 +462,7 @@ def main():
     neuron_steps = n_hh * args.steps / sec
     events_s = events / sec
 
-    # Per-kernel launch duration: `profile_steps` further live steps, each
-    # kernel launched directly with a start/stop hipEvent pair that the HIP
-    # runtime stamps with that dispatch's own begin and end.  The algorithmic
-    # bytes of those launches are counted exactly: the propagation launches
-    # deliver the spikes pending at the start plus those emitted during the
-    # window, less those still pending at its end.
-    pend0 = [[net.last_spikes(b, p).astype(np.int64) for p in range(len(spec["instances"][b]["pops"]))]
-             for b in range(len(spec["instances"]))]
-    ca = spike_totals(net, spec)
-    prof = net.profile_steps(args.profile_steps)
-    cb = spike_totals(net, spec)
-    pend_events = 0
-    pend_rows = 0
-    for b in range(len(spec["instances"])):
-        for p in range(len(spec["instances"][b]["pops"])):
-            delivered = pend0[b][p] + (cb[b][p] - ca[b][p]) - net.last_spikes(b, p).astype(np.int64)
-            n_out = sum(1 for q in spec["instances"][b]["projs"] if q["pre"] == p)
-            pend_events += int((delivered * deg[b][p]).sum())
-            pend_rows += int(delivered.sum()) * n_out
-    n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
-               for inst in spec["instances"] for k in range(len(inst["pops"])))
-    neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
-    prop_bytes = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
-    kern = {
-        "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_bytes),
-        "neuron": dict(ms=prof["neuron"][0], n=prof["neuron"][1], bytes=neuron_bytes * prof["neuron"][1]),
-    }
-    if kern["propagate"]["n"] == 0:
-        # fused delivery: the neuron update walks the rows itself
-        kern["neuron"]["bytes"] += prop_bytes
-        del kern["propagate"]
-    if prof["potentiate"][1]:
-        # the potentiation launches walk the columns of the post neurons whose
-        # spikes were pending at the start or emitted in the window, less
-        # those still pending at its end
-        pot_entries = 0
-        for b, inst in enumerate(spec["instances"]):
-            for q in inst["projs"]:
-                if not q.get("stdp"):
-                    continue
-                k = q["post"]
-                cdeg = np.bincount(np.asarray(q["col_idx"]), minlength=inst["pops"][k]["n"]).astype(np.int64)
-                delivered = pend0[b][k] + (cb[b][k] - ca[b][k]) - net.last_spikes(b, k).astype(np.int64)
-                pot_entries += int((delivered * cdeg).sum())
-        kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1],
-                                  bytes=POT_BYTES_PER_ENTRY * pot_entries)
-    # dominant = the larger share of kernel time over the profiled steps
-    dom = max(kern, key=lambda k: kern[k]["ms"])
-    achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
-    roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-            "traffic": profiled_traffic("k_" + dom, args.workload),
-            "profiled_steps": args.profile_steps,
-            "ms_per_launch": {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()},
-            "bytes_per_launch": {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}}
+    roof = live_roofline(net, spec, n_hh, deg, args.profile_steps, args.workload)
 
     cpu = None
     if not args.no_cpu:
