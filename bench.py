@@ -225,55 +225,79 @@ def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
 
 
 def calibrate_bench(args):
-    """The calibration of Section 5.1 (Fig. 1) end to end: the sweep over
-    nConn = 100..1000 (step 50) x 25 gScale values in [0.1, 10] stepped as one
-    batched network (A = nConn / 0.2 Poisson inputs at 20 Hz, B = 1000,
-    C = 100), then the selection against the run at nConn 100, gScale 1 and
-    the fit of gScale = k1 / (k2 + nConn) + k3."""
+    """The calibration of Section 5.1 (Fig. 1) end to end: each (nConn,
+    gScale) sweep stepped as one batched network, then the selection against
+    the reference run (gScale 1 at the smallest nConn) and the fit of
+    gScale = k1 / (k2 + nConn) + k3.
+
+    layered: nConn = 100..1000 (step 50) x 25 gScale in [0.1, 10], A = nConn /
+    0.2 Poisson inputs at 20 Hz, B = 1000, C = 100.
+    lhi: the LHI variant, PN = 100..1000 (step 50) x 25 scales, KC = 1000,
+    DN = 100, with 20 and 40 LHI, the PN->KC and the PN->LHI scale each swept."""
     import numpy as np
     import torch
     from paper_1412_0595_amd import calibrate as cal
     from paper_1412_0595_amd import netgen, snn
-    n_conn = np.arange(100.0, 1001.0, 50.0)
     gs = 10.0 ** np.linspace(-1.0, 1.0, 25)
-    spec = netgen.calibration_config(n_conn, gs, n_b=1000, n_c=100, ref_n_conn=100.0, steps=args.steps)
-    ref = cal.reference_run(spec, 100.0, 1.0)
-    n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
-    n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
-    t_make = time.perf_counter()
-    net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=args.tune_cache)
-    t_make = time.perf_counter() - t_make
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    net.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    t_fit = time.perf_counter()
-    res = cal.calibrate(net, spec, ref)
-    t_fit = time.perf_counter() - t_fit
-    # after the table is read: the profiled steps continue the runs
-    roof = live_roofline(net, spec, n_hh, out_degree_table(spec), args.profile_steps, None)
-    launch = net.launch
-    net.close()
-    picked = res["picked"]
-    rec = {"metric": "calibration sweep (Fig. 1) neuron-steps/s", "value": n_hh * args.steps / (ms * 1e-3),
+    if args.model == "layered":
+        sweeps = [("layered: A->B scale, B spiking",
+                   netgen.calibration_config(np.arange(100.0, 1001.0, 50.0), gs, n_b=1000, n_c=100,
+                                             ref_n_conn=100.0, steps=args.steps))]
+        workload = ("calibration sweep: nConn 100..1000 step 50 x 25 gScale in [0.1, 10]; "
+                    "A = nConn/0.2 Poisson at 20 Hz, B = 1000 HH, C = 100 HH, p = 0.2/0.5")
+    else:
+        n_pn = np.arange(100, 1001, 50)
+        sweeps = [(f"LHI variant, {nl} LHI: PN->{sw.upper()} scale, {sw.upper()} spiking",
+                   netgen.mushroom_body_calibration_config(n_pn, gs, swept=sw, n_lhi=nl, n_kc=1000, n_dn=100,
+                                                           ref_n_pn=100, steps=args.steps))
+                  for nl in (20, 40) for sw in ("kc", "lhi")]
+        workload = ("LHI-variant calibration sweeps: PN 100..1000 step 50 x 25 scales in [0.1, 10]; PN Poisson at "
+                    "20 Hz, LHI 20 or 40, KC 1000, DN 100 HH; PN->KC p 0.2, PN->LHI p 0.5; PN->KC and PN->LHI "
+                    "scale each swept")
+    out, total_ns, total_ms, roof, launch = [], 0.0, 0.0, None, None
+    for label, spec in sweeps:
+        ref = cal.reference_run(spec, spec["n_conn"][0], 1.0)
+        n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
+        n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
+        t_make = time.perf_counter()
+        net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=args.tune_cache)
+        t_make = time.perf_counter() - t_make
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        net.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        t_fit = time.perf_counter()
+        res = cal.calibrate(net, spec, ref)
+        t_fit = time.perf_counter() - t_fit
+        if roof is None:
+            # after the table is read: the profiled steps continue the runs
+            roof = live_roofline(net, spec, n_hh, out_degree_table(spec), args.profile_steps, None)
+            launch = net.launch
+        net.close()
+        total_ns += n_hh * args.steps
+        total_ms += ms
+        out.append({"sweep": label, "runs": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn,
+                    "sweep_ms": ms, "ms_per_step": ms / args.steps, "create_s": t_make,
+                    "table_select_fit_ms": t_fit * 1e3,
+                    "reference": {"n_conn": spec["n_conn"][0], "g_scale": 1.0,
+                                  "avg_spike": float(res["avg_spike"][ref])},
+                    "n_nans_total": int(res["n_nans"].sum()),
+                    "points": [[float(x), float(res["g_scale"][i]) if i >= 0 else None]
+                               for x, i in zip(res["groups"], res["picked"])],
+                    "k": [float(v) for v in res["k"]], "mape_percent": res["mape"]})
+    rec = {"metric": "calibration sweep (Fig. 1) neuron-steps/s", "value": total_ns / (total_ms * 1e-3),
            "unit": "neuron-steps/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
-           "ms_per_step": ms / args.steps, "sweep_ms": ms, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "calibration sweep: nConn 100..1000 step 50 x 25 gScale in [0.1, 10]; "
-                                  "A = nConn/0.2 Poisson at 20 Hz, B = 1000 HH, C = 100 HH, p = 0.2/0.5",
-                      "runs": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn},
-           "create_s": t_make, "table_select_fit_ms": t_fit * 1e3,
-           "reference": {"n_conn": 100.0, "g_scale": 1.0, "avg_spike": float(res["avg_spike"][ref])},
-           "n_nans_total": int(res["n_nans"].sum()),
-           "points": [[float(x), float(res["g_scale"][i]) if i >= 0 else None]
-                      for x, i in zip(res["groups"], picked)],
-           "k": [float(v) for v in res["k"]], "mape_percent": res["mape"], "launch": launch, "roofline": roof}
+           "dtype": "f64", "data": "synthetic", "config": {"workload": workload, "sweeps": len(sweeps)},
+           "sweeps": out, "launch": launch, "roofline": roof}
     if not args.no_cpu:
         from oracle import oracle
-        inst = spec["instances"][len(spec["instances"]) // 2]
+        spec = sweeps[0][1]
+        mid = len(spec["instances"]) // 2
+        inst = spec["instances"][mid]
         orc = oracle.OracleNet(inst)
         nh = sum(p["n"] for p in inst["pops"] if p["kind"] == "hh")
         t0, steps = time.perf_counter(), 0
@@ -282,7 +306,7 @@ def calibrate_bench(args):
             steps += 50
         dt = time.perf_counter() - t0
         rec["cpu_baseline"] = {"value": nh * steps / dt, "unit": "neuron-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one run of the sweep (nConn {spec['n_conn'][len(spec['instances']) // 2]:.0f}), "
+                               "sample": f"one run of the first sweep (nConn {spec['n_conn'][mid]:.0f}), "
                                          f"{steps} steps, {dt:.1f} s"}
     print(json.dumps(rec), flush=True)
 
@@ -310,6 +334,8 @@ def parse():
     ap.add_argument("--ckpt-every", type=int, default=100)
     ap.add_argument("--calibrate", action="store_true",
                     help="the calibration of Fig. 1: (nConn, gScale) sweep, selection and law fit")
+    ap.add_argument("--model", choices=("layered", "lhi"), default="layered",
+                    help="calibration network: the layered model, or its LHI variant (two swept scales)")
     ap.add_argument("--sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration)")

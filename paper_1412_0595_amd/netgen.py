@@ -191,6 +191,70 @@ def calibration_config(n_conn_values, g_scales, *, n_b=1000, n_c=100, p_ab=0.2, 
     return spec
 
 
+# Lateral horn interneurons (LHI) of the insect-olfaction model: excited by
+# the projection neurons (PN), they inhibit the Kenyon cells (KC) feed-forward.
+G_PN_LHI = 0.1     # PN->LHI: g = U[0,1) * G_PN_LHI / ref_nConn_LHI
+G_LHI_KC = 0.02    # LHI->KC: g = U[0,1) * G_LHI_KC / n_LHI
+TAU_LHI_KC = 5.0
+
+
+def mushroom_body_instance(n_pn, n_lhi, *, n_kc=1000, n_dn=100, p_pn_kc=0.2, p_pn_lhi=0.5, rate_hz=20.0,
+                           ref_n_pn=100, scale_kc=1.0, scale_lhi=1.0, seed=0, conn_seed=0):
+    """The LHI variant of the layered model (Section 5.1's PN, LHI, KC, DN):
+    PN(Poisson) -> KC and PN -> LHI excitatory, LHI -> KC all-to-all
+    inhibitory, KC -> DN excitatory, DN -> DN all-to-all inhibitory.  PN->KC
+    and PN->LHI weights are normalised by the in-degree at ref_n_pn PNs and
+    multiplied by scale_kc and scale_lhi, the two swept conductance scales."""
+    rng = np.random.default_rng(conn_seed)
+    pops = [dict(name="PN", kind="poisson", n=int(n_pn), rate_hz=float(rate_hz), i_ext=0.0),
+            dict(name="LHI", kind="hh", n=int(n_lhi), rate_hz=0.0, i_ext=0.0),
+            dict(name="KC", kind="hh", n=int(n_kc), rate_hz=0.0, i_ext=0.0),
+            dict(name="DN", kind="hh", n=int(n_dn), rate_hz=0.0, i_ext=0.0)]
+    projs = []
+    rp, ci = bernoulli_csr(rng, n_pn, n_kc, p_pn_kc)
+    projs.append(dict(pre=0, post=2, row_ptr=rp, col_idx=ci, e_rev=E_EXC, tau=TAU_AB, stdp=None,
+                      g=(uniform_weights(rng, ci.size, G0_AB / (ref_n_pn * p_pn_kc)) * np.float32(scale_kc))))
+    rp, ci = bernoulli_csr(rng, n_pn, n_lhi, p_pn_lhi)
+    projs.append(dict(pre=0, post=1, row_ptr=rp, col_idx=ci, e_rev=E_EXC, tau=TAU_AB, stdp=None,
+                      g=(uniform_weights(rng, ci.size, G_PN_LHI / (ref_n_pn * p_pn_lhi)) * np.float32(scale_lhi))))
+    rp, ci = bernoulli_csr(rng, n_lhi, n_kc, 1.0)
+    projs.append(dict(pre=1, post=2, row_ptr=rp, col_idx=ci, e_rev=E_INH, tau=TAU_LHI_KC, stdp=None,
+                      g=uniform_weights(rng, ci.size, G_LHI_KC / n_lhi)))
+    rp, ci = bernoulli_csr(rng, n_kc, n_dn, 0.5)
+    projs.append(dict(pre=2, post=3, row_ptr=rp, col_idx=ci, e_rev=E_EXC, tau=TAU_BC, stdp=None,
+                      g=uniform_weights(rng, ci.size, G1_BC / (n_kc * 0.5))))
+    rp, ci = bernoulli_csr(rng, n_dn, n_dn, 1.0, no_self=True)
+    projs.append(dict(pre=3, post=3, row_ptr=rp, col_idx=ci, e_rev=E_INH, tau=TAU_CC, stdp=None,
+                      g=uniform_weights(rng, ci.size, G_INH_CC * 100.0 / n_dn)))
+    return dict(g_scale=1.0, seed=int(seed), pops=pops, projs=projs)
+
+
+def mushroom_body_calibration_config(n_pn_values, scales, *, swept="kc", n_lhi=20, n_kc=1000, n_dn=100,
+                                     p_pn_kc=0.2, p_pn_lhi=0.5, ref_n_pn=100, steps=5000, key=7000):
+    """Calibration sweep of the LHI variant for one of its two swept scales:
+    swept="kc" scales PN->KC (criterion: KC spiking, nConn = p_PN_KC * n_PN),
+    swept="lhi" scales PN->LHI (criterion: LHI spiking, nConn = p_PN_LHI *
+    n_PN); the other scale stays 1.  Runs of one PN count share connectivity
+    and Poisson stream.  The spec carries per-run "n_conn", the criterion
+    population under "pop" and the swept projection under "proj"."""
+    if swept not in ("kc", "lhi"):
+        raise ValueError("swept must be 'kc' or 'lhi'")
+    spec = dict(dt=0.1, substeps=3, instances=[], steps=int(steps), n_conn=[], grid=[],
+                pop=2 if swept == "kc" else 1, proj=0 if swept == "kc" else 1)
+    p = p_pn_kc if swept == "kc" else p_pn_lhi
+    for i, n_pn in enumerate(n_pn_values):
+        for j, s in enumerate(scales):
+            kw = dict(scale_kc=float(s)) if swept == "kc" else dict(scale_lhi=float(s))
+            inst = mushroom_body_instance(int(n_pn), n_lhi, n_kc=n_kc, n_dn=n_dn, p_pn_kc=p_pn_kc,
+                                          p_pn_lhi=p_pn_lhi, ref_n_pn=ref_n_pn, seed=instance_seed(key + 2, i),
+                                          conn_seed=key + 1 + i, **kw)
+            inst["g_scale_swept"] = float(s)
+            spec["instances"].append(inst)
+            spec["n_conn"].append(float(p * n_pn))
+            spec["grid"].append((i, j))
+    return spec
+
+
 def random_tiny(seed, *, n_pops=3, max_n=64, p=0.3, n_poisson=1, rate_hz=200.0, stdp=False,
                 integer_g=False, g_scale=1.0):
     """Small random network for brute-force checks: arbitrary sizes, empty rows,

@@ -98,3 +98,30 @@ def test_fit_errors():
     # points on a straight line: the law's best k2 runs to infinity
     with pytest.raises(snn.SNNError, match="straight line"):
         snn.gscale_fit([100.0, 200.0, 300.0, 400.0], [4.0, 3.0, 2.0, 1.0])
+
+
+def test_calibration_sweeps_layout():
+    """The sweep generators: nConn is the swept projection's design in-degree,
+    runs of one nConn share their connectivity and Poisson stream, and the
+    swept scale touches only the swept projection's weights."""
+    from paper_1412_0595_amd import calibrate as drv
+    from paper_1412_0595_amd import netgen
+    gs = [0.5, 1.0, 2.0]
+    spec = netgen.calibration_config([20, 40], gs, n_b=30, n_c=5, ref_n_conn=20.0, steps=10)
+    assert spec["n_conn"] == [20.0] * 3 + [40.0] * 3
+    assert [i["pops"][0]["n"] for i in spec["instances"]] == [100] * 3 + [200] * 3
+    assert drv.reference_run(spec, 20.0, 1.0) == 1
+    a, b = spec["instances"][0], spec["instances"][2]
+    assert a["seed"] == b["seed"] and a["projs"][0]["col_idx"] is b["projs"][0]["col_idx"]
+    for swept, proj, pop, p in (("kc", 0, 2, 0.2), ("lhi", 1, 1, 0.5)):
+        spec = netgen.mushroom_body_calibration_config([40, 60], gs, swept=swept, n_lhi=4, n_kc=30, n_dn=5,
+                                                       ref_n_pn=40, steps=10)
+        assert spec["pop"] == pop and spec["proj"] == proj
+        assert spec["n_conn"] == [p * 40] * 3 + [p * 60] * 3
+        assert drv.reference_run(spec, p * 40, 1.0) == 1
+        base, dbl = spec["instances"][1], spec["instances"][2]
+        assert base["seed"] == dbl["seed"]
+        for q, (qa, qb) in enumerate(zip(base["projs"], dbl["projs"])):
+            np.testing.assert_array_equal(qa["col_idx"], qb["col_idx"])
+            want = qa["g"] * np.float32(2.0) if q == proj else qa["g"]
+            np.testing.assert_array_equal(qb["g"], want)

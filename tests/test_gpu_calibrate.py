@@ -26,13 +26,12 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_calibration_sweep_matches_oracle(snn):
+def check_sweep(snn, spec, ref_n_conn, T):
+    """Step the sweep on the GPU, compare its table with the oracle's and the
+    library's selection and fit with the calibration oracle's."""
     from paper_1412_0595_amd import calibrate as cal
-    T = 1000
-    spec = netgen.calibration_config([20, 30, 40, 60, 80], 10.0 ** np.linspace(-1.0, 1.0, 17), n_b=200, n_c=20,
-                                     ref_n_conn=20.0, steps=T)
-    say(f"case: calibration sweep of {len(spec['instances'])} runs, {T} steps, batched on the GPU")
-    ref = cal.reference_run(spec, 20.0, 1.0)
+    pop = spec.get("pop", 1)
+    ref = cal.reference_run(spec, ref_n_conn, 1.0)
     net = snn.Network(spec)
     net.step(T)
     res = cal.calibrate(net, spec, ref)
@@ -41,14 +40,15 @@ def test_calibration_sweep_matches_oracle(snn):
     for k, inst in enumerate(spec["instances"]):
         orc = O.OracleNet(inst)
         orc.step(T)
-        c = orc.counts(1)
-        g = net.spikes(k, 1)
+        c = orc.counts(pop)
+        g = net.spikes(k, pop)
         differing += int(np.sum(c != g))
         total += c.size
         o_avg.append(c.mean())
         o_nan.append(orc.nan_count)
     net.close()
-    say(f"  B neurons with a different spike count: {differing} of {total}; NaN counts {res['n_nans'].sum()}")
+    say(f"  criterion neurons with a different spike count: {differing} of {total}; "
+        f"NaN counts {res['n_nans'].sum()}")
     assert differing <= total // 1000
     assert list(res["n_nans"]) == o_nan
     # selection and fit: bit-exact picks and 1e-6 coefficients on the same table
@@ -65,3 +65,22 @@ def test_calibration_sweep_matches_oracle(snn):
         np.testing.assert_array_equal(ocal.select(res["n_conn"], res["g_scale"], o_avg, o_nan, ref)[1], picked)
     # the calibrated gScale falls as nConn grows (more inputs, each as strong)
     assert np.all(np.diff(res["g_scale"][picked]) <= 0)
+
+
+def test_calibration_sweep_matches_oracle(snn):
+    T = 1000
+    spec = netgen.calibration_config([20, 30, 40, 60, 80], 10.0 ** np.linspace(-1.0, 1.0, 17), n_b=200, n_c=20,
+                                     ref_n_conn=20.0, steps=T)
+    say(f"case: calibration sweep of {len(spec['instances'])} runs, {T} steps, batched on the GPU")
+    check_sweep(snn, spec, 20.0, T)
+
+
+@pytest.mark.parametrize("swept", ["kc", "lhi"])
+def test_lhi_variant_calibration_matches_oracle(snn, swept):
+    """The LHI variant (PN -> LHI -| KC feed-forward inhibition): the PN->KC
+    and the PN->LHI scale each swept with the other held at 1."""
+    T = 1000
+    spec = netgen.mushroom_body_calibration_config([40, 60, 80, 120, 160], 10.0 ** np.linspace(-1.0, 1.0, 17),
+                                                   swept=swept, n_lhi=20, n_kc=100, n_dn=10, ref_n_pn=40, steps=T)
+    say(f"case: LHI variant, PN->{swept.upper()} scale swept, {len(spec['instances'])} runs, {T} steps")
+    check_sweep(snn, spec, spec["n_conn"][0], T)
