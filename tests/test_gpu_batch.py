@@ -217,3 +217,28 @@ def test_memory_bytes_eq1(snn):
     expect = [4 * (2 * q["col_idx"].size + inst["pops"][q["pre"]]["n"] + 1) for q in inst["projs"]]
     assert net.memory_bytes().tolist() == expect
     net.close()
+
+
+def test_full_size_batch_sampled_parity(snn):
+    """Workload 4 at its full size (256 instances, 612 M synapses) in the
+    launch shape the autotuner picks, as the benchmark runs it: the smallest,
+    the median and the largest instance against the FP64 oracle."""
+    say("case: workload 4 full size, autotuned, 200 steps; instances 198 (smallest B), 141 (median), 147 (largest)")
+    spec = netgen.make_config(4)
+    T = 200
+    net = snn.Network(spec, autotune=True)
+    say(f"  launch {net.launch}")
+    net.step(T)
+    for k in (198, 141, 147):
+        orc = O.OracleNet(spec["instances"][k])
+        orc.step(T)
+        d = np.concatenate([net.state(k, p, snn.V) - orc.get(p, O.V) for p in (1, 2)])
+        rms = math.sqrt(np.mean(d * d))
+        same = [float(np.mean(net.spikes(k, p) == orc.counts(p))) for p in (1, 2)]
+        say(f"  instance {k} (B = {spec['instances'][k]['pops'][1]['n']}): V RMS {rms:.2e} mV, "
+            f"identical spike counts {same}")
+        assert rms < 1e-3
+        assert np.array_equal(net.spikes(k, 0), orc.counts(0))
+        assert min(same) > 0.999
+    say(f"  instances with NaNs: {int(np.sum(net.nan_counts() > 0))} of 256")
+    net.close()
