@@ -242,3 +242,38 @@ def test_full_size_batch_sampled_parity(snn):
         assert min(same) > 0.999
     say(f"  instances with NaNs: {int(np.sum(net.nan_counts() > 0))} of 256")
     net.close()
+
+
+def test_full_size_stdp_workload3(snn):
+    """Workload 3 at its full size (A=2000 @30 Hz, B=100000, C=1000; 91 M
+    synapses, plastic B->C) in the autotuned launch shape: 400 steps (C's
+    first volleys come near step 250, after which every plastic weight has
+    moved) against the FP64 oracle, voltages, spike counts and the plastic
+    weights."""
+    say("case: workload 3 full size, autotuned, 400 steps")
+    spec = netgen.make_config(3)
+    inst = spec["instances"][0]
+    T = 400
+    net = snn.Network(spec, autotune=True)
+    say(f"  launch {net.launch}")
+    orc = O.OracleNet(inst)
+    net.step(T)
+    orc.step(T)
+    d = np.concatenate([net.state(0, p, snn.V) - orc.get(p, O.V) for p in (1, 2)])
+    rms = math.sqrt(np.mean(d * d))
+    w_gpu = net.weights(0, 1).astype(np.float64)
+    w_orc = orc.weights(1)
+    w0 = inst["projs"][1]["g"].astype(np.float64)
+    changed = np.abs(w_orc - w0) > 0
+    rel = np.linalg.norm(w_gpu - w_orc) / np.linalg.norm(w_orc - w0)
+    same = [float(np.mean(net.spikes(0, p) == orc.counts(p))) for p in (1, 2)]
+    say(f"  V RMS {rms:.2e} mV; identical spike counts {same}; {changed.mean() * 100:.2f}% of plastic weights "
+        f"changed, |w_gpu - w_oracle| / |w_oracle - w0| = {rel:.2e}")
+    assert rms < 1e-3
+    assert np.array_equal(net.spikes(0, 0), orc.counts(0))
+    assert min(same) > 0.999
+    assert changed.mean() > 0.5
+    gmax = inst["projs"][1]["stdp"]["g_max"]
+    assert np.all(w_gpu >= 0) and np.all(w_gpu <= np.float32(gmax))
+    assert rel < 1e-3
+    net.close()

@@ -517,3 +517,32 @@ def test_vbar_accumulates_post_step_voltage(snn):
     assert np.allclose(vs, acc, rtol=0, atol=1e-9)
     assert np.max(np.abs(vs - orc.vsum(2))) < 1e-3
     net.close()
+
+
+def test_network_parity_workload2_1000_steps_autotuned(snn):
+    """Workload 2, the benchmark's network (A=1000, B=20000, C=1000; 15M
+    synapses), in the launch shape the autotuner picks: V RMS over the first
+    1000 steps (every 50th step) within 1e-3 mV, spike counts per neuron."""
+    say("case: workload 2, autotuned launch, 1000 steps")
+    spec = netgen.make_config(2)
+    inst = spec["instances"][0]
+    net = snn.Network(spec, autotune=True)
+    say(f"  launch {net.launch}")
+    orc = O.OracleNet(inst)
+    se, cnt = 0.0, 0
+    for _ in range(20):
+        net.step(50)
+        orc.step(50)
+        for p in (1, 2):
+            d = net.state(0, p, snn.V) - orc.get(p, O.V)
+            se += float(np.sum(d * d))
+            cnt += d.size
+    rms = math.sqrt(se / cnt)
+    say(f"  V RMS over steps 1..1000 (every 50th) = {rms:.3e} mV")
+    assert rms <= 1e-3
+    assert np.array_equal(net.spikes(0, 0), orc.counts(0))
+    for p in (1, 2):
+        a, b = net.spikes(0, p), orc.counts(p)
+        say(f"  pop {p}: counts identical for {np.mean(a == b) * 100:.3f}% of neurons, max |diff| {np.max(np.abs(a - b))}")
+        assert np.mean(a == b) > 0.999
+    net.close()
