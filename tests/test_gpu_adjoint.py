@@ -177,3 +177,49 @@ def test_instance_in_batch_has_the_gradient_it_has_alone(snn):
         alone.close()
         off += n_c
     net.close()
+
+
+def test_adjoint_full_size_sampled(snn):
+    """The adjoint workload at the benchmark's size (64 x (A=500, B=5000,
+    C=200), T = 2000, K = 100): instances 0 and 63 of the batched gradient
+    against the FP64 oracle adjoint on the GPU's raster."""
+    import torch
+    say("case: adjoint workload full size, T=2000, K=100; instances 0 and 63 against the oracle")
+    spec = netgen.make_config(5)
+    T, K = 2000, 100
+    net = snn.Network(spec, record_vbar=("C",))
+    vbar = net.forward_record(2, T, K)
+    vb = vbar.cpu().numpy()
+    L, dv = _loss_grad(vb, spec)
+    dg, ds, mism = net.backward(torch.tensor(dv, device=net.device), check=True)
+    say(f"  loss {L:.6e}; recomputed segments differing from checkpoints: {mism} values")
+    assert mism == 0
+    dg = dg.cpu().numpy().astype(np.float64)
+    ds = ds.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([inst["pops"][2]["n"] for inst in spec["instances"]])])
+    for b in (0, 63):
+        inst = spec["instances"][b]
+        off, n_c = int(offs[b]), inst["pops"][2]["n"]
+        ro, ri = _oracle_raster(net, spec, b, T)
+        orc = O.OracleNet(inst)
+        for p in (1, 2):
+            orc.set_replay(p, ro, ri, T)
+        vb_o, grads, ds_o = orc.adjoint(T, 2, dv[off:off + n_c])
+        dvb = np.max(np.abs(vb_o - vb[off:off + n_c]))
+        rel_s = abs(ds[b] - ds_o) / abs(ds_o)
+        # dL/ds = (1/s) sum g dL/dg: how far its terms cancel sets how much of
+        # the fp32 adjoint's error shows in it
+        mag = sum(float(np.abs(inst["projs"][q]["g"].astype(np.float64) * grads[q]).sum())
+                  for q in range(3)) / inst["g_scale"]
+        say(f"  instance {b}: max |Vbar gpu - oracle| {dvb:.2e} mV, dL/ds gpu {ds[b]:.6e} oracle {ds_o:.6e} "
+            f"rel {rel_s:.2e} (sum of |terms| {mag / abs(ds_o):.1f}x |dL/ds|; error / sum of |terms| "
+            f"{abs(ds[b] - ds_o) / mag:.1e})")
+        assert dvb < 1e-3
+        assert rel_s <= 1e-3
+        for q in (1, 2):
+            o = net.weight_offset(b, q)
+            nnz = inst["projs"][q]["col_idx"].size
+            rel = np.linalg.norm(dg[o:o + nnz] - grads[q]) / np.linalg.norm(grads[q])
+            say(f"    projection {q}: |dg gpu - oracle| / |dg oracle| = {rel:.2e}")
+            assert rel <= 1e-3
+    net.close()
