@@ -70,7 +70,8 @@ def profiled_traffic(kernel, workload):
     counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE passes, each scaled
     by the same counter's reading for a plain copy of known size), or None
     when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_workload{workload}_traffic.txt")
+    name = f"workload{workload}" if isinstance(workload, int) else str(workload)
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -275,7 +276,8 @@ def calibrate_bench(args):
         t_fit = time.perf_counter() - t_fit
         if roof is None:
             # after the table is read: the profiled steps continue the runs
-            roof = live_roofline(net, spec, n_hh, out_degree_table(spec), args.profile_steps, None)
+            roof = live_roofline(net, spec, n_hh, out_degree_table(spec), args.profile_steps,
+                                 "calibration_sweep" if args.model == "layered" else None)
             launch = net.launch
         net.close()
         total_ns += n_hh * args.steps
