@@ -427,6 +427,10 @@ def sweep(args):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
     if args.sources_sha:
         print(kernel_sources_sha256())
         return
@@ -447,10 +451,6 @@ def main():
     if args.calibrate:
         calibrate_bench(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
     import numpy as np
     import torch
     from paper_1412_0595_amd import netgen, snn
