@@ -165,3 +165,25 @@ def test_null_arguments():
     cnt = (ctypes.c_int64 * 3)()
     assert L.snn_profile_steps(None, 10, ms, cnt) == snn.SNN_EINVAL
     L.snn_destroy(None)
+
+
+def test_header_compiles_as_c_and_host_routines_run(tmp_path):
+    """include/snn.h is a plain C11 header; a C program linked against
+    libsnn.so calls the host calibration routines (no GPU involved)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    lib_dir = os.path.dirname(snn.LIB_PATH)
+    exe = str(tmp_path / "abi_calibrate")
+    subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "c", "abi_calibrate.c"), "-o", exe,
+                           "-L", lib_dir, "-lsnn", f"-Wl,-rpath,{lib_dir}", "-lm"])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    fit, sel = out.stdout.strip().splitlines()
+    k1, k2, k3, mape = (float(v) for v in fit.split())
+    assert k1 == pytest.approx(1318.0, rel=1e-7) and k2 == pytest.approx(109.9, rel=1e-7)
+    assert k3 == pytest.approx(-0.28, rel=1e-7) and mape < 1e-6
+    # nConn 10 -> run 0 (the reference); nConn 20 -> run 1 (|5.5 - 5| = |4 - 5| / 2; run 3 has NaNs)
+    assert sel.split() == ["2", "10", "0", "20", "1"]
