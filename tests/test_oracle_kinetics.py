@@ -223,3 +223,11 @@ def test_nan_counted_once_per_neuron(orc):
     assert net.nan_count == 2
     V = net.get(0, orc.V)
     assert not np.isfinite(V[0]) and np.isfinite(V[1]) and not np.isfinite(V[2])
+
+
+def test_kinetics_hand_derived_values(orc):
+    """Rates where their exponent is exactly +-1 (fixing the slope divisors),
+    the ionic current at gate values that separate m^3 h and n^4 from their
+    neighbouring powers, and the resting point of the unstimulated neuron."""
+    import tm_pins
+    assert tm_pins.violations(orc.lib(), orc.default_hh()) == []
