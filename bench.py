@@ -1,16 +1,19 @@
 """Benchmark of the spiking-network timestep on one MI355X.
 
-Default workload: A = 1000 Poisson sources at 20 Hz, B = 20000 and C = 1000
-Traub-Miles neurons, A->B p = 0.2, B->C p = 0.5, C->C all-to-all inhibitory
-(15.0 M synapses), dt = 0.1 ms with 3 Euler substeps.  A "step" is one
-timestep of the whole network: propagation of the previous step's spikes,
-the neuron update and spike compaction.
+Default workload: the batched conductance-scaling sweep, 256 independent
+instances of uneven size (A ~ LU[200, 1000] Poisson sources at 20 Hz,
+B ~ LU[2000, 20000] and C ~ LU[100, 1000] Traub-Miles neurons, A->B p = 0.2,
+B->C p = 0.5, C->C all-to-all inhibitory; g_scale ~ LU[0.1, 10] per
+instance; about 612 M synapses), stepped together, dt = 0.1 ms with 3 Euler
+substeps.  A "step" is one timestep of every instance: propagation of the
+previous step's spikes, the neuron update and spike compaction.
 
 Prints ONE JSON line: value = Traub-Miles neuron-steps per second over the
-timed steps (inputs already resident in HBM), plus synaptic events per
-second, the roofline of the dominant kernel (its per-launch duration from
-event-stamped launches over live steps after the timed region) and the FP64 oracle timed on a bounded
-sample on the host cores.
+timed steps (graph replays, inputs already resident in HBM), synaptic events
+per second, the roofline of the dominant kernel (per-launch durations from
+event-stamped launches over live steps after the timed region), the same
+instances stepped one at a time on the same kernels (per-instance loop), and
+the FP64 oracle timed on a bounded sample on the host cores.
 """
 import argparse
 import json
@@ -22,22 +25,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP64_VECTOR_TFLOPS = 78.6      # MI355X fp64 vector peak (FMA = 2 flops)
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz; fp64 FMA
+# issues at this full rate (78.6 fp64 TFLOP/s = 2 flops x 3.93e13)
+VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic traffic per unit (bytes):
-#  - propagation: 8 B per synaptic event (col_idx + weight) + 16 B per
-#    spiking row (its work item and its two row-start entries)
-#  - neuron update: per Traub-Miles neuron-step, 4 double-float state
-#    variables read and written (64 B) + 16 B per incoming projection
-#    (64-bit conductance read and written)
+# Algorithmic work per unit (the method's own data, not this library's
+# representation of it):
+#  - propagation: 8 B per synaptic event (col_idx + fp32 weight) + 12 B per
+#    spiking row (its two row-start entries and its spike id)
+#  - neuron update: per Traub-Miles neuron-step, V, m, h, n in fp32 read and
+#    written (32 B), the V compensation word read and written (8 B), and 8 B
+#    per incoming projection (fp32 conductance read and written); and about
+#    500 VALU lane-instructions (3 substeps of 6 exponentials, 4 divisions
+#    and about 50 other operations)
 #  - potentiation: per column entry of a post neuron that spiked, its CRS
 #    position and pre index (8 B), the weight read and written (8 B) and the
 #    pre-synaptic trace read (4 B)
 PROP_BYTES_PER_EVENT = 8
-PROP_BYTES_PER_ROW = 16
-NEURON_STATE_BYTES = 64
-NEURON_G_BYTES = 16
+PROP_BYTES_PER_ROW = 12
+NEURON_ALG_STATE_BYTES = 32
+NEURON_ALG_VLO_BYTES = 8
+NEURON_ALG_G_BYTES = 8
+NEURON_VALU_PER_STEP = 500
 POT_BYTES_PER_ENTRY = 20
+# What this library stores per unit (double-float state, 64-bit conductances,
+# 16 B per spiking row including its work item): bytes a launch moves beyond
+# the algorithmic ones
+NEURON_REPR_STATE_BYTES = 64
+NEURON_REPR_G_BYTES = 16
+PROP_REPR_BYTES_PER_ROW = 16
 
 WORKLOADS = {
     1: "A=100 Poisson @20 Hz, B=1000 HH, C=100 HH; A->B p=0.5, B->C and C->C all-to-all; dt=0.1 ms, 3 Euler substeps",
@@ -92,15 +108,26 @@ def sub_spec(spec, k):
     return dict(dt=spec["dt"], substeps=spec["substeps"], instances=[spec["instances"][k]])
 
 
-def time_loop(spec, steps, warmup):
-    """Every instance alone on the same kernels, one after the other; step
-    time only (hipEvents around each instance's steps)."""
+def time_loop(spec, steps, warmup, tune_cache=None):
+    """Every instance alone on the same kernels (autotuned, graph replays),
+    one after the other: `warmup` untimed steps and one untimed run of the
+    timed length (graph capture), then `steps` timed.  Returns the summed
+    step time (hipEvents around each instance's timed steps) and the synaptic
+    events of those steps."""
+    import numpy as np
     import torch
     from paper_1412_0595_amd import snn
     total_ms = 0.0
+    events = 0
     for k in range(len(spec["instances"])):
-        net = snn.Network(sub_spec(spec, k))
+        if k % 64 == 0:
+            note(f"per-instance loop: instance {k} of {len(spec['instances'])}")
+        sub = sub_spec(spec, k)
+        net = snn.Network(sub, autotune=True, tune_cache=tune_cache)
         net.step(warmup)
+        net.step(steps)
+        deg = out_degree_table(sub)
+        c0 = spike_totals(net, sub)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s = torch.cuda.current_stream()
         e0.record(s)
@@ -108,8 +135,11 @@ def time_loop(spec, steps, warmup):
         e1.record(s)
         e1.synchronize()
         total_ms += e0.elapsed_time(e1)
+        c1 = spike_totals(net, sub)
+        events += sum(int(((c1[0][p] - c0[0][p]) * deg[0][p]).sum()) for p in range(len(c0[0])))
         net.close()
-    return total_ms
+        del net
+    return total_ms, events
 
 
 def adjoint_bench(args):
@@ -165,14 +195,18 @@ def adjoint_bench(args):
 
 def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
     """Roofline of the dominant kernel over `profile_steps` further live steps
-    (advances the network)."""
+    (advances the network).
+
+    Per-kernel launch duration: every kernel of those steps is launched
+    directly with a start/stop hipEvent pair that the HIP runtime stamps with
+    that dispatch's own begin and end.  The algorithmic work of those launches
+    is counted exactly: the propagation launches deliver the spikes pending at
+    the start plus those emitted during the window, less those still pending
+    at its end.  A kernel's roofline is the tighter of its HBM bound
+    (algorithmic bytes / duration against 8 TB/s) and its VALU bound
+    (algorithmic lane-instructions / duration against the issue peak); the
+    dominant kernel is the one with the most time."""
     import numpy as np
-    # Per-kernel launch duration: `profile_steps` further live steps, each
-    # kernel launched directly with a start/stop hipEvent pair that the HIP
-    # runtime stamps with that dispatch's own begin and end.  The algorithmic
-    # bytes of those launches are counted exactly: the propagation launches
-    # deliver the spikes pending at the start plus those emitted during the
-    # window, less those still pending at its end.
     pend0 = [[net.last_spikes(b, p).astype(np.int64) for p in range(len(spec["instances"][b]["pops"]))]
              for b in range(len(spec["instances"]))]
     ca = spike_totals(net, spec)
@@ -188,15 +222,20 @@ def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
             pend_rows += int(delivered.sum()) * n_out
     n_in = sum(len([q for q in inst["projs"] if q["post"] == k]) * inst["pops"][k]["n"]
                for inst in spec["instances"] for k in range(len(inst["pops"])))
-    neuron_bytes = NEURON_STATE_BYTES * n_hh + NEURON_G_BYTES * n_in
-    prop_bytes = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
+    n_launch = prof["neuron"][1]
+    neuron_alg = neuron_alg_bytes(spec)
+    neuron_repr = NEURON_REPR_STATE_BYTES * n_hh + NEURON_REPR_G_BYTES * n_in
+    prop_alg = PROP_BYTES_PER_EVENT * pend_events + PROP_BYTES_PER_ROW * pend_rows
+    prop_repr = PROP_BYTES_PER_EVENT * pend_events + PROP_REPR_BYTES_PER_ROW * pend_rows
     kern = {
-        "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_bytes),
-        "neuron": dict(ms=prof["neuron"][0], n=prof["neuron"][1], bytes=neuron_bytes * prof["neuron"][1]),
+        "propagate": dict(ms=prof["propagate"][0], n=prof["propagate"][1], bytes=prop_alg, repr=prop_repr, valu=0),
+        "neuron": dict(ms=prof["neuron"][0], n=n_launch, bytes=neuron_alg * n_launch,
+                       repr=neuron_repr * n_launch, valu=NEURON_VALU_PER_STEP * n_hh * n_launch),
     }
     if kern["propagate"]["n"] == 0:
         # fused delivery: the neuron update walks the rows itself
-        kern["neuron"]["bytes"] += prop_bytes
+        kern["neuron"]["bytes"] += prop_alg
+        kern["neuron"]["repr"] += prop_repr
         del kern["propagate"]
     if prof["potentiate"][1]:
         # the potentiation launches walk the columns of the post neurons whose
@@ -212,16 +251,40 @@ def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
                 delivered = pend0[b][k] + (cb[b][k] - ca[b][k]) - net.last_spikes(b, k).astype(np.int64)
                 pot_entries += int((delivered * cdeg).sum())
         kern["potentiate"] = dict(ms=prof["potentiate"][0], n=prof["potentiate"][1],
-                                  bytes=POT_BYTES_PER_ENTRY * pot_entries)
-    # dominant = the larger share of kernel time over the profiled steps
+                                  bytes=POT_BYTES_PER_ENTRY * pot_entries, repr=POT_BYTES_PER_ENTRY * pot_entries,
+                                  valu=0)
+
+    def fracs(k):
+        sec = kern[k]["ms"] * 1e-3
+        hbm = kern[k]["bytes"] / sec / 1e9
+        alu = kern[k]["valu"] / sec / 1e12
+        return hbm, alu
+
     dom = max(kern, key=lambda k: kern[k]["ms"])
-    achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
-    roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-            "traffic": profiled_traffic("k_" + dom, workload) if workload is not None else None,
-            "profiled_steps": profile_steps,
-            "ms_per_launch": {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()},
-            "bytes_per_launch": {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}}
+    hbm, alu = fracs(dom)
+    per = lambda v: int(v / max(kern[dom]["n"], 1))
+    if alu / VALU_PEAK_TLANE > hbm / HBM_PEAK_GBS:
+        roof = {"kernel": "k_" + dom, "bound": "alu", "achieved": round(alu, 4), "peak": round(VALU_PEAK_TLANE, 3),
+                "unit": "T VALU lane-instructions/s", "frac": round(alu / VALU_PEAK_TLANE, 6),
+                "work_per_launch": per(kern[dom]["valu"]),
+                "work_per_unit": f"{NEURON_VALU_PER_STEP} VALU lane-instructions per Traub-Miles neuron-step"}
+    else:
+        roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(hbm, 3), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 6)}
+    roof["traffic"] = profiled_traffic("k_" + dom, workload) if workload is not None else None
+    roof["hbm"] = {"algorithmic_bytes_per_launch": per(kern[dom]["bytes"]),
+                   "achieved_GBs": round(hbm, 3), "frac": round(hbm / HBM_PEAK_GBS, 6),
+                   "stored_bytes_per_launch": per(kern[dom]["repr"])}
+    roof["profiled_steps"] = profile_steps
+    roof["ms_per_launch"] = {k: round(v["ms"] / max(v["n"], 1), 6) for k, v in kern.items()}
+    roof["algorithmic_bytes_per_launch"] = {k: int(v["bytes"] / max(v["n"], 1)) for k, v in kern.items()}
+    roof["share_of_kernel_time"] = {k: round(v["ms"] / sum(x["ms"] for x in kern.values()), 4)
+                                    for k, v in kern.items()}
+    if "propagate" in kern and dom != "propagate":
+        h, _ = fracs("propagate")
+        roof["propagate"] = {"achieved_GBs": round(h, 3), "frac": round(h / HBM_PEAK_GBS, 6),
+                             "events_per_launch": int(pend_events / max(kern["propagate"]["n"], 1)),
+                             "traffic": profiled_traffic("k_propagate", workload) if workload is not None else None}
     return roof
 
 
@@ -316,21 +379,24 @@ def calibrate_bench(args):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--preroll", type=int, default=1000,
+                    help="untimed steps before the warmup that leave the start-up transient of a network at rest")
+    ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--instances", type=int, default=None, help="trim a batched workload")
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of tuned launch shapes per network signature (read, and written after tuning)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-steps", type=int, default=2000)
+    ap.add_argument("--profile-steps", type=int, default=500)
     ap.add_argument("--sweep", action="store_true",
                     help="forced-activity sweep of the propagation kernel instead of the step benchmark")
     ap.add_argument("--sweep-workload", type=int, default=3)
-    ap.add_argument("--loop", action="store_true",
-                    help="batched workloads: also time every instance alone on the same kernels (per-instance loop)")
+    ap.add_argument("--loop", type=int, default=None,
+                    help="1: also time every instance alone on the same kernels (per-instance loop); "
+                         "default: on for batched workloads")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the recorded forward + reverse pass (gradient) instead of plain steps")
     ap.add_argument("--ckpt-every", type=int, default=100)
@@ -425,6 +491,195 @@ def sweep(args):
     net.close()
 
 
+def note(msg):
+    """Progress line on stderr (the result stays the one JSON line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """Cores this process may use (capped at 16, the host share of one GPU)
+    and the CPU model, read from the OS."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": avail, "threads": max(1, min(16, avail)), "cpu_model": model}
+
+
+def cpu_baseline(spec, seconds, max_instances=32):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: up to `max_instances` instances spread over the batch (all of a
+    single-instance workload), S steps each.  Single-thread runs step the
+    sample serially; all-core runs step the instances on a thread pool (a
+    batch) or run the neuron loop on OpenMP threads (one instance).  Median
+    of 3 runs each; S is sized so that the six runs take about `seconds`."""
+    import numpy as np
+    from oracle import oracle as O
+    hc = host_cpu()
+    n_inst = len(spec["instances"])
+    pick = sorted(set(np.linspace(0, n_inst - 1, min(max_instances, n_inst)).round().astype(int).tolist()))
+    nets = [O.OracleNet(spec["instances"][k]) for k in pick]
+    n_hh = sum(p["n"] for k in pick for p in spec["instances"][k]["pops"] if p["kind"] == "hh")
+    deg = out_degree_table(dict(instances=[spec["instances"][k] for k in pick]))
+    t0 = time.perf_counter()
+    O.step_many(nets, 5, 1)
+    per_step = (time.perf_counter() - t0) / 5
+    S = int(min(2000, max(10, seconds / 3.0 / 2.0 / per_step)))
+
+    def counts():
+        return [[net.counts(p).astype(np.int64) for p in range(len(net.pops))] for net in nets]
+
+    def run(threads):
+        if len(nets) == 1:
+            nets[0].set_threads(threads)
+        c0 = counts()
+        t = time.perf_counter()
+        O.step_many(nets, S, threads if len(nets) > 1 else 1)
+        el = time.perf_counter() - t
+        c1 = counts()
+        ev = sum(int(((c1[b][p] - c0[b][p]) * deg[b][p]).sum()) for b in range(len(nets)) for p in range(len(c0[b])))
+        return n_hh * S / el, ev / el
+
+    single = sorted(run(1) for _ in range(3))
+    multi = sorted(run(hc["threads"]) for _ in range(3))
+    for net in nets:
+        net.set_threads(1)
+    how = ("instances on a thread pool" if len(nets) > 1 else "neuron loop on OpenMP threads")
+    return {"value": multi[1][0], "unit": "neuron-steps/s", "cores": hc["threads"], "kind": "oracle",
+            "sample": f"{len(nets)} of {n_inst} instances ({n_hh} HH neurons), {S} steps per run after 5, "
+                      f"median of 3 runs; all-core: {how}",
+            "synaptic_events_per_s": multi[1][1],
+            "single_thread": {"value": single[1][0], "synaptic_events_per_s": single[1][1], "cores": 1},
+            "runs_neuron_steps_per_s": {"all_core": [r[0] for r in multi], "single": [r[0] for r in single]},
+            "host": hc}
+
+
+def neuron_alg_bytes(spec):
+    """Algorithmic bytes of one neuron-update launch: per Traub-Miles neuron,
+    V, m, h, n (fp32) read and written, the V compensation word read and
+    written, and each incoming projection's fp32 conductance read and written."""
+    tot = 0
+    for inst in spec["instances"]:
+        for k, p in enumerate(inst["pops"]):
+            if p["kind"] != "hh":
+                continue
+            n_in = sum(1 for q in inst["projs"] if q["post"] == k)
+            tot += p["n"] * (NEURON_ALG_STATE_BYTES + NEURON_ALG_VLO_BYTES + NEURON_ALG_G_BYTES * n_in)
+    return tot
+
+
+def step_bench(args):
+    import numpy as np
+    import torch
+    from paper_1412_0595_amd import netgen, snn
+
+    t_gen = time.perf_counter()
+    spec = netgen.make_config(args.workload, n_instances=args.instances)
+    t_gen = time.perf_counter() - t_gen
+    n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
+    n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
+    note(f"workload {args.workload}: {len(spec['instances'])} instances, {n_hh} HH neurons, {n_syn} synapses "
+         f"drawn in {t_gen:.1f} s")
+    t_make = time.perf_counter()
+    net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=args.tune_cache)
+    t_make = time.perf_counter() - t_make
+    note(f"created (autotune {args.autotune}) in {t_make:.1f} s: launch {net.launch}")
+    stream = torch.cuda.current_stream()
+
+    # untimed: the pre-roll leaves the start-up transient of a network started
+    # at rest; the warmup steps follow; one untimed run of the timed length
+    # captures the graphs the timed run replays
+    net.step(args.preroll)
+    net.step(args.warmup)
+    net.step(args.steps)
+    net.sync()
+    t_start = net.t
+    deg = out_degree_table(spec)
+    c0 = spike_totals(net, spec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    net.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    net.sync()
+    ms = e0.elapsed_time(e1)
+    c1 = spike_totals(net, spec)
+    events = 0
+    spikes = 0
+    for b in range(len(spec["instances"])):
+        for p in range(len(c0[b])):
+            d = c1[b][p] - c0[b][p]
+            spikes += int(d.sum())
+            events += int((d * deg[b][p]).sum())
+    nan_total = int(net.nan_counts().sum())
+    sec = ms * 1e-3
+    neuron_steps = n_hh * args.steps / sec
+    events_s = events / sec
+
+    note(f"timed {args.steps} steps: {ms / args.steps * 1e3:.2f} us per step")
+    roof = live_roofline(net, spec, n_hh, deg, args.profile_steps, args.workload)
+    note(f"profiled {args.profile_steps} live steps: {roof['ms_per_launch']}")
+    launch = net.launch
+    net.close()
+
+    rec = {
+        "metric": "neuron-steps/s + synaptic events/s (1 GPU); batched/adjoint vs plain loop",
+        "value": neuron_steps,
+        "unit": "neuron-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS.get(args.workload, f"workload {args.workload}"),
+                   "instances": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn,
+                   "preroll_steps": args.preroll,
+                   "timed_steps_start_at": t_start,
+                   "untimed_before_timed": "pre-roll (leaves the rest transient), warmup, and one run of the "
+                                           "timed length that captures the replayed graphs",
+                   "timed_region": "captured hipGraphs of whole steps (64-step graphs and one of the remainder)"},
+        "synaptic_events_per_s": events_s,
+        "spikes": spikes,
+        "nan_neurons_total": nan_total,
+        "wall_s": t_wall,
+        "netgen_s": t_gen,
+        "create_s": t_make,
+        "launch": launch,
+        "roofline": roof,
+    }
+    if args.loop is None:
+        args.loop = len(spec["instances"]) > 1
+    if args.loop and len(spec["instances"]) > 1:
+        note("per-instance loop")
+        loop_ms, loop_events = time_loop(spec, args.steps, args.preroll + args.warmup, args.tune_cache)
+        note(f"per-instance loop: {loop_ms:.2f} ms for {args.steps} steps")
+        rec["per_instance_loop"] = {"ms": loop_ms, "neuron_steps_per_s": n_hh * args.steps / (loop_ms * 1e-3),
+                                    "synaptic_events_per_s": loop_events / (loop_ms * 1e-3),
+                                    "batched_speedup": loop_ms / ms,
+                                    "how": "every instance alone on the same kernels (autotuned, graphs), "
+                                           "one after the other, same pre-roll and step count; step time only"}
+    if not args.no_cpu:
+        note("oracle sample on the host cores")
+    rec["cpu_baseline"] = None if args.no_cpu else cpu_baseline(spec, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -451,92 +706,7 @@ def main():
     if args.calibrate:
         calibrate_bench(args)
         return
-    import numpy as np
-    import torch
-    from paper_1412_0595_amd import netgen, snn
-
-    spec = netgen.make_config(args.workload, n_instances=args.instances)
-    n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
-    n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
-    cache = args.tune_cache
-    t_make = time.perf_counter()
-    net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=cache)
-    t_make = time.perf_counter() - t_make
-    stream = torch.cuda.current_stream()
-
-    net.step(args.warmup)
-    net.sync()
-    deg = out_degree_table(spec)
-    c0 = spike_totals(net, spec)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    net.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    net.sync()
-    ms = e0.elapsed_time(e1)
-    c1 = spike_totals(net, spec)
-    events = 0
-    spikes = 0
-    for b in range(len(spec["instances"])):
-        for p in range(len(c0[b])):
-            d = c1[b][p] - c0[b][p]
-            spikes += int(d.sum())
-            events += int((d * deg[b][p]).sum())
-    sec = ms * 1e-3
-    neuron_steps = n_hh * args.steps / sec
-    events_s = events / sec
-
-    roof = live_roofline(net, spec, n_hh, deg, args.profile_steps, args.workload)
-
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as O
-        inst = spec["instances"][0]
-        orc = O.OracleNet(inst)
-        n_hh0 = sum(p["n"] for p in inst["pops"] if p["kind"] == "hh")
-        orc.step(1)
-        t0 = time.perf_counter()
-        k = 0
-        while time.perf_counter() - t0 < args.cpu_seconds and k < args.steps:
-            orc.step(10)
-            k += 10
-        el = time.perf_counter() - t0
-        cpu = {"value": n_hh0 * k / el, "unit": "neuron-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"FP64 oracle, instance 0 of the same workload, {k} steps from step 1, single thread"}
-
-    rec = {
-        "metric": "neuron-steps/s + synaptic events/s (1 GPU); batched/adjoint vs plain loop",
-        "value": neuron_steps,
-        "unit": "neuron-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS.get(args.workload, f"workload {args.workload}"),
-                   "instances": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn},
-        "synaptic_events_per_s": events_s,
-        "spikes": spikes,
-        "wall_s": t_wall,
-        "create_s": t_make,
-        "launch": net.launch,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
-    net.close()
-    if args.loop and len(spec["instances"]) > 1:
-        loop_ms = time_loop(spec, args.steps, args.warmup)
-        rec["per_instance_loop"] = {"ms": loop_ms, "neuron_steps_per_s": n_hh * args.steps / (loop_ms * 1e-3),
-                                    "batched_speedup": loop_ms / ms}
-    print(json.dumps(rec))
+    step_bench(args)
 
 
 if __name__ == "__main__":

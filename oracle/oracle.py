@@ -28,7 +28,7 @@ def build(force=True):
     if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(s) for s in DEPS):
         return LIB
     tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp",
                            "-o", tmp, *srcs, "-lm"])
     os.replace(tmp, LIB)
     return LIB
@@ -72,6 +72,7 @@ def lib():
             "orc_get_last_spikes": (C.c_int, [vp, C.c_int, vp]),
             "orc_set_last_spikes": (C.c_int, [vp, C.c_int, vp]),
             "orc_nan_count": (i64, [vp]),
+            "orc_set_threads": (None, [vp, C.c_int]),
             "orc_time": (i64, [vp]),
             "orc_set_g_scale": (None, [vp, d]),
             "orc_log_events": (None, [vp, C.c_int]),
@@ -147,6 +148,20 @@ def philox(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def step_many(nets, n, threads=1):
+    """Advance independent instances by n steps each, on up to `threads`
+    host threads at once (ctypes drops the interpreter lock during each call,
+    so the instances really run in parallel).  Every instance does exactly
+    the arithmetic of a serial run."""
+    if threads <= 1 or len(nets) <= 1:
+        for net in nets:
+            net.step(n)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=int(threads)) as ex:
+        list(ex.map(lambda net: net.step(n), nets))
 
 
 class OracleNet:
@@ -255,6 +270,10 @@ class OracleNet:
     def set_last_spikes(self, pop, flags):
         a = np.ascontiguousarray(flags, np.uint8)
         lib().orc_set_last_spikes(self.h, int(pop), _p(a))
+
+    def set_threads(self, n):
+        """Run the HH neuron loop of every step on n OpenMP threads (1: serial)."""
+        lib().orc_set_threads(self.h, int(n))
 
     @property
     def nan_count(self):

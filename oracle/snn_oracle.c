@@ -346,6 +346,10 @@ void orc_phase_neurons(orc_net *net)
     for (int p = 0; p < net->n_pops; ++p) {
         opop *P = &net->pops[p];
         if (P->kind != ORC_HH) continue;
+        /* Neurons are independent within a step, so the loop may run on
+         * several threads; each neuron's arithmetic is the same either way. */
+        int64_t nan_new = 0;
+        #pragma omp parallel for schedule(static) reduction(+ : nan_new) num_threads(net->threads > 1 ? net->threads : 1) if (net->threads > 1)
         for (int j = 0; j < P->n; ++j) {
             double v0 = P->V[j];
             double isyn = 0.0;
@@ -357,9 +361,10 @@ void orc_phase_neurons(orc_net *net)
                 orc_substep(P->hh, hs, isyn + P->i_ext, &v, &m, &h, &n);
             P->V[j] = v; P->m[j] = m; P->h[j] = h; P->nn[j] = n;
             P->spk_now[j] = (v0 < 0.0 && v >= 0.0) ? 1 : 0;
-            if (isfinite(v0) && !isfinite(v)) net->nan_count++;
+            if (isfinite(v0) && !isfinite(v)) nan_new++;
             P->vsum[j] += v;
         }
+        net->nan_count += nan_new;
     }
     for (int q = 0; q < net->n_projs; ++q) {
         oproj *Q = &net->projs[q];
@@ -535,6 +540,7 @@ int orc_set_last_spikes(orc_net *net, int pop, const unsigned char *in)
 }
 
 int64_t orc_nan_count(orc_net *net) { return net->nan_count; }
+void orc_set_threads(orc_net *net, int n) { net->threads = n; }
 int64_t orc_time(orc_net *net) { return net->t; }
 void orc_set_g_scale(orc_net *net, double s) { net->g_scale = s; }
 

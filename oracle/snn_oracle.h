@@ -53,6 +53,7 @@ typedef struct orc_net {
     int64_t t;                   /* index of the next step */
     int64_t nan_count;           /* HH neurons whose V turned non-finite */
     int ready;
+    int threads;                 /* >1: the HH neuron loop runs on that many OpenMP threads */
     /* event log: (t, pop, id) of every spike, when enabled */
     int log_events;
     int64_t ev_n, ev_cap;

@@ -190,10 +190,11 @@ struct snn_net {
     uint32_t *d_wmax;        // per projection: bits of the largest weight (weight checks)
     int64_t max_nnz;
 
-    // launch shape and graph
+    // launch shape and captured step sequences: graphs[k] replays
+    // graph_len[k] whole steps (kGraphSteps, and the remainders asked for)
     snn_launch launch;
-    hipGraphExec_t graph_exec;
-    int graph_steps;
+    std::vector<hipGraphExec_t> graphs;
+    std::vector<int> graph_len;
 };
 
 namespace {
@@ -223,12 +224,16 @@ void dev_free(snn_net *net, void *p)
         }
 }
 
+void drop_graphs(snn_net *net)
+{
+    for (hipGraphExec_t g : net->graphs) (void)hipGraphExecDestroy(g);
+    net->graphs.clear();
+    net->graph_len.clear();
+}
+
 void release(snn_net *net)
 {
-    if (net->graph_exec) {
-        (void)hipGraphExecDestroy(net->graph_exec);
-        net->graph_exec = nullptr;
-    }
+    drop_graphs(net);
     for (void *p : net->allocs) {
         if (net->free_fn) net->free_fn(p, net->alloc_ctx); else (void)hipFree(p);
     }
@@ -365,48 +370,78 @@ hipError_t enqueue_step(snn_net *net, hipStream_t s)
 }
 
 constexpr int kGraphSteps = 64;
+constexpr size_t kMaxGraphs = 8;   // the full-length graph plus a few remainders
 
-int build_graph(snn_net *net)
+// The captured graph of n whole steps (built on first use).  The step
+// counters live on the device, so one capture serves every later replay.
+int graph_for(snn_net *net, int n, hipGraphExec_t *out)
 {
-    if (net->graph_exec) {
-        (void)hipGraphExecDestroy(net->graph_exec);
-        net->graph_exec = nullptr;
+    for (size_t k = 0; k < net->graphs.size(); ++k)
+        if (net->graph_len[k] == n) {
+            *out = net->graphs[k];
+            return SNN_OK;
+        }
+    if (net->graphs.size() >= kMaxGraphs) {
+        // evict the oldest remainder; the full-length graph stays
+        for (size_t k = 0; k < net->graphs.size(); ++k)
+            if (net->graph_len[k] != kGraphSteps) {
+                (void)hipGraphExecDestroy(net->graphs[k]);
+                net->graphs.erase(net->graphs.begin() + (long)k);
+                net->graph_len.erase(net->graph_len.begin() + (long)k);
+                break;
+            }
     }
     hipGraph_t g = nullptr;
     HIP_OK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(net, net->cap_stream);
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = enqueue_step(net, net->cap_stream);
     hipError_t e2 = hipStreamEndCapture(net->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         net->sticky = true;
         return fail(SNN_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    e = hipGraphInstantiate(&net->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        net->graph_exec = nullptr;
         net->sticky = true;
         return fail(SNN_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    net->graph_steps = kGraphSteps;
+    net->graphs.push_back(x);
+    net->graph_len.push_back(n);
+    *out = x;
     return SNN_OK;
 }
 
+// Capture, ahead of time, every graph run_steps(n) will replay.
+int prepare_graphs(snn_net *net, int64_t n)
+{
+    hipGraphExec_t g = nullptr;
+    int rc = SNN_OK;
+    if (n >= kGraphSteps) rc = graph_for(net, kGraphSteps, &g);
+    if (!rc && n % kGraphSteps) rc = graph_for(net, (int)(n % kGraphSteps), &g);
+    return rc;
+}
+
+// n steps as replays of captured graphs: n div 64 of the 64-step graph, then
+// one graph of the remaining n mod 64 steps.
 int run_steps(snn_net *net, int64_t n)
 {
-    if (n >= kGraphSteps && !net->graph_exec) {
-        int rc = build_graph(net);
-        if (rc) return rc;
+    int rc = prepare_graphs(net, n);
+    if (rc) return rc;
+    hipGraphExec_t g = nullptr;
+    if (n >= kGraphSteps) {
+        if ((rc = graph_for(net, kGraphSteps, &g))) return rc;
+        for (; n >= kGraphSteps; n -= kGraphSteps) {
+            HIP_OK(hipGraphLaunch(g, net->stream));
+            net->t += kGraphSteps;
+        }
     }
-    while (n >= kGraphSteps) {
-        HIP_OK(hipGraphLaunch(net->graph_exec, net->stream));
-        n -= kGraphSteps;
-        net->t += kGraphSteps;
-    }
-    for (; n > 0; --n) {
-        HIP_OK(enqueue_step(net, net->stream));
-        net->t += 1;
+    if (n > 0) {
+        if ((rc = graph_for(net, (int)n, &g))) return rc;
+        HIP_OK(hipGraphLaunch(g, net->stream));
+        net->t += n;
     }
     return SNN_OK;
 }
@@ -1579,10 +1614,7 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
             rc = rebuild_pending(net, -1, nullptr);
         if (rc) return rc;
     }
-    if (net->graph_exec) {
-        (void)hipGraphExecDestroy(net->graph_exec);
-        net->graph_exec = nullptr;
-    }
+    drop_graphs(net);
     return SNN_OK;
 }
 
@@ -1592,7 +1624,7 @@ int snn_time_steps(snn_net *net, int64_t n_steps, double *out_ms)
     if (rc) return rc;
     if (n_steps < 1 || !out_ms) return fail(SNN_EINVAL, "need n_steps >= 1 and an output");
     // capture the graph before the clock starts: host capture time is not step time
-    if (n_steps >= kGraphSteps && !net->graph_exec && (rc = build_graph(net))) return rc;
+    if ((rc = prepare_graphs(net, n_steps))) return rc;
     double ms = 0.0;
     rc = timed_on_snapshot(net, [&]() { return run_steps(net, n_steps); }, &ms);
     if (rc) return rc;

@@ -241,3 +241,39 @@ def test_layered_network_activity(orc):
     for p in (1, 2):
         hz = net.counts(p).mean() / 0.3
         assert 2.0 < hz < 100.0
+
+
+def test_threaded_neuron_phase_equals_serial(orc):
+    """The neuron loop on several OpenMP threads gives the serial run's bits:
+    voltages, gates, counts, V sums and the NaN count."""
+    spec = netgen.make_config(1, scale=0.5)
+    inst = spec["instances"][0]
+    inst["g_scale"] = 3.0
+    a, b = orc.OracleNet(inst), orc.OracleNet(inst)
+    b.set_threads(4)
+    a.step(400)
+    b.step(400)
+    for p in (1, 2):
+        for var in (orc.V, orc.M, orc.H, orc.N):
+            assert np.array_equal(a.get(p, var), b.get(p, var))
+        assert np.array_equal(a.vsum(p), b.vsum(p))
+    for p in range(3):
+        assert np.array_equal(a.counts(p), b.counts(p))
+    assert a.counts(1).sum() > 0
+    assert a.nan_count == b.nan_count
+
+
+def test_instances_on_threads_equal_serial(orc):
+    """Instances stepped concurrently on a thread pool end bit-identical to
+    the same instances stepped one after the other."""
+    spec = netgen.make_config(4, n_instances=4, scale=0.05)
+    ser = [orc.OracleNet(inst) for inst in spec["instances"]]
+    par = [orc.OracleNet(inst) for inst in spec["instances"]]
+    orc.step_many(ser, 200, threads=1)
+    orc.step_many(par, 200, threads=4)
+    for x, y in zip(ser, par):
+        for p in (1, 2):
+            assert np.array_equal(x.get(p, orc.V), y.get(p, orc.V))
+            assert np.array_equal(x.vsum(p), y.vsum(p))
+        for p in range(3):
+            assert np.array_equal(x.counts(p), y.counts(p))
