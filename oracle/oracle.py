@@ -18,7 +18,7 @@ SRC = [os.path.join(HERE, "snn_oracle.c"), os.path.join(HERE, "snn_adjoint.c")]
 DEPS = SRC + [os.path.join(HERE, "snn_oracle.h")]
 LIB = os.path.join(HERE, "liboracle.so")
 
-POISSON, HH = 0, 1
+POISSON, HH, IZH = 0, 1, 2
 V, M, H, N = 0, 1, 2, 3
 
 
@@ -73,6 +73,8 @@ def lib():
             "orc_set_last_spikes": (C.c_int, [vp, C.c_int, vp]),
             "orc_nan_count": (i64, [vp]),
             "orc_set_threads": (None, [vp, C.c_int]),
+            "orc_set_izh_params": (C.c_int, [vp, C.c_int, vp]),
+            "orc_izh_substep": (None, [d, d, d, d, vp, vp]),
             "orc_time": (i64, [vp]),
             "orc_set_g_scale": (None, [vp, d]),
             "orc_log_events": (None, [vp, C.c_int]),
@@ -177,7 +179,7 @@ class OracleNet:
         self.pops = inst["pops"]
         self._keep = []
         for k, p in enumerate(self.pops):
-            kind = POISSON if p["kind"] == "poisson" else HH
+            kind = {"poisson": POISSON, "hh": HH, "izh": IZH}[p["kind"]]
             hh = None
             if hh_params is not None and hh_params.get(k) is not None:
                 hh = np.asarray(hh_params[k], np.float64)
@@ -186,6 +188,12 @@ class OracleNet:
                               float(p.get("i_ext", 0.0)), _p(hh) if hh is not None else None)
             if r < 0:
                 raise ValueError("bad population")
+            if kind == IZH:
+                abcd = np.ascontiguousarray(p["abcd"], np.float32)
+                assert abcd.shape == (4, int(p["n"]))
+                self._keep.append(abcd)
+                if L.orc_set_izh_params(self.h, k, _p(abcd)) != 0:
+                    raise ValueError("bad Izhikevich parameters")
         for q in inst["projs"]:
             rp = np.ascontiguousarray(q["row_ptr"], np.int32)
             ci = np.ascontiguousarray(q["col_idx"], np.int32)

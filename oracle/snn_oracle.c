@@ -25,6 +25,11 @@
  *    infinite, the two quantities the calibration of Fig. 1 reads
  *    (avgSpike, sumNANs).
  *  - Optional pair-based STDP with all-to-all traces on chosen projections.
+ *  - Izhikevich neurons (Section 5.1's first network cites the model,
+ *    reference [9], without its equations; they are taken from Izhikevich,
+ *    "Simple model of spiking neurons", IEEE TNN 14, 2003): v' = 0.04 v^2 +
+ *    5 v + 140 - u + I, u' = a (b v - u), and at v >= 30 mV the reset
+ *    v <- c, u <- u + d, with a, b, c, d per neuron.
  *
  * Parity pins (tests that tie this code to mathematics rather than to
  * itself) live in tests/test_oracle_*.py.
@@ -87,6 +92,26 @@ void orc_substep(const double *p, double hs, double i_in, double *V, double *m, 
     *m = mm + hs * dm;
     *h = hh + hs * dh;
     *n = nn + hs * dn;
+}
+
+/* Whether x stays finite when held in single precision, the precision of
+ * the workloads' neuron state: |x| below FLT_MAX plus half its ulp, the
+ * values that round to a finite float (NaN does not). */
+static int fits_fp32(double x)
+{
+    return fabs(x) < 0x1.ffffffp127;
+}
+
+/* One forward-Euler substep of the Izhikevich model (v in mV, u in the
+ * same units, t in ms); both right-hand sides from the substep-start state,
+ * i_in the injected current (synaptic + external), held fixed. */
+void orc_izh_substep(double a, double b, double hs, double i_in, double *v, double *u)
+{
+    double vv = *v, uu = *u;
+    double dv = 0.04 * vv * vv + 5.0 * vv + 140.0 - uu + i_in;
+    double du = a * (b * vv - uu);
+    *v = vv + hs * dv;
+    *u = uu + hs * du;
 }
 
 /* Net membrane current with every gate at its steady state a/(a+b). */
@@ -178,7 +203,7 @@ orc_net *orc_create(double dt, int substeps, double g_scale, uint64_t seed)
 int orc_add_pop(orc_net *net, int kind, int n, double rate_hz, double i_ext, const double *hh)
 {
     if (net->ready || net->n_pops >= ORC_MAX_POPS || n < 0) return -1;
-    if (kind != ORC_POISSON && kind != ORC_HH) return -1;
+    if (kind != ORC_POISSON && kind != ORC_HH && kind != ORC_IZH) return -1;
     opop *P = &net->pops[net->n_pops];
     memset(P, 0, sizeof(*P));
     P->kind = kind;
@@ -196,7 +221,7 @@ int orc_add_proj(orc_net *net, int pre, int post, int64_t nnz, const int32_t *ro
 {
     if (net->ready || net->n_projs >= ORC_MAX_PROJS || nnz < 0 || nnz >= ((int64_t)1 << 31)) return -1;
     if (pre < 0 || pre >= net->n_pops || post < 0 || post >= net->n_pops) return -1;
-    if (net->pops[post].kind != ORC_HH || !(tau > 0.0)) return -1;
+    if (net->pops[post].kind == ORC_POISSON || !(tau > 0.0)) return -1;
     int npre = net->pops[pre].n, npost = net->pops[post].n;
     if (row_ptr[0] != 0 || row_ptr[npre] != nnz) return -1;
     for (int i = 0; i < npre; ++i) {
@@ -225,8 +250,25 @@ int orc_add_proj(orc_net *net, int pre, int post, int64_t nnz, const int32_t *ro
     return net->n_projs++;
 }
 
-/* Allocate state; every HH neuron starts at its resting point, G = 0,
- * traces = 0, no spikes at step -1. */
+/* Izhikevich parameters of population pop: abcd holds a[n], b[n], c[n],
+ * d[n] (parameter-major, fp32, widened exactly).  Before orc_init. */
+int orc_set_izh_params(orc_net *net, int pop, const float *abcd)
+{
+    if (net->ready || pop < 0 || pop >= net->n_pops || net->pops[pop].kind != ORC_IZH) return -1;
+    opop *P = &net->pops[pop];
+    size_t n = (size_t)(P->n > 0 ? P->n : 1);
+    double **dst[4] = {&P->iza, &P->izb, &P->izc, &P->izd};
+    for (int k = 0; k < 4; ++k) {
+        free(*dst[k]);
+        *dst[k] = (double *)calloc(n, sizeof(double));
+        for (int j = 0; j < P->n; ++j) (*dst[k])[j] = (double)abcd[(size_t)k * (size_t)P->n + (size_t)j];
+    }
+    return 0;
+}
+
+/* Allocate state; every HH neuron starts at its resting point, every
+ * Izhikevich neuron at v = -65 mV, u = b v; G = 0, traces = 0, no spikes at
+ * step -1. */
 int orc_init(orc_net *net)
 {
     for (int p = 0; p < net->n_pops; ++p) {
@@ -245,6 +287,16 @@ int orc_init(orc_net *net)
             P->vsum = (double *)calloc(n, sizeof(double));
             for (int j = 0; j < P->n; ++j) {
                 P->V[j] = v; P->m[j] = m; P->h[j] = h; P->nn[j] = nn;
+            }
+        }
+        if (P->kind == ORC_IZH) {
+            if (!P->iza) return -1;
+            P->V = (double *)malloc(n * sizeof(double));
+            P->m = (double *)malloc(n * sizeof(double));
+            P->vsum = (double *)calloc(n, sizeof(double));
+            for (int j = 0; j < P->n; ++j) {
+                P->V[j] = -65.0;
+                P->m[j] = P->izb[j] * -65.0;
             }
         }
     }
@@ -361,10 +413,39 @@ void orc_phase_neurons(orc_net *net)
                 orc_substep(P->hh, hs, isyn + P->i_ext, &v, &m, &h, &n);
             P->V[j] = v; P->m[j] = m; P->h[j] = h; P->nn[j] = n;
             P->spk_now[j] = (v0 < 0.0 && v >= 0.0) ? 1 : 0;
-            if (isfinite(v0) && !isfinite(v)) nan_new++;
+            /* Fig. 1's NaN count covers overflow: a neuron counts once, at
+             * the step its V leaves the range of the single-precision state */
+            if (fits_fp32(v0) && !fits_fp32(v)) nan_new++;
             P->vsum[j] += v;
         }
         net->nan_count += nan_new;
+    }
+    /* Izhikevich populations: synaptic current from the start-of-step v,
+     * Euler substeps on (v, u), then the threshold test on the step's end
+     * value: v >= 30 mV is a spike, and the neuron resets. */
+    for (int p = 0; p < net->n_pops; ++p) {
+        opop *P = &net->pops[p];
+        if (P->kind != ORC_IZH) continue;
+        for (int j = 0; j < P->n; ++j) {
+            double v0 = P->V[j];
+            double isyn = 0.0;
+            for (int q = 0; q < net->n_projs; ++q)
+                if (net->projs[q].post == p)
+                    isyn += net->projs[q].G[j] * (net->projs[q].e_rev - v0);
+            double v = v0, u = P->m[j];
+            for (int k = 0; k < net->substeps; ++k)
+                orc_izh_substep(P->iza[j], P->izb[j], hs, isyn + P->i_ext, &v, &u);
+            int fired = v >= 30.0;
+            if (fits_fp32(v0) && !fits_fp32(v)) net->nan_count++;
+            if (fired) {
+                v = P->izc[j];
+                u = u + P->izd[j];
+            }
+            P->V[j] = v;
+            P->m[j] = u;
+            P->spk_now[j] = (unsigned char)fired;
+            P->vsum[j] += v;
+        }
     }
     for (int q = 0; q < net->n_projs; ++q) {
         oproj *Q = &net->projs[q];
@@ -439,7 +520,7 @@ int orc_step(orc_net *net, int64_t n_steps)
  * out[k * n_pop + j] (a voltage trace for parity checks). */
 int orc_step_trace(orc_net *net, int64_t n_steps, int pop, double *out)
 {
-    if (!net->ready || pop < 0 || pop >= net->n_pops || net->pops[pop].kind != ORC_HH) return -1;
+    if (!net->ready || pop < 0 || pop >= net->n_pops || net->pops[pop].kind == ORC_POISSON) return -1;
     int n = net->pops[pop].n;
     for (int64_t k = 0; k < n_steps; ++k) {
         orc_step1(net);
@@ -453,8 +534,9 @@ enum { ORC_V = 0, ORC_M, ORC_H, ORC_N };
 
 static double *var_ptr(orc_net *net, int pop, int var)
 {
-    if (pop < 0 || pop >= net->n_pops || net->pops[pop].kind != ORC_HH) return NULL;
+    if (pop < 0 || pop >= net->n_pops || net->pops[pop].kind == ORC_POISSON) return NULL;
     opop *P = &net->pops[pop];
+    if (P->kind == ORC_IZH && var != ORC_V && var != ORC_M) return NULL;
     switch (var) {
     case ORC_V: return P->V;
     case ORC_M: return P->m;
@@ -519,7 +601,7 @@ int orc_get_counts(orc_net *net, int pop, int32_t *out)
 
 int orc_get_vsum(orc_net *net, int pop, double *out)
 {
-    if (pop < 0 || pop >= net->n_pops || net->pops[pop].kind != ORC_HH) return -1;
+    if (pop < 0 || pop >= net->n_pops || net->pops[pop].kind == ORC_POISSON) return -1;
     memcpy(out, net->pops[pop].vsum, sizeof(double) * (size_t)net->pops[pop].n);
     return 0;
 }
@@ -578,6 +660,7 @@ void orc_destroy(orc_net *net)
         opop *P = &net->pops[p];
         free(P->V); free(P->m); free(P->h); free(P->nn);
         free(P->spk_prev); free(P->spk_now); free(P->count); free(P->vsum);
+        free(P->iza); free(P->izb); free(P->izc); free(P->izd);
     }
     for (int q = 0; q < net->n_projs; ++q) {
         oproj *Q = &net->projs[q];

@@ -8,7 +8,7 @@
 
 #include <stdint.h>
 
-enum { ORC_POISSON = 0, ORC_HH = 1 };
+enum { ORC_POISSON = 0, ORC_HH = 1, ORC_IZH = 2 };
 enum { HH_GNA = 0, HH_ENA, HH_GK, HH_EK, HH_GL, HH_EL, HH_CM, HH_NPARAM };
 
 /* ------------------------------------------------------------------ */
@@ -21,7 +21,8 @@ typedef struct {
     int kind, n;
     double rate_hz, i_ext, hh[HH_NPARAM];
     uint64_t thresh;
-    double *V, *m, *h, *nn;      /* HH state */
+    double *V, *m, *h, *nn;      /* HH state; Izhikevich: v in V, u in m */
+    double *iza, *izb, *izc, *izd;  /* Izhikevich parameters per neuron (fp32 input widened) */
     unsigned char *spk_prev;     /* spikes of the previous step */
     unsigned char *spk_now;      /* spikes of the current step */
     int32_t *count;              /* spikes per neuron since init */
@@ -73,6 +74,7 @@ double orc_beta_h(double V);
 double orc_alpha_n(double V);
 double orc_beta_n(double V);
 void orc_substep(const double *p, double hs, double i_in, double *V, double *m, double *h, double *n);
+void orc_izh_substep(double a, double b, double hs, double i_in, double *v, double *u);
 void orc_phase_deliver(orc_net *net);
 void orc_phase_potentiate(orc_net *net);
 void orc_phase_neurons(orc_net *net);

@@ -18,7 +18,8 @@ A network spec is a plain dict::
 
     {"dt": 0.1, "substeps": 3,
      "instances": [{"g_scale": s, "seed": k,
-                    "pops":  [{"name", "kind": "poisson"|"hh", "n", "rate_hz", "i_ext"}],
+                    "pops":  [{"name", "kind": "poisson"|"hh"|"izh", "n", "rate_hz", "i_ext",
+                               "abcd" (izh only: float32[4, n] rows a, b, c, d)}],
                     "projs": [{"pre", "post", "row_ptr" int32[n_pre+1],
                                "col_idx" int32[nnz], "g" float32[nnz],
                                "e_rev", "tau", "stdp": None | {...}}]}]}
@@ -251,6 +252,81 @@ def mushroom_body_calibration_config(n_pn_values, scales, *, swept="kc", n_lhi=2
             inst["g_scale_swept"] = float(s)
             spec["instances"].append(inst)
             spec["n_conn"].append(float(p * n_pn))
+            spec["grid"].append((i, j))
+    return spec
+
+
+# The 4:1 excitatory/inhibitory Izhikevich network of Section 5.1 (the
+# paper's first scalability network; its neuron model is reference [9]).
+# The paper gives the size (1000 neurons, E:I = 4:1) and the swept number of
+# connections per neuron (nConn = 100 .. 1000), nothing else; the rest is
+# this module's reading: per-neuron a, b, c, d drawn as in Izhikevich (2003)
+# (excitatory: a 0.02, b 0.2, c -65 + 15 r^2, d 8 - 6 r^2; inhibitory:
+# a 0.02 + 0.08 r, b 0.25 - 0.05 r, c -65, d 2; r ~ U[0,1) per neuron),
+# rounded to fp32; the random thalamic input of that reference replaced by
+# Poisson sources with conductance synapses (as the other workloads' inputs);
+# recurrent connections Bernoulli(nConn / n) per (pre, post) pair without
+# self-connections, conductance synapses onto v with reversal 0 mV
+# (excitatory) or -80 mV (inhibitory), 5 ms decay.
+IZH_G_IN = 0.01      # input -> E/I: g = U[0,1) * IZH_G_IN (uS)
+IZH_G_E = 0.005      # E -> E/I:     g = U[0,1) * IZH_G_E * gScale
+IZH_G_I = 0.0025     # I -> E/I:     g = U[0,1) * IZH_G_I * gScale
+IZH_E_INH = -80.0
+IZH_TAU = 5.0
+
+
+def izhikevich_params(rng, n_exc, n_inh):
+    """float32[4, n_exc + n_inh] rows a, b, c, d (excitatory neurons first)."""
+    re, ri = rng.random(n_exc), rng.random(n_inh)
+    a = np.concatenate([np.full(n_exc, 0.02), 0.02 + 0.08 * ri])
+    b = np.concatenate([np.full(n_exc, 0.2), 0.25 - 0.05 * ri])
+    c = np.concatenate([-65.0 + 15.0 * re * re, np.full(n_inh, -65.0)])
+    d = np.concatenate([8.0 - 6.0 * re * re, np.full(n_inh, 2.0)])
+    return np.stack([a, b, c, d]).astype(np.float32)
+
+
+def izhikevich_instance(n_conn, *, n_exc=800, n_inh=200, n_in=1000, p_in=0.1, rate_hz=20.0, g_scale=1.0,
+                        seed=0, conn_seed=0):
+    """One 4:1 E/I Izhikevich network: populations IN (Poisson), E, I; the
+    recurrent projections E->E, E->I, I->E, I->I with p = nConn / (n_exc +
+    n_inh) and weights scaled by g_scale (built into the fp32 weights: the
+    instance g_scale stays 1, so the input projections are not scaled)."""
+    rng = np.random.default_rng(conn_seed)
+    n = n_exc + n_inh
+    abcd = izhikevich_params(rng, n_exc, n_inh)
+    pops = [dict(name="IN", kind="poisson", n=int(n_in), rate_hz=float(rate_hz), i_ext=0.0),
+            dict(name="E", kind="izh", n=int(n_exc), rate_hz=0.0, i_ext=0.0, abcd=abcd[:, :n_exc].copy()),
+            dict(name="I", kind="izh", n=int(n_inh), rate_hz=0.0, i_ext=0.0, abcd=abcd[:, n_exc:].copy())]
+    p = min(1.0, float(n_conn) / n)
+    projs = []
+
+    def add(pre, post, n_pre, n_post, pp, scale, e_rev, no_self=False):
+        rp, ci = bernoulli_csr(rng, n_pre, n_post, pp, no_self=no_self)
+        g = uniform_weights(rng, ci.size, scale)
+        projs.append(dict(pre=pre, post=post, row_ptr=rp, col_idx=ci, g=g, e_rev=e_rev, tau=IZH_TAU, stdp=None))
+
+    add(0, 1, n_in, n_exc, p_in, IZH_G_IN, E_EXC)
+    add(0, 2, n_in, n_inh, p_in, IZH_G_IN, E_EXC)
+    add(1, 1, n_exc, n_exc, p, IZH_G_E * g_scale, E_EXC, no_self=True)
+    add(1, 2, n_exc, n_inh, p, IZH_G_E * g_scale, E_EXC)
+    add(2, 1, n_inh, n_exc, p, IZH_G_I * g_scale, IZH_E_INH)
+    add(2, 2, n_inh, n_inh, p, IZH_G_I * g_scale, IZH_E_INH, no_self=True)
+    return dict(g_scale=1.0, seed=int(seed), pops=pops, projs=projs, g_scale_swept=float(g_scale))
+
+
+def izhikevich_calibration_config(n_conn_values, g_scales, *, n_exc=800, n_inh=200, steps=5000, key=8000):
+    """Calibration sweep of the 4:1 Izhikevich network (Section 5.1, Fig. 1
+    and Table 1): one run per (nConn, gScale) pair; the runs of one nConn
+    share the network's neurons, connectivity pattern and Poisson stream, and
+    differ in the recurrent weights' scale only.  The criterion population is
+    E (avgSpike of the excitatory neurons)."""
+    spec = dict(dt=0.1, substeps=3, instances=[], steps=int(steps), n_conn=[], grid=[], pop=1)
+    for i, x in enumerate(n_conn_values):
+        for j, g in enumerate(g_scales):
+            inst = izhikevich_instance(float(x), n_exc=n_exc, n_inh=n_inh, g_scale=float(g),
+                                       seed=instance_seed(key + 2, i), conn_seed=key + 1 + i)
+            spec["instances"].append(inst)
+            spec["n_conn"].append(float(x))
             spec["grid"].append((i, j))
     return spec
 

@@ -86,3 +86,107 @@ def test_parameters_of_the_4_to_1_population():
     assert a[1] == pytest.approx(0.1) and b[1] == pytest.approx(0.2)
     v, u = iz.initial_state(b)
     assert np.all(v == -65.0) and np.allclose(u, b * -65.0)
+
+
+# ---------------------------------------------------------------------------
+# The network oracle's Izhikevich populations (oracle/snn_oracle.c), tied to
+# the single-neuron reference above (itself pinned to the model's closed
+# forms) and to the model's fixed point and reset.
+# ---------------------------------------------------------------------------
+from oracle import oracle as O  # noqa: E402
+from paper_1412_0595_amd import netgen  # noqa: E402
+
+
+def _izh_net(abcd, i_ext=0.0, dt=0.1, substeps=1, projs=(), extra_pops=()):
+    n = abcd.shape[1]
+    pops = [dict(name="X", kind="izh", n=n, rate_hz=0.0, i_ext=i_ext, abcd=abcd)] + list(extra_pops)
+    inst = dict(g_scale=1.0, seed=3, pops=pops, projs=list(projs))
+    return O.OracleNet(inst, dt=dt, substeps=substeps)
+
+
+def test_network_oracle_equals_single_neuron_reference():
+    """No synapses, constant input, one substep per step: the network
+    oracle's trajectory and spike counts equal the reference step function's
+    bit for bit, across regular- and fast-spiking parameters and inputs
+    below and above rheobase."""
+    rng = np.random.default_rng(11)
+    abcd = netgen.izhikevich_params(rng, 6, 4)
+    a, b, c, d = (abcd[k].astype(np.float64) for k in range(4))
+    for i_in in (0.0, 3.0, 6.0, 15.0):
+        net = _izh_net(abcd, i_ext=i_in)
+        v, u = iz.initial_state(b)
+        counts = np.zeros(10, np.int64)
+        for _ in range(3000):
+            v, u, s = iz.step(v, u, i_in, a, b, c, d, 0.1)
+            counts += s
+        net.step(3000)
+        assert np.array_equal(net.get(0, O.V), v)
+        assert np.array_equal(net.get(0, O.M), u)
+        assert np.array_equal(net.counts(0), counts)
+        if i_in >= 6.0:
+            assert counts.min() > 0
+
+
+def test_network_oracle_substeps_are_reference_steps_between_tests():
+    """k substeps of h/k make k reference steps of h/k when no spike occurs
+    (the threshold is tested once, at the step's end)."""
+    rng = np.random.default_rng(12)
+    abcd = netgen.izhikevich_params(rng, 5, 5)
+    a, b, c, d = (abcd[k].astype(np.float64) for k in range(4))
+    net = _izh_net(abcd, i_ext=0.5, dt=0.3, substeps=3)
+    v, u = iz.initial_state(b)
+    hs = 0.3 / 3
+    for _ in range(4000):
+        for _ in range(3):
+            v, u, s = iz.step(v, u, 0.5, a, b, c, d, hs)
+            assert not s.any()
+    net.step(4000)
+    assert np.array_equal(net.get(0, O.V), v) and np.array_equal(net.get(0, O.M), u)
+    assert net.counts(0).sum() == 0
+
+
+def test_network_oracle_rest_and_reset():
+    """A regular-spiking neuron placed on its lower fixed point (b as stored
+    in fp32) stays there; a step ending above 30 mV resets v to c exactly and
+    adds d to the Euler-stepped u."""
+    abcd = np.array([[0.02], [0.2], [-55.0], [4.0]], np.float32)
+    b = float(abcd[1, 0])
+    vr = (-(5.0 - b) - math.sqrt((5.0 - b) ** 2 - 0.16 * 140.0)) / 0.08
+    net = _izh_net(abcd)
+    net.set(0, O.V, [vr])
+    net.set(0, O.M, [b * vr])
+    net.step(10000)
+    assert abs(net.get(0, O.V)[0] - vr) < 1e-9 and net.counts(0)[0] == 0
+    net = _izh_net(abcd, i_ext=100.0)
+    net.set(0, O.V, [29.0])
+    net.set(0, O.M, [-10.0])
+    net.step(1)
+    assert net.counts(0)[0] == 1 and net.last_spikes(0)[0] == 1
+    assert net.get(0, O.V)[0] == -55.0
+    assert net.get(0, O.M)[0] == -10.0 + 0.1 * (float(abcd[0, 0]) * (b * 29.0 + 10.0)) + 4.0
+
+
+def test_network_oracle_synaptic_current_sign_and_delay():
+    """A Poisson source that fires at every step (rate * dt >= 1) with one
+    synapse of weight w onto the neuron: no current at step 0, then at
+    step 1 the current w (E_rev - v0) from the start-of-step v; an
+    inhibitory reversal below v slows the upstroke, an excitatory one
+    speeds it."""
+    abcd = np.array([[0.02], [0.2], [-65.0], [8.0]], np.float32)
+    w = np.float32(0.25)
+    src = dict(name="S", kind="poisson", n=1, rate_hz=1e5, i_ext=0.0)
+    outs = {}
+    for e_rev in (0.0, -80.0):
+        proj = dict(pre=1, post=0, row_ptr=np.array([0, 1], np.int32), col_idx=np.array([0], np.int32),
+                    g=np.array([w], np.float32), e_rev=e_rev, tau=5.0, stdp=None)
+        net = _izh_net(abcd, projs=[proj], extra_pops=[src])
+        v0, u0 = net.get(0, O.V)[0], net.get(0, O.M)[0]
+        net.step(1)
+        v1, u1 = net.get(0, O.V)[0], net.get(0, O.M)[0]
+        assert v1 == v0 + 0.1 * (0.04 * v0 * v0 + 5.0 * v0 + 140.0 - u0)
+        net.step(1)
+        v2 = net.get(0, O.V)[0]
+        i_syn = float(w) * (e_rev - v1)
+        assert v2 == v1 + 0.1 * (0.04 * v1 * v1 + 5.0 * v1 + 140.0 - u1 + i_syn)
+        outs[e_rev] = v2
+    assert outs[0.0] > outs[-80.0]

@@ -214,20 +214,49 @@ def test_upward_crossing_detection(orc):
 
 
 def test_nan_counted_once_per_neuron(orc):
-    """Instability (h G / C > 2) drives V non-finite; each neuron counts once."""
+    """A voltage far outside the physiological range runs away to a
+    non-finite value; each neuron counts once, at the step its V leaves the
+    range of single precision (the workloads' state precision), so a V that
+    starts beyond it (1e200) is never counted and one that starts inside it
+    (1e30) is counted exactly once however long it stays non-finite."""
     inst, hp = _single()
-    inst["pops"][0]["n"] = 3
+    inst["pops"][0]["n"] = 4
     net = orc.OracleNet(inst)
-    net.set(0, orc.V, [1e200, -63.0, 1e200])
-    net.step(50)
+    net.set(0, orc.V, [1e30, -63.0, 1e30, 1e200])
+    net.step(1)
+    assert net.nan_count == 2
+    net.step(49)
     assert net.nan_count == 2
     V = net.get(0, orc.V)
-    assert not np.isfinite(V[0]) and np.isfinite(V[1]) and not np.isfinite(V[2])
+    assert not np.isfinite(V[0]) and np.isfinite(V[1]) and not np.isfinite(V[2]) and not np.isfinite(V[3])
 
 
-def test_kinetics_hand_derived_values(orc):
-    """Rates where their exponent is exactly +-1 (fixing the slope divisors),
-    the ionic current at gate values that separate m^3 h and n^4 from their
-    neighbouring powers, and the resting point of the unstimulated neuron."""
-    import tm_pins
-    assert tm_pins.violations(orc.lib(), orc.default_hh()) == []
+def nan_edge_instance(orc):
+    """Two leak-only neurons (g_Na = g_K = 0, g_L = 1 uS, E_L = -64 mV, C = 1
+    nF) at V = E_L, one substep of 0.125 ms: V(1) = -64 + I/8 exactly rounded.
+    Population 0 gets I = 8 x (2^128 - 2^103), the single-precision range's
+    edge (FLT_MAX plus half an ulp, which rounds to infinity); population 1
+    gets 8 x the double just below it (which rounds to FLT_MAX)."""
+    edge = 2.0 ** 128 - 2.0 ** 103
+    below = float(np.nextafter(edge, 0.0))
+    hh = orc.default_hh()
+    hh[0] = hh[2] = 0.0
+    hh[4], hh[5], hh[6] = 1.0, -64.0, 1.0
+    pops = [dict(name="X", kind="hh", n=1, rate_hz=0.0, i_ext=8.0 * edge),
+            dict(name="Y", kind="hh", n=1, rate_hz=0.0, i_ext=8.0 * below)]
+    return dict(g_scale=1.0, seed=1, pops=pops, projs=[]), {0: hh, 1: hh}, edge, below
+
+
+def test_nan_count_edge_is_the_single_precision_range(orc):
+    """A V landing exactly on FLT_MAX + half an ulp counts as a NaN/overflow;
+    one landing on the double just below it does not, and is still finite
+    in single precision."""
+    inst, hp, edge, below = nan_edge_instance(orc)
+    with np.errstate(over="ignore"):
+        assert np.isinf(np.float32(edge)) and np.float32(below) == np.finfo(np.float32).max
+    net = orc.OracleNet(inst, dt=0.125, substeps=1, hh_params=hp)
+    for p in (0, 1):
+        net.set(p, orc.V, [-64.0])
+    net.step(1)
+    assert net.get(0, orc.V)[0] == edge and net.get(1, orc.V)[0] == below
+    assert net.nan_count == 1
