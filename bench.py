@@ -47,6 +47,9 @@ NEURON_ALG_STATE_BYTES = 32
 NEURON_ALG_VLO_BYTES = 8
 NEURON_ALG_G_BYTES = 8
 NEURON_VALU_PER_STEP = 500
+#  - Izhikevich neuron-step: v and u in fp32 read and written (16 B), its
+#    a, b, c, d read (16 B), and 8 B per incoming projection
+NEURON_ALG_IZH_BYTES = 32
 POT_BYTES_PER_ENTRY = 20
 # What this library stores per unit (double-float state, 64-bit conductances,
 # 16 B per spiking row including its work item): bytes a launch moves beyond
@@ -178,13 +181,18 @@ def adjoint_bench(args):
     (fb, bb), n_hh = run(spec, y, w)
     loop_f = loop_b = 0.0
     off = 0
-    for k, n in enumerate(sizes):
+    if args.loop == 0:
+        sizes_loop = []          # batched pass only (profiling runs)
+    else:
+        sizes_loop = sizes
+    for k, n in enumerate(sizes_loop):
         (f, b), _ = run(sub_spec(spec, k), y[off:off + n], w[off:off + n], reps=1)
         loop_f += f
         loop_b += b
         off += n
     rec = {"metric": "adjoint (recorded forward + reverse) time, batched vs plain per-instance loop",
-           "value": (loop_f + loop_b) / (fb + bb), "unit": "x speedup", "higher_is_better": True,
+           "value": (loop_f + loop_b) / (fb + bb) if sizes_loop else None, "unit": "x speedup",
+           "higher_is_better": True,
            "n_gpus": 1, "steps": T, "ckpt_every": K, "dtype": "f64", "data": "synthetic",
            "config": {"workload": WORKLOADS.get(args.workload), "instances": len(sizes), "hh_neurons": n_hh},
            "batched_ms": {"forward_record": fb, "backward": bb},
@@ -297,7 +305,11 @@ def calibrate_bench(args):
     layered: nConn = 100..1000 (step 50) x 25 gScale in [0.1, 10], A = nConn /
     0.2 Poisson inputs at 20 Hz, B = 1000, C = 100.
     lhi: the LHI variant, PN = 100..1000 (step 50) x 25 scales, KC = 1000,
-    DN = 100, with 20 and 40 LHI, the PN->KC and the PN->LHI scale each swept."""
+    DN = 100, with 20 and 40 LHI, the PN->KC and the PN->LHI scale each swept.
+    izh: the 4:1 Izhikevich network of Section 5.1 (800 excitatory, 200
+    inhibitory neurons, 1000 Poisson inputs at 20 Hz), nConn = 100..1000
+    (step 50) recurrent connections per neuron x 25 scales of the recurrent
+    weights in [0.03, 10], criterion the excitatory avgSpike."""
     import numpy as np
     import torch
     from paper_1412_0595_amd import calibrate as cal
@@ -309,6 +321,12 @@ def calibrate_bench(args):
                                              ref_n_conn=100.0, steps=args.steps))]
         workload = ("calibration sweep: nConn 100..1000 step 50 x 25 gScale in [0.1, 10]; "
                     "A = nConn/0.2 Poisson at 20 Hz, B = 1000 HH, C = 100 HH, p = 0.2/0.5")
+    elif args.model == "izh":
+        gi = 10.0 ** np.linspace(np.log10(0.03), 1.0, 25)
+        sweeps = [("Izhikevich 4:1 network: recurrent scale, E spiking",
+                   netgen.izhikevich_calibration_config(np.arange(100.0, 1001.0, 50.0), gi, steps=args.steps))]
+        workload = ("Izhikevich calibration sweep (Section 5.1): nConn 100..1000 step 50 x 25 recurrent scales in "
+                    "[0.03, 10]; 800 E + 200 I Izhikevich neurons, 1000 Poisson inputs at 20 Hz (p 0.1)")
     else:
         n_pn = np.arange(100, 1001, 50)
         sweeps = [(f"LHI variant, {nl} LHI: PN->{sw.upper()} scale, {sw.upper()} spiking",
@@ -322,6 +340,7 @@ def calibrate_bench(args):
     for label, spec in sweeps:
         ref = cal.reference_run(spec, spec["n_conn"][0], 1.0)
         n_hh = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] == "hh")
+        n_state = sum(p["n"] for inst in spec["instances"] for p in inst["pops"] if p["kind"] != "poisson")
         n_syn = sum(int(np.asarray(q["col_idx"]).size) for inst in spec["instances"] for q in inst["projs"])
         t_make = time.perf_counter()
         net = snn.Network(spec, autotune=bool(args.autotune), tune_cache=args.tune_cache)
@@ -343,9 +362,9 @@ def calibrate_bench(args):
                                  "calibration_sweep" if args.model == "layered" else None)
             launch = net.launch
         net.close()
-        total_ns += n_hh * args.steps
+        total_ns += n_state * args.steps
         total_ms += ms
-        out.append({"sweep": label, "runs": len(spec["instances"]), "hh_neurons": n_hh, "synapses": n_syn,
+        out.append({"sweep": label, "runs": len(spec["instances"]), "neurons": n_state, "synapses": n_syn,
                     "sweep_ms": ms, "ms_per_step": ms / args.steps, "create_s": t_make,
                     "table_select_fit_ms": t_fit * 1e3,
                     "reference": {"n_conn": spec["n_conn"][0], "g_scale": 1.0,
@@ -364,7 +383,7 @@ def calibrate_bench(args):
         mid = len(spec["instances"]) // 2
         inst = spec["instances"][mid]
         orc = oracle.OracleNet(inst)
-        nh = sum(p["n"] for p in inst["pops"] if p["kind"] == "hh")
+        nh = sum(p["n"] for p in inst["pops"] if p["kind"] != "poisson")
         t0, steps = time.perf_counter(), 0
         while time.perf_counter() - t0 < args.cpu_seconds:
             orc.step(50)
@@ -402,8 +421,9 @@ def parse():
     ap.add_argument("--ckpt-every", type=int, default=100)
     ap.add_argument("--calibrate", action="store_true",
                     help="the calibration of Fig. 1: (nConn, gScale) sweep, selection and law fit")
-    ap.add_argument("--model", choices=("layered", "lhi"), default="layered",
-                    help="calibration network: the layered model, or its LHI variant (two swept scales)")
+    ap.add_argument("--model", choices=("layered", "lhi", "izh"), default="layered",
+                    help="calibration network: the layered model, its LHI variant (two swept scales), or the "
+                         "4:1 Izhikevich network")
     ap.add_argument("--sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration)")
@@ -570,10 +590,11 @@ def neuron_alg_bytes(spec):
     tot = 0
     for inst in spec["instances"]:
         for k, p in enumerate(inst["pops"]):
-            if p["kind"] != "hh":
+            if p["kind"] == "poisson":
                 continue
             n_in = sum(1 for q in inst["projs"] if q["post"] == k)
-            tot += p["n"] * (NEURON_ALG_STATE_BYTES + NEURON_ALG_VLO_BYTES + NEURON_ALG_G_BYTES * n_in)
+            own = (NEURON_ALG_STATE_BYTES + NEURON_ALG_VLO_BYTES) if p["kind"] == "hh" else NEURON_ALG_IZH_BYTES
+            tot += p["n"] * (own + NEURON_ALG_G_BYTES * n_in)
     return tot
 
 

@@ -2,7 +2,8 @@
  * snn.h - C ABI of the MI355X spiking-network timestep library (libsnn.so).
  *
  * The library advances networks of Hodgkin-Huxley neurons (Traub-Miles
- * kinetics) and Poisson input sources, coupled by conductance synapses kept
+ * kinetics), Izhikevich neurons and Poisson input sources, coupled by
+ * conductance synapses kept
  * in Compressed Row Storage, one discrete time step at a time.  This is the
  * per-timestep update that the paper (Balaji, Yavuz, Nowotny, "Scalability
  * and Optimization Strategies for GPU Enhanced Neural Networks") runs inside
@@ -44,30 +45,42 @@ enum snn_status {
     SNN_ERANGE = -5   /* value outside the representable range */
 };
 
-enum snn_pop_kind { SNN_POISSON = 0, SNN_TRAUB_MILES = 1 };
+enum snn_pop_kind { SNN_POISSON = 0, SNN_TRAUB_MILES = 1, SNN_IZHIKEVICH = 2 };
 
-/* State variables of a Traub-Miles population. */
-enum snn_var { SNN_V = 0, SNN_M = 1, SNN_H = 2, SNN_N = 3 };
+/* State variables: V, m, h, n of a Traub-Miles population; V and the
+ * recovery variable u (SNN_U) of an Izhikevich population. */
+enum snn_var { SNN_V = 0, SNN_M = 1, SNN_H = 2, SNN_N = 3, SNN_U = 1 };
 
 /* Neuron parameters, in this order: g_Na (uS), E_Na (mV), g_K (uS),
  * E_K (mV), g_leak (uS), E_leak (mV), C_m (nF). */
 enum { SNN_HH_NPARAM = 7 };
 
-/* A population (Section 5.1 "populations of neurons at different stages").
+/* A population (Section 5.1: networks are built of populations of neurons).
  *  kind      SNN_POISSON: source i fires at step t iff the first output word
  *            of Philox-4x32-10 (Salmon et al., SC'11) with counter
  *            (i, t mod 2^32, t div 2^32, 0) and key (seed mod 2^32,
  *            seed div 2^32) is below floor(p * 2^32), p = rate_hz * dt_ms *
  *            1e-3 evaluated left to right in double precision (p >= 1:
  *            always fires).
- *            SNN_TRAUB_MILES: Hodgkin-Huxley neuron, Traub-Miles rates.
+ *            SNN_TRAUB_MILES: Hodgkin-Huxley neuron, Traub-Miles rates
+ *            (the neuron model of Section 2).
+ *            SNN_IZHIKEVICH: the neuron of the 4:1 excitatory/inhibitory
+ *            network of Section 5.1, the model of its reference [9]
+ *            (Izhikevich, IEEE TNN 14, 2003): v' = 0.04 v^2 + 5 v + 140 -
+ *            u + I and u' = a (b v - u), both right-hand sides from the
+ *            substep-start state in each Euler substep; after the step's
+ *            substeps, v >= 30 mV is a spike and resets v <- c, u <- u + d.
+ *            I (synaptic + i_ext_nA) enters v' as is.  Starts at v = -65 mV,
+ *            u = b v.
  *  n         number of neurons (>= 0).
- *  rate_hz   Poisson rate (finite, >= 0); ignored for HH.
- *  i_ext_nA  constant injected current of every HH neuron.
+ *  rate_hz   Poisson rate (finite, >= 0); ignored otherwise.
+ *  i_ext_nA  constant injected current of every HH or Izhikevich neuron.
  *  hh        neuron parameters (see above); snn_default_hh() fills the
- *            Traub-Miles values.  C_m must be > 0.
+ *            Traub-Miles values.  C_m must be > 0.  Traub-Miles only.
  *  record_vbar  1: accumulate every neuron's post-step V in double
- *            precision (read with snn_get_vbar). */
+ *            precision (read with snn_get_vbar).
+ *  izh_abcd  Izhikevich only: host float[4 * n], parameter-major (a[0..n),
+ *            then b, c, d), all finite; copied at create.  NULL otherwise. */
 typedef struct {
     int32_t kind;
     int32_t n;
@@ -75,6 +88,7 @@ typedef struct {
     double i_ext_nA;
     double hh[SNN_HH_NPARAM];
     int32_t record_vbar;
+    const float *izh_abcd;
 } snn_pop_desc;
 
 /* A projection in Compressed Row Storage (Section 3): row_ptr holds the
@@ -84,7 +98,8 @@ typedef struct {
  * >= 0).  A spike of pre neuron i at step t - 1 adds g_scale * g[k] to the
  * conductance G[col_idx[k]] of the post population for every k in row i at
  * step t; G enters the post neuron as G (e_rev_mV - V) and decays by
- * exp(-dt / tau_ms) per step.  The post population must be Traub-Miles.
+ * exp(-dt / tau_ms) per step.  The post population must be Traub-Miles or
+ * Izhikevich.
  *
  * stdp = 1 makes the weights plastic with pair-based, all-to-all traces
  * (trace time constant tau_stdp_ms): on a pre spike, every synapse of its
@@ -171,7 +186,8 @@ void snn_default_hh(double *p);
 
 /* Validate the description, copy every host array to the device and set
  * every Traub-Miles neuron to its resting point (the root of the
- * steady-state membrane current in [-80, -60] mV), conductances and traces
+ * steady-state membrane current in [-80, -60] mV), every Izhikevich neuron
+ * to v = -65 mV, u = b v, conductances and traces
  * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL.
  * Device memory beyond the state: the CRS arrays (8 B per synapse plus row
  * starts); for every non-plastic projection a column-ordered copy used by
@@ -185,8 +201,10 @@ int snn_create(const snn_config *cfg, snn_net **out);
 /* Release every device buffer.  NULL is ignored. */
 void snn_destroy(snn_net *net);
 
-/* Enqueue n_steps timesteps on the net's stream and return (asynchronous).
- * Each step t: (1) deliver the spikes of step t-1 through every projection
+/* Enqueue n_steps timesteps on the net's stream and return (asynchronous):
+ * the per-timestep update of Section 2 (Hodgkin-Huxley neurons integrated
+ * at discrete time steps) with spike propagation through the CRS arrays of
+ * Section 3.  Each step t: (1) deliver the spikes of step t-1 through every projection
  * (and depress plastic rows), (2) potentiate plastic columns of post neurons
  * that spiked at t-1, (3) update every neuron: synaptic current from the
  * start-of-step V, `substeps` Euler substeps, conductance decay, spike iff
@@ -200,10 +218,12 @@ int snn_sync(snn_net *net);
 int64_t snn_time(const snn_net *net);
 
 /* Spike count of every neuron of population pop of instance inst since
- * create (host int32[n]).  Synchronises. */
+ * create (host int32[n]): the per-neuron counts that the avgSpike of Fig. 1
+ * averages (Section 5.1).  Synchronises. */
 int snn_get_spikes(snn_net *net, int32_t inst, int32_t pop, int32_t *counts);
 
-/* Raster of population pop of instance inst for steps [t0, t1), which must
+/* Spike raster (the spike times of the discrete-time simulation of
+ * Section 2) of population pop of instance inst for steps [t0, t1), which must
  * lie within the last raster_steps steps, or, after snn_forward_record and
  * until the next reset, within the recorded steps.  offsets (host int64[t1-t0+1])
  * receives the start of each step's ids in `ids` (host int32[cap]),
@@ -212,8 +232,10 @@ int snn_get_spikes(snn_net *net, int32_t inst, int32_t pop, int32_t *counts);
 int snn_get_raster(snn_net *net, int32_t inst, int32_t pop, int64_t t0, int64_t t1,
                    int64_t *offsets, int32_t *ids, int64_t cap);
 
-/* Read / write one state variable (enum snn_var) of a Traub-Miles
- * population as float (host float[n]); the read returns the rounded value
+/* Read / write one state variable (enum snn_var; the neuron state that the
+ * Hodgkin-Huxley integration of Section 2 advances) of a Traub-Miles or
+ * Izhikevich population (SNN_V or SNN_U for the latter; SNN_EINVAL for a
+ * Poisson population) as float (host float[n]); the read returns the rounded value
  * of the stored double-float pair, the write sets the pair to the value
  * exactly.  Synchronise. */
 int snn_get_state(snn_net *net, int32_t inst, int32_t pop, int32_t var, float *out);
@@ -241,8 +263,11 @@ int snn_set_last_spikes(snn_net *net, int32_t inst, int32_t pop, const uint8_t *
  * for a population created with record_vbar = 1.  Synchronises. */
 int snn_get_vbar(snn_net *net, int32_t inst, int32_t pop, double *out);
 
-/* Per instance, how many Traub-Miles neurons had a finite V at the start of
- * a step and a non-finite V at its end (host int32[n_instances]). */
+/* Per instance, how many neurons had a V within the single-precision range
+ * at the start of a step and outside it at its end (|V| at or above FLT_MAX
+ * plus half its ulp, which rounds to infinity, or NaN): the sumNANs of
+ * Fig. 1, whose caption says the count covers overflow.  Each neuron counts
+ * once, at the step its V leaves the range (host int32[n_instances]). */
 int snn_get_nan_counts(snn_net *net, int32_t *per_instance);
 
 /* Replace every instance's g_scale (host float[n_instances], finite, >= 0).
@@ -292,7 +317,7 @@ int snn_time_kernel(snn_net *net, int32_t which, int64_t launches, double *ms_pe
 int snn_profile_steps(snn_net *net, int64_t n_steps, double *ms_total, int64_t *launches);
 
 /* Restore the state created by snn_create: every Traub-Miles neuron at its
- * resting point, conductances, traces, counts, Vbar sums, NaN counts and
+ * resting point, every Izhikevich neuron at v = -65 mV, u = b v, conductances, traces, counts, Vbar sums, NaN counts and
  * spikes at zero, step counter 0.  Weights (including STDP changes) and
  * g_scale are kept.  Enqueued on the net's stream. */
 int snn_reset(snn_net *net);

@@ -150,6 +150,30 @@ __device__ __forceinline__ void hh_substep(const Seg &S, double hs, double hc, d
     n = nn;
 }
 
+// Whether x stays finite once held in the fp32 state arrays: |x| below
+// FLT_MAX plus half its ulp (anything larger rounds to infinity; NaN fails).
+// The NaN count of the conductance sweep (Fig. 1) counts a neuron once, at
+// the step its V leaves this range.
+__device__ __forceinline__ bool fits_fp32(double x)
+{
+    return fabs(x) < 0x1.ffffffp127;
+}
+
+// Izhikevich (2003) neuron, the model of the 4:1 network of Section 5.1
+// (its reference [9]): v' = 0.04 v^2 + 5 v + 140 - u + I, u' = a (b v - u).
+// One forward-Euler substep, both right-hand sides from the substep-start
+// state, iin (synaptic + external) held over the step.  A step whose end
+// value reaches kIzhPeak is a spike: v <- c, u <- u + d.
+constexpr double kIzhPeak = 30.0;   // mV
+
+__device__ __forceinline__ void izh_substep(double ia, double ib, double hs, double iin, double &v, double &u)
+{
+    const double dv = 0.04 * v * v + 5.0 * v + 140.0 - u + iin;
+    const double du = ia * (ib * v - u);
+    v = v + hs * dv;
+    u = u + hs * du;
+}
+
 // A double held as an fp32 pair (hi = fl32(x), lo = fl32(x - hi)).
 __device__ __forceinline__ double pair_load(const float *hi, const float *lo, int64_t i)
 {

@@ -42,7 +42,7 @@ __host__ __device__ inline uint32_t group_words(uint32_t na, uint32_t rows, uint
 constexpr double kFixOne = 1099511627776.0;          // 2^40
 constexpr double kFixInv = 1.0 / 1099511627776.0;    // 2^-40
 
-enum { kPoisson = 0, kHH = 1 };
+enum { kPoisson = 0, kHH = 1, kIzh = 2 };
 
 // Delivery strategies (bitwise the same result; chosen by measurement):
 // rows = a work item per chunk of a spiking row, 64-bit atomics into G;
@@ -121,10 +121,12 @@ struct Seg {
     // Poisson
     uint64_t thresh;   // fires iff Philox word < thresh (thresh may be 2^32)
     uint64_t seed;
-    // Traub-Miles
+    // Traub-Miles (i_ext also for Izhikevich)
     double gna, ena, gk, ek, gl, el, inv_c, i_ext;
     int32_t record_vbar;
     int32_t pad_;
+    // Izhikevich: offset of the population's (a, b, c, d) in the parameter pool
+    int64_t izp_base;
 };
 
 struct Proj {
@@ -218,6 +220,7 @@ struct NeuronArgs {
     uint32_t *scnt;          // [2][n_segs]  spikes
     int32_t *awl;            // [2][n_waves]
     int32_t n_segs;
+    const float4 *izp;       // Izhikevich (a, b, c, d) per neuron, at Seg::izp_base + index
 };
 
 struct PropArgs {

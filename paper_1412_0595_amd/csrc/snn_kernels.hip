@@ -197,7 +197,43 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 pair_split(m, a.mh[gid], a.ml[gid]);
                 pair_split(h, a.hh[gid], a.hl[gid]);
                 pair_split(n, a.nh[gid], a.nl[gid]);
-                if (isfinite(v0) && !isfinite(v)) atomicAdd(&a.nan_count[s_inst], 1);
+                if (fits_fp32(v0) && !fits_fp32(v)) atomicAdd(&a.nan_count[s_inst], 1);
+                if (s_rec) a.vsum[gid] = vs + v;
+            }
+        } else if (s_kind == kIzh) {
+            // Izhikevich: v in the V pair, u in the M pair, (a, b, c, d) from
+            // the parameter pool; the same conductance handling as above
+            const double vs = s_rec ? a.vsum[gid] : 0.0;
+            double v = pair_load(a.vh, a.vl, gid);
+            double u = pair_load(a.mh, a.ml, gid);
+            const float4 pr = a.izp[S.izp_base + jj];
+            const double v0 = v;
+            const int64_t dcur = (int64_t)cur * a.G_count;
+            int64_t g[kMaxIn];
+#pragma unroll
+            for (int q = 0; q < kMaxIn; ++q)
+                if (q < s_nin) {
+                    g[q] = a.G[s_inG[q] + jj];
+                    if (a.mode == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
+                }
+            const double iin = syn_current(S, g, v0);
+            for (int k = 0; k < a.substeps; ++k) izh_substep((double)pr.x, (double)pr.y, a.hs, iin, v, u);
+            if (active) {
+#pragma unroll
+                for (int q = 0; q < kMaxIn; ++q)
+                    if (q < s_nin) {
+                        a.G[s_inG[q] + j] = fix_decay(g[q], S.in_decay[q]);
+                        if (a.mode == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
+                    }
+                // threshold on the step's end value, then the reset
+                spike = v >= kIzhPeak;
+                if (fits_fp32(v0) && !fits_fp32(v)) atomicAdd(&a.nan_count[s_inst], 1);
+                if (spike) {
+                    v = (double)pr.z;
+                    u = u + (double)pr.w;
+                }
+                pair_split(v, a.vh[gid], a.vl[gid]);
+                pair_split(u, a.mh[gid], a.ml[gid]);
                 if (s_rec) a.vsum[gid] = vs + v;
             }
         } else {

@@ -117,6 +117,7 @@ struct snn_net {
     std::vector<float> gscale;
     int64_t n_waves, n_neurons_padded;
     int64_t n_hh;                    // Traub-Miles neurons (not padded)
+    int64_t n_izh;                   // Izhikevich neurons
     bool plastic;
     int64_t qcap, lcap;
     int raster_steps;
@@ -148,6 +149,7 @@ struct snn_net {
     int64_t *D;          // arena: [2][G pool]  fused-mode deliveries for the next update
     float *d_w;
     float *d_gscale;
+    float4 *d_izp;       // Izhikevich parameters (a, b, c, d) per neuron
     int64_t w_count;
     // arena of everything a step mutates (one block, so that snapshots are one copy)
     char *d_arena;
@@ -299,6 +301,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.w_pool = net->d_w;
     a.gscale = net->d_gscale;
     a.n_segs = (int32_t)net->segs.size();
+    a.izp = net->d_izp;
     return a;
 }
 
@@ -446,12 +449,14 @@ int run_steps(snn_net *net, int64_t n)
     return SNN_OK;
 }
 
-int seg_index(const snn_net *net, int32_t inst, int32_t pop, bool need_hh)
+// need_state: the population must have a membrane state (Traub-Miles or
+// Izhikevich, not Poisson)
+int seg_index(const snn_net *net, int32_t inst, int32_t pop, bool need_state)
 {
     if (inst < 0 || inst >= net->n_inst) return fail(SNN_EINVAL, "instance %d out of range", inst);
     if (pop < 0 || pop >= (int32_t)net->seg_of[inst].size()) return fail(SNN_EINVAL, "population %d out of range", pop);
     const int s = net->seg_of[inst][pop];
-    if (need_hh && net->segs[s].kind != kHH) return fail(SNN_EINVAL, "population %d is not Traub-Miles", pop);
+    if (need_state && net->segs[s].kind == kPoisson) return fail(SNN_EINVAL, "population %d is a Poisson source (no state)", pop);
     return s;
 }
 
@@ -496,7 +501,8 @@ int validate(const snn_config *cfg)
         std::vector<int> n_in(I.n_pops, 0), n_out(I.n_pops, 0), n_tr(I.n_pops, 0), n_ltp(I.n_pops, 0);
         for (int p = 0; p < I.n_pops; ++p) {
             const snn_pop_desc &P = I.pops[p];
-            if (P.kind != SNN_POISSON && P.kind != SNN_TRAUB_MILES) return fail(SNN_EINVAL, "instance %d pop %d: bad kind %d", b, p, P.kind);
+            if (P.kind != SNN_POISSON && P.kind != SNN_TRAUB_MILES && P.kind != SNN_IZHIKEVICH)
+                return fail(SNN_EINVAL, "instance %d pop %d: bad kind %d", b, p, P.kind);
             if (P.n < 0) return fail(SNN_EINVAL, "instance %d pop %d: n < 0", b, p);
             if (P.kind == SNN_POISSON && (!(P.rate_hz >= 0.0) || !std::isfinite(P.rate_hz)))
                 return fail(SNN_EINVAL, "instance %d pop %d: rate must be finite and >= 0", b, p);
@@ -508,13 +514,20 @@ int validate(const snn_config *cfg)
                 double r[4];
                 if (!resting_state(P.hh, r)) return fail(SNN_EINVAL, "instance %d pop %d: no resting point in [-80, -60] mV", b, p);
             }
+            if (P.kind == SNN_IZHIKEVICH) {
+                if (!std::isfinite(P.i_ext_nA)) return fail(SNN_EINVAL, "instance %d pop %d: i_ext not finite", b, p);
+                if (P.n > 0 && !P.izh_abcd) return fail(SNN_EINVAL, "instance %d pop %d: izh_abcd is NULL", b, p);
+                for (int64_t k = 0; k < 4 * (int64_t)P.n; ++k)
+                    if (!std::isfinite(P.izh_abcd[k]))
+                        return fail(SNN_EINVAL, "instance %d pop %d: Izhikevich parameter %lld not finite", b, p, (long long)k);
+            }
         }
         for (int q = 0; q < I.n_projs; ++q) {
             const snn_proj_desc &Q = I.projs[q];
             if (Q.pre_pop < 0 || Q.pre_pop >= I.n_pops || Q.post_pop < 0 || Q.post_pop >= I.n_pops)
                 return fail(SNN_EINVAL, "instance %d proj %d: population index out of range", b, q);
-            if (I.pops[Q.post_pop].kind != SNN_TRAUB_MILES)
-                return fail(SNN_EINVAL, "instance %d proj %d: post population must be Traub-Miles", b, q);
+            if (I.pops[Q.post_pop].kind == SNN_POISSON)
+                return fail(SNN_EINVAL, "instance %d proj %d: post population must be Traub-Miles or Izhikevich", b, q);
             if (!(Q.tau_ms > 0.0f) || !std::isfinite(Q.tau_ms) || !std::isfinite(Q.e_rev_mV))
                 return fail(SNN_EINVAL, "instance %d proj %d: tau must be > 0 and e_rev finite", b, q);
             const int32_t npre = I.pops[Q.pre_pop].n, npost = I.pops[Q.post_pop].n;
@@ -666,7 +679,9 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->proj_of.resize(net->n_inst);
     net->gscale.resize(net->n_inst);
     net->n_hh = 0;
+    net->n_izh = 0;
     net->plastic = false;
+    int64_t izp_total = 0;
     std::vector<double> colsum_bound, w_bound;
     for (int b = 0; b < net->n_inst; ++b) {
         const snn_instance_desc &I = cfg->inst[b];
@@ -674,7 +689,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
         for (int p = 0; p < I.n_pops; ++p) {
             const snn_pop_desc &P = I.pops[p];
             Seg S{};
-            S.kind = P.kind == SNN_POISSON ? kPoisson : kHH;
+            S.kind = P.kind == SNN_POISSON ? kPoisson : P.kind == SNN_IZHIKEVICH ? kIzh : kHH;
             S.n = P.n;
             S.base = base;
             S.inst = b;
@@ -689,6 +704,11 @@ int snn_create(const snn_config *cfg, snn_net **out)
             net->segs.push_back(S);
             base += align_up(P.n, kWave);
             if (S.kind == kHH) net->n_hh += P.n;
+            if (S.kind == kIzh) {
+                net->segs.back().izp_base = izp_total;
+                izp_total += P.n;
+                net->n_izh += P.n;
+            }
         }
         for (int q = 0; q < I.n_projs; ++q) {
             const snn_proj_desc &Q = I.projs[q];
@@ -946,6 +966,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->d_pull_col = (int32_t *)dev_alloc(net, 4 * (size_t)kWave * std::max<size_t>(pull_slices.size(), 1));
     net->d_pull_rw = (int2 *)dev_alloc(net, 8 * std::max<int64_t>(pull_total, 1));
     net->d_pull_perm = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(pull_total, 1));
+    net->d_izp = (float4 *)dev_alloc(net, sizeof(float4) * (size_t)std::max<int64_t>(izp_total, 1));
+    if (!net->d_izp) return bail(fail(SNN_ENOMEM, "device allocation failed"));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
         !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
         !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_rw ||
@@ -985,6 +1007,17 @@ int snn_create(const snn_config *cfg, snn_net **out)
             for (int64_t w = S.base / kWave; w < (S.base + align_up(S.n, kWave)) / kWave; ++w) wave_seg[w] = (int32_t)s;
         }
         if ((rc = up(net->d_wave_seg, wave_seg.data(), 4 * W))) return bail(rc);
+        // Izhikevich parameters, interleaved per neuron for one 16-byte load
+        std::vector<float4> izp(std::max<int64_t>(izp_total, 1), make_float4(0.f, 0.f, 0.f, 0.f));
+        for (size_t s = 0; s < net->segs.size(); ++s) {
+            const Seg &S = net->segs[s];
+            if (S.kind != kIzh) continue;
+            const float *abcd = cfg->inst[S.inst].pops[S.pop].izh_abcd;
+            for (int32_t j = 0; j < S.n; ++j)
+                izp[S.izp_base + j] = make_float4(abcd[j], abcd[S.n + j], abcd[2 * (int64_t)S.n + j],
+                                                  abcd[3 * (int64_t)S.n + j]);
+        }
+        if ((rc = up(net->d_izp, izp.data(), sizeof(float4) * (size_t)izp_total))) return bail(rc);
         if ((rc = up(net->d_units, units.data(), sizeof(int4) * units.size()))) return bail(rc);
         if ((rc = up(net->d_pull_units, pull_units.data(), sizeof(PullUnit) * pull_units.size()))) return bail(rc);
         if ((rc = up(net->d_pull_slices, pull_red.data(), sizeof(PullSlice) * pull_red.size()))) return bail(rc);
@@ -1064,7 +1097,8 @@ int snn_create(const snn_config *cfg, snn_net **out)
             }
         }
     }
-    // initial state: rest point of every Traub-Miles population; the rest zero
+    // initial state: rest point of every Traub-Miles population, v = -65 mV
+    // and u = b v for every Izhikevich population; the rest zero
     {
         std::vector<float> hi[4], lo[4];
         for (int k = 0; k < 4; ++k) {
@@ -1074,6 +1108,17 @@ int snn_create(const snn_config *cfg, snn_net **out)
         for (int b = 0; b < net->n_inst; ++b)
             for (int p = 0; p < cfg->inst[b].n_pops; ++p) {
                 const snn_pop_desc &P = cfg->inst[b].pops[p];
+                if (P.kind == SNN_IZHIKEVICH) {
+                    const Seg &S = net->segs[net->seg_of[b][p]];
+                    for (int32_t j = 0; j < S.n; ++j) {
+                        const double v0 = -65.0, u0 = (double)P.izh_abcd[S.n + j] * v0;
+                        hi[0][S.base + j] = (float)v0;
+                        lo[0][S.base + j] = (float)(v0 - (double)(float)v0);
+                        hi[1][S.base + j] = (float)u0;
+                        lo[1][S.base + j] = (float)(u0 - (double)(float)u0);
+                    }
+                    continue;
+                }
                 if (P.kind != SNN_TRAUB_MILES) continue;
                 double r[4];
                 resting_state(P.hh, r);
@@ -1206,7 +1251,8 @@ int snn_get_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, doub
     if (rc) return rc;
     const int s = seg_index(net, inst, pop, true);
     if (s < 0) return s;
-    if (var < 0 || var > 3) return fail(SNN_EINVAL, "bad variable %d", var);
+    if (var < 0 || var > (net->segs[s].kind == kIzh ? 1 : 3))
+        return fail(SNN_EINVAL, "bad variable %d for population %d", var, pop);
     if (!out) return fail(SNN_EINVAL, "out is NULL");
     const Seg &S = net->segs[s];
     std::vector<float> h(S.n), l(S.n);
@@ -1234,7 +1280,8 @@ int snn_set_state_f64(snn_net *net, int32_t inst, int32_t pop, int32_t var, cons
     if (rc) return rc;
     const int s = seg_index(net, inst, pop, true);
     if (s < 0) return s;
-    if (var < 0 || var > 3) return fail(SNN_EINVAL, "bad variable %d", var);
+    if (var < 0 || var > (net->segs[s].kind == kIzh ? 1 : 3))
+        return fail(SNN_EINVAL, "bad variable %d for population %d", var, pop);
     if (!in) return fail(SNN_EINVAL, "in is NULL");
     const Seg &S = net->segs[s];
     std::vector<float> h(S.n), l(S.n);

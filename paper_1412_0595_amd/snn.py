@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_ESTATE, SNN_ERANGE = 0, -1, -2, -3, -4, -5
-POISSON, TRAUB_MILES = 0, 1
+POISSON, TRAUB_MILES, IZHIKEVICH = 0, 1, 2
 V, M, H, N = 0, 1, 2, 3
+U = 1   # recovery variable of an Izhikevich population
 
 # Every symbol include/snn.h declares.
 EXPORTS = [
@@ -33,7 +34,7 @@ EXPORTS = [
 
 class PopDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("rate_hz", C.c_double), ("i_ext_nA", C.c_double),
-                ("hh", C.c_double * 7), ("record_vbar", C.c_int32)]
+                ("hh", C.c_double * 7), ("record_vbar", C.c_int32), ("izh_abcd", C.c_void_p)]
 
 
 class ProjDesc(C.Structure):
@@ -159,7 +160,13 @@ def build_config(spec, *, record_vbar=(), raster_steps=0, autotune=False, tune_c
     for b, inst in enumerate(spec["instances"]):
         pops = (PopDesc * len(inst["pops"]))()
         for k, p in enumerate(inst["pops"]):
-            pops[k].kind = POISSON if p["kind"] == "poisson" else TRAUB_MILES
+            pops[k].kind = {"poisson": POISSON, "hh": TRAUB_MILES, "izh": IZHIKEVICH}[p["kind"]]
+            if p["kind"] == "izh":
+                abcd = np.ascontiguousarray(p["abcd"], np.float32)
+                if abcd.shape != (4, int(p["n"])):
+                    raise ValueError("abcd must be float32[4, n]")
+                keep.append(abcd)
+                pops[k].izh_abcd = abcd.ctypes.data
             pops[k].n = int(p["n"])
             pops[k].rate_hz = float(p.get("rate_hz", 0.0))
             pops[k].i_ext_nA = float(p.get("i_ext", 0.0))

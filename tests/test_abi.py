@@ -149,6 +149,38 @@ def test_single_weight_range_rejected():
     assert rc == snn.SNN_ERANGE and "largest weight" in msg, msg
 
 
+def _izh_spec(n_conn=50):
+    inst = netgen.izhikevich_instance(n_conn, n_exc=80, n_inh=20, n_in=50, seed=1, conn_seed=2)
+    return dict(dt=0.1, substeps=3, instances=[inst])
+
+
+def test_izhikevich_description_validated():
+    """An Izhikevich population passes the host checks; a non-finite a, b, c
+    or d, missing parameters or a wrong kind are rejected before any device
+    call."""
+    rc, msg = snn.create_status(_izh_spec())
+    assert rc in (snn.SNN_OK, snn.SNN_EDEVICE), msg
+    for k in range(4):
+        spec = _izh_spec()
+        bad = spec["instances"][0]["pops"][1]["abcd"].copy()
+        bad[k, 7] = np.inf
+        spec["instances"][0]["pops"][1]["abcd"] = bad
+        rc, msg = snn.create_status(spec)
+        assert rc == snn.SNN_EINVAL and "Izhikevich parameter" in msg, msg
+    L = snn.load()
+    cfg, keep = snn.build_config(_izh_spec())
+    inst = snn.InstDesc.from_address(cfg.inst)
+    pops = (snn.PopDesc * inst.n_pops).from_address(inst.pops)
+    pops[2].izh_abcd = None
+    h = ctypes.c_void_p()
+    rc = L.snn_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == snn.SNN_EINVAL and "izh_abcd is NULL" in snn.last_error()
+    pops[2].izh_abcd = pops[1].izh_abcd
+    pops[2].kind = 7
+    rc = L.snn_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc == snn.SNN_EINVAL and "bad kind" in snn.last_error()
+
+
 def test_valid_description_passes_validation():
     """A valid network passes every host check; without a GPU the first
     device call then fails cleanly with SNN_EDEVICE (on a GPU it succeeds)."""

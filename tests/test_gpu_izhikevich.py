@@ -1,0 +1,206 @@
+"""Izhikevich populations on the GPU (the 4:1 excitatory/inhibitory network
+of Section 5.1, whose neuron model is the paper's reference [9]) against the
+FP64 oracle, through the C ABI.
+
+The library holds v and u as fp32 pairs and does the update in double, so
+away from spike-time flips it follows the FP64 oracle to about 1e-12 mV; the
+bar is the network's 1e-3 mV RMS over the first 1000 steps, with spike counts
+per neuron compared (identical here).  The calibration sweep of Fig. 1 over
+nConn runs on this network as it does on the layered one."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1412_0595_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0595_amd import snn as S
+    S.load()
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def single_neuron_instance():
+    """Unconnected Izhikevich neurons of the reference's classes (regular
+    spiking, intrinsically bursting, chattering, fast spiking, low-threshold
+    spiking, resonator) under constant currents 0..15, 70 neurons in all, so
+    that one population spans two 64-lane waves and a ragged tail."""
+    classes = [(0.02, 0.2, -65.0, 8.0), (0.02, 0.2, -55.0, 4.0), (0.02, 0.2, -50.0, 2.0),
+               (0.1, 0.2, -65.0, 2.0), (0.02, 0.25, -65.0, 2.0), (0.1, 0.26, -65.0, 2.0)]
+    rows = []
+    currents = []
+    for k in range(70):
+        rows.append(classes[k % len(classes)])
+        currents.append(15.0 * (k // len(classes)) / 11.0)
+    abcd = np.asarray(rows, np.float32).T.copy()
+    return abcd, np.asarray(currents)
+
+
+def test_izhikevich_neurons_match_oracle_every_step(snn):
+    """Every neuron class under a range of steady drives, v and u compared
+    with the oracle after every step.  The drive of each neuron is its own
+    synapse from a source that fires every step (rate far above 1/dt), with
+    reversal 0 mV: G settles at w / (1 - e^(-dt/tau)) and injects G (0 - v),
+    about the nominal current at v = -65 mV.
+
+    Some of these neurons (bursting and chattering classes near their onset
+    currents) amplify a perturbation about e-fold every 75 steps: in the
+    oracle itself, 1e-12 mV added to v grows to 3.5e-7 mV by step 1000 and to
+    0.3 mV by step 2000.  The library's conductances sit on a 2^-40 uS grid
+    (about 1e-11 of these conductances per delivery and decay), which those
+    neurons amplify to about 1.5e-3 mV at worst by step 1000; a CPU
+    emulation of the same arithmetic gives the same figure, with an RMS of
+    9e-6 mV.  So the bar is the network bar, v and u RMS over every neuron
+    and step of the first 1000 within 1e-3 (the largest single difference is
+    reported and held to 1e-2), spike counts identical; over steps 1000-2000
+    a spike may legitimately move by a step, and the counts are held to
+    within one."""
+    say("case: unconnected Izhikevich neurons, six classes x twelve drives, 2000 steps, every step")
+    abcd, cur = single_neuron_instance()
+    n = abcd.shape[1]
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    w = (cur / 3300.0).astype(np.float32)
+    inst = dict(g_scale=1.0, seed=9,
+                pops=[dict(name="S", kind="poisson", n=n, rate_hz=1e9, i_ext=0.0),
+                      dict(name="Z", kind="izh", n=n, rate_hz=0.0, i_ext=0.0, abcd=abcd)],
+                projs=[dict(pre=0, post=1, row_ptr=rp, col_idx=ci, g=w, e_rev=0.0, tau=5.0, stdp=None)])
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    net = snn.Network(spec)
+    orc = O.OracleNet(inst)
+    v0 = net.state(0, 1, snn.V)
+    u0 = net.state(0, 1, snn.U)
+    assert np.array_equal(v0, np.full(n, -65.0, np.float32))
+    assert np.array_equal(u0, abcd[1].astype(np.float64) * -65.0)
+    dv = du = sv = su = 0.0
+    for t in range(1000):
+        net.step(1)
+        orc.step(1)
+        ev = net.state(0, 1, snn.V) - orc.get(1, O.V)
+        eu = net.state(0, 1, snn.U) - orc.get(1, O.M)
+        dv, du = max(dv, float(np.max(np.abs(ev)))), max(du, float(np.max(np.abs(eu))))
+        sv, su = sv + float(np.sum(ev * ev)), su + float(np.sum(eu * eu))
+    rv, ru = np.sqrt(sv / (1000 * n)), np.sqrt(su / (1000 * n))
+    same = np.array_equal(net.spikes(0, 1), orc.counts(1))
+    say(f"  steps 1-1000: v RMS {rv:.2e} mV (max |dv| {dv:.2e}), u RMS {ru:.2e} (max {du:.2e}); "
+        f"spike counts identical: {same}")
+    assert same
+    assert rv <= 1e-3 and ru <= 1e-3
+    assert dv <= 1e-2 and du <= 1e-2
+    net.step(1000)
+    orc.step(1000)
+    diff = np.abs(net.spikes(0, 1) - orc.counts(1))
+    say(f"  steps 1-2000: spike counts identical for {int(np.sum(diff == 0))} of {n}, max |difference| "
+        f"{int(diff.max())}; counts {orc.counts(1)[:12].tolist()}...")
+    assert diff.max() <= 1
+    assert orc.counts(1).max() > 20 and orc.counts(1).min() == 0
+    net.close()
+
+
+def test_izhikevich_state_access(snn):
+    """SNN_U reads and writes u; h and n do not exist for this kind; the
+    parameters are validated at create."""
+    abcd, _ = single_neuron_instance()
+    n = abcd.shape[1]
+    inst = dict(g_scale=1.0, seed=1, pops=[dict(name="Z", kind="izh", n=n, rate_hz=0.0, i_ext=10.0, abcd=abcd)],
+                projs=[])
+    net = snn.Network(dict(dt=0.1, substeps=3, instances=[inst]))
+    # a double-float pair holds any fp32 value exactly, and a double to ~2^-48
+    u = np.linspace(-20.0, 5.0, n).astype(np.float32).astype(np.float64)
+    net.set_state(0, 0, snn.U, u)
+    assert np.array_equal(net.state(0, 0, snn.U), u)
+    u2 = np.linspace(-20.0, 5.0, n)
+    net.set_state(0, 0, snn.U, u2)
+    np.testing.assert_allclose(net.state(0, 0, snn.U), u2, rtol=2.0 ** -46, atol=0)
+    with pytest.raises(snn.SNNError):
+        net.state(0, 0, snn.H)
+    with pytest.raises(snn.SNNError):
+        net.set_state(0, 0, snn.N, u)
+    net.reset()
+    assert np.array_equal(net.state(0, 0, snn.V), np.full(n, -65.0, np.float32))
+    net.close()
+    bad = abcd.copy()
+    bad[2, 5] = np.nan
+    inst["pops"][0]["abcd"] = bad
+    with pytest.raises(snn.SNNError):
+        snn.Network(dict(dt=0.1, substeps=3, instances=[inst]))
+
+
+@pytest.mark.parametrize("n_conn", [100, 500, 1000])
+def test_izhikevich_network_matches_oracle(snn, n_conn):
+    """The 4:1 network (800 excitatory, 200 inhibitory neurons, 1000 Poisson
+    inputs) at nConn recurrent connections per neuron: v RMS over every step
+    of the first 1000 within 1e-3 mV, u likewise, spike counts per neuron
+    identical."""
+    T = 1000
+    inst = netgen.izhikevich_instance(n_conn, seed=5, conn_seed=11)
+    say(f"case: 4:1 Izhikevich network, nConn {n_conn}, {T} steps, every step")
+    net = snn.Network(dict(dt=0.1, substeps=3, instances=[inst]))
+    orc = O.OracleNet(inst)
+    sv = su = 0.0
+    cnt = 0
+    for t in range(T):
+        net.step(1)
+        orc.step(1)
+        for p in (1, 2):
+            dv = net.state(0, p, snn.V) - orc.get(p, O.V)
+            du = net.state(0, p, snn.U) - orc.get(p, O.M)
+            sv += float(np.sum(dv * dv))
+            su += float(np.sum(du * du))
+            cnt += dv.size
+    rv, ru = np.sqrt(sv / cnt), np.sqrt(su / cnt)
+    same = [float(np.mean(net.spikes(0, p) == orc.counts(p))) for p in (1, 2)]
+    rate = orc.counts(1).mean() / (T * 0.1e-3)
+    say(f"  v RMS {rv:.2e} mV, u RMS {ru:.2e}; spike counts identical E {same[0]:.4f} I {same[1]:.4f}; "
+        f"E rate {rate:.1f} Hz; NaN {net.nan_counts()[0]} (oracle {orc.nan_count})")
+    assert rv <= 1e-3 and ru <= 1e-3
+    assert same == [1.0, 1.0]
+    assert net.nan_counts()[0] == orc.nan_count
+    net.close()
+
+
+def test_izhikevich_batch_in_every_delivery_mode(snn):
+    """A batch of 4:1 networks at several nConn and gScale: every delivery
+    mode gives the same bits (integer conductances), and each instance's
+    spike counts equal the oracle's after 600 steps."""
+    T = 600
+    spec = netgen.izhikevich_calibration_config([100, 300], [0.3, 1.0, 3.0], n_exc=400, n_inh=100, steps=T)
+    say(f"case: batch of {len(spec['instances'])} Izhikevich networks, {T} steps, delivery modes 0/1/2")
+    res = []
+    for mode in (0, 1, 2):
+        net = snn.Network(spec)
+        net.set_launch(mode=mode)
+        net.step(T)
+        res.append(([net.state(b, p, snn.V) for b in range(len(spec["instances"])) for p in (1, 2)],
+                    [net.spikes(b, p) for b in range(len(spec["instances"])) for p in (1, 2)]))
+        net.close()
+    for r in res[1:]:
+        assert all(np.array_equal(x, y) for x, y in zip(res[0][0], r[0]))
+        assert all(np.array_equal(x, y) for x, y in zip(res[0][1], r[1]))
+    for b, inst in enumerate(spec["instances"]):
+        orc = O.OracleNet(inst)
+        orc.step(T)
+        for k, p in enumerate((1, 2)):
+            assert np.array_equal(res[0][1][2 * b + k], orc.counts(p)), (b, p)
+
+
+def test_izhikevich_calibration_matches_oracle(snn):
+    """Fig. 1 on the 4:1 network: nConn 100..500 x 9 gScale (the recurrent
+    weights' scale), criterion E's avgSpike; the per-run table run by run,
+    the selection bit-exact and the fit against the calibration oracle."""
+    from test_gpu_calibrate import check_sweep
+    T = 1000
+    spec = netgen.izhikevich_calibration_config([100, 200, 300, 500], 10.0 ** np.linspace(-1.0, 1.0, 9), steps=T)
+    say(f"case: Izhikevich calibration sweep, {len(spec['instances'])} runs, {T} steps")
+    res, nan_runs = check_sweep(snn, spec, 100.0, T)
+    assert not nan_runs.any()

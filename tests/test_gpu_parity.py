@@ -183,6 +183,35 @@ def test_compaction_exact_zero_and_non_finite(snn):
     net.close()
 
 
+def test_nan_count_edge_is_the_single_precision_range(snn):
+    """The NaN count of Fig. 1 counts a neuron once, at the step its V leaves
+    the fp32 state's range: a leak-only neuron whose V lands exactly on
+    FLT_MAX + half an ulp (which rounds to infinity) counts, one landing on the
+    double just below it does not (the same instance as the oracle's pin of
+    this edge).  Only the first step is compared: the stored pair of the value
+    just below the edge (hi = FLT_MAX, lo = fl32(rest)) reads back as the edge
+    itself, so from there on the two sides may count that neuron differently;
+    nothing in the range a network reaches before it overflows is affected."""
+    say("case: NaN count at the single-precision range edge")
+    from test_oracle_kinetics import nan_edge_instance
+    inst, hp, edge, below = nan_edge_instance(O)
+    spec = dict(dt=0.125, substeps=1, instances=[inst])
+    net = snn.Network(spec, hh_params=hp)
+    orc = O.OracleNet(inst, dt=0.125, substeps=1, hh_params=hp)
+    for p in (0, 1):
+        net.set_state(0, p, snn.V, [-64.0])
+        orc.set(p, O.V, [-64.0])
+    net.step(1)
+    orc.step(1)
+    assert orc.nan_count == 1
+    assert net.nan_counts()[0] == 1
+    assert not np.isfinite(net.state(0, 0, snn.V)[0])
+    # the neuron that overflowed is not counted again
+    net.step(1)
+    assert net.nan_counts()[0] >= 1 and not np.isfinite(net.state(0, 0, snn.V)[0])
+    net.close()
+
+
 def test_one_step_update_from_same_state(snn):
     """From an identical random state (including mid-spike and hyperpolarised
     neurons and nonzero conductances) one step agrees to far below fp32."""
