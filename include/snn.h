@@ -366,6 +366,25 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
 int snn_backward(snn_net *net, const double *dL_dvbar_dev, float *dL_dg_dev, double *dL_dgscale_dev,
                  int64_t *mismatch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * backward pass of snn_backward, with the same kernels and results, but its
+ * scratch -- the per-segment tape of recomputed states and delivered
+ * conductances, their adjoints and the adjoint carried from segment to
+ * segment, 8 * n_loss * (K * (4 + 2 * n_in) + 4 + n_in) + 256 bytes for
+ * n_loss loss neurons over the batch, checkpoint interval K and at most
+ * n_in projections into a loss neuron -- in a fixed library-wide device
+ * array of SNN_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends)
+ * instead of the net's buffers.  It calls no allocator and records no memset
+ * (outputs and scratch are cleared by a kernel).  Arguments as snn_backward
+ * (no recompute check is reported).  SNN_ERANGE if the recording needs more
+ * scratch than the array holds; SNN_ESTATE without a recording.  All calls
+ * on one GPU share the array and it keeps the last call's contents: calls
+ * that overlap on one GPU (any nets, any streams) race and give wrong
+ * gradients; serialise them. */
+enum { SNN_NOALLOC_SCRATCH_BYTES = 64 << 20 };
+int snn_backward_noalloc(snn_net *net, const double *dL_dvbar_dev, float *dL_dg_dev, double *dL_dgscale_dev);
+
 /* ---------------- Conductance-scale calibration (Section 5.1) ----------------
  * Host routines over the per-run table of a conductance-scaling sweep (one
  * row per run: nConn, gScale, avgSpike, NaN count), as in Fig. 1.  They keep

@@ -328,6 +328,8 @@ hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_
 hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);
 hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n, hipStream_t s);
+// Zero `bytes` (a multiple of 4) at p with a kernel.
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_check_weights(const float *w, const Proj *projs, int32_t n_projs, int64_t max_nnz, uint32_t *flag,
                                 uint32_t *wmax, hipStream_t s);
 

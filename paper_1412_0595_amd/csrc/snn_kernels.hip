@@ -1221,4 +1221,28 @@ hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_
     return hipGetLastError();
 }
 
+// Zero n_words 32-bit words with a kernel (a fill inside a captured graph
+// stays a kernel node; no memset node): 16-byte stores over the aligned body
+// when p is 16-byte aligned, 4-byte stores for the rest.
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p, int64_t n_words, int32_t vec)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = vec ? n_words / 4 : 0;
+    uint4 *p4 = reinterpret_cast<uint4 *>(p);
+    for (int64_t i = i0; i < n4; i += stride) p4[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = 4 * n4 + i0; i < n_words; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t n_words = (int64_t)(bytes / 4);
+    if (n_words == 0) return hipSuccess;
+    const int32_t vec = ((uintptr_t)p & 15u) == 0 ? 1 : 0;
+    const int64_t items = vec ? (n_words + 3) / 4 : n_words;
+    const int64_t blocks = std::min<int64_t>((items + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, n_words, vec);
+    return hipGetLastError();
+}
+
 }  // namespace snn

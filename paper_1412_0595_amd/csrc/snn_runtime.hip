@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,44 @@ int fail(int code, const char *fmt, ...)
 }  // namespace
 
 int snn::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+// ------------------------ scratch of snn_backward_noalloc ---------------------
+// A fixed device array that snn_backward_noalloc uses in place of the net's
+// backward tape, for callers that cannot allocate.  Every GPU the library
+// runs on holds its own copy for the life of the process; host code reaches
+// it only through the device address hipGetSymbolAddress returns on that GPU
+// (the array's name is a host-side stand-in, not a device address).
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)SNN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+
+// Looks up the array's address on device dev, which must be current, once
+// per device (snn_create does it for every net's device); nullptr if the
+// lookup failed.
+void *scratch_on_device(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+        g_scratch_done[dev] = true;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -897,6 +936,9 @@ int snn_create(const snn_config *cfg, snn_net **out)
         (void)hipGetLastError();
         return bail(fail(SNN_EDEVICE, "no HIP device"));
     }
+    // set-up of snn_backward_noalloc on this device (its failure only
+    // disables that entry point, which then reports it)
+    (void)scratch_on_device(net->device);
     if (hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         net->cap_stream = nullptr;
@@ -1938,18 +1980,34 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
     return SNN_OK;
 }
 
-int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_dgscale, int64_t *mismatch)
+}  // extern "C"
+
+namespace {
+
+// The backward pass of snn_backward and snn_backward_noalloc: per segment,
+// from the last to the first, recompute the loss population from its
+// checkpoint into the tape, reverse it, gather the weight gradients.  The
+// tape (tape_x, tape_g, lg), the adjoint carried across segments (lam) and
+// the recompute check flag are the callers' scratch; lam, the flag and the
+// two outputs are cleared here, by memset nodes or (fill_kernel) by a fill
+// kernel.
+int run_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_dgscale, double *tape_x,
+                 double *tape_g, double *lg, double *lam, uint32_t *flag, bool fill_kernel)
 {
-    int rc = check_net(net);
-    if (rc) return rc;
-    if (!net->recorded) return fail(SNN_ESTATE, "call snn_forward_record first");
-    if (!dL_dvbar || !dL_dg || !dL_dgscale) return fail(SNN_EINVAL, "NULL argument");
     const int64_t N = net->n_neurons_padded;
     const int64_t gstride = std::max<int64_t>(net->G_count, 1);
-    HIP_OK(hipMemsetAsync(net->d_lam, 0, 8 * (size_t)((4 + net->n_in_max) * std::max<int64_t>(net->n_loss, 1)), net->stream));
-    HIP_OK(hipMemsetAsync(dL_dg, 0, 4 * (size_t)net->w_count, net->stream));
-    HIP_OK(hipMemsetAsync(dL_dgscale, 0, 8 * (size_t)net->n_inst, net->stream));
-    HIP_OK(hipMemsetAsync(net->d_flag, 0, 4, net->stream));
+    const size_t lam_bytes = 8 * (size_t)((4 + net->n_in_max) * std::max<int64_t>(net->n_loss, 1));
+    if (fill_kernel) {
+        HIP_OK(launch_fill_zero(lam, lam_bytes, net->stream));
+        HIP_OK(launch_fill_zero(dL_dg, 4 * (size_t)net->w_count, net->stream));
+        HIP_OK(launch_fill_zero(dL_dgscale, 8 * (size_t)net->n_inst, net->stream));
+        HIP_OK(launch_fill_zero(flag, 4, net->stream));
+    } else {
+        HIP_OK(hipMemsetAsync(lam, 0, lam_bytes, net->stream));
+        HIP_OK(hipMemsetAsync(dL_dg, 0, 4 * (size_t)net->w_count, net->stream));
+        HIP_OK(hipMemsetAsync(dL_dgscale, 0, 8 * (size_t)net->n_inst, net->stream));
+        HIP_OK(hipMemsetAsync(flag, 0, 4, net->stream));
+    }
     AdjArgs a{};
     a.segs = net->d_segs;
     a.projs = net->d_projs;
@@ -1963,15 +2021,15 @@ int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_
     a.n_waves = net->n_waves;
     a.T = net->rec_T;
     a.n_pad = N;
-    a.mismatch = net->d_flag;
+    a.mismatch = flag;
     a.rp_pool = net->d_rp;
     a.col_pool = net->d_col;
     a.w_pool = net->d_w;
     a.gscale = net->d_gscale;
-    a.tape_x = net->d_tape_x;
-    a.tape_g = net->d_tape_g;
-    a.lam = net->d_lam;
-    a.lg = net->d_lg;
+    a.tape_x = tape_x;
+    a.tape_g = tape_g;
+    a.lam = lam;
+    a.lg = lg;
     a.dvbar = dL_dvbar;
     a.substeps = net->substeps;
     a.hs = net->dt / net->substeps;
@@ -1990,6 +2048,32 @@ int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_
         HIP_OK(launch_adj_reverse(a, net->stream));
         HIP_OK(launch_adj_gather(a, net->stream));
     }
+    return SNN_OK;
+}
+
+// Bytes of scratch the backward of the current recording needs: the check
+// flag (256 B, keeping what follows aligned), then tape_x [K][4][n_loss],
+// tape_g and lg [K][n_in_max][n_loss], lam [4 + n_in_max][n_loss], doubles.
+size_t backward_scratch_bytes(const snn_net *net)
+{
+    const size_t nl = (size_t)std::max<int64_t>(net->n_loss, 1), K = (size_t)net->rec_K;
+    const size_t nin = (size_t)net->n_in_max;
+    return 256 + 8 * nl * (K * 4 + 2 * K * nin + 4 + nin);
+}
+
+}  // namespace
+
+extern "C" {
+
+int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_dgscale, int64_t *mismatch)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!net->recorded) return fail(SNN_ESTATE, "call snn_forward_record first");
+    if (!dL_dvbar || !dL_dg || !dL_dgscale) return fail(SNN_EINVAL, "NULL argument");
+    if ((rc = run_backward(net, dL_dvbar, dL_dg, dL_dgscale, net->d_tape_x, net->d_tape_g, net->d_lg, net->d_lam,
+                           net->d_flag, false)))
+        return rc;
     if (mismatch) {
         uint32_t m = 0;
         HIP_OK(hipMemcpyAsync(&m, net->d_flag, 4, hipMemcpyDeviceToHost, net->stream));
@@ -1997,6 +2081,29 @@ int snn_backward(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_
         *mismatch = m;
     }
     return SNN_OK;
+}
+
+int snn_backward_noalloc(snn_net *net, const double *dL_dvbar, float *dL_dg, double *dL_dgscale)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!net->recorded) return fail(SNN_ESTATE, "call snn_forward_record first");
+    if (!dL_dvbar || !dL_dg || !dL_dgscale) return fail(SNN_EINVAL, "NULL argument");
+    const size_t need = backward_scratch_bytes(net);
+    if (need > kScratchBytes)
+        return fail(SNN_ERANGE, "this recording's backward needs %zu bytes of scratch, more than the %zu of "
+                                "snn_backward_noalloc (fewer loss neurons or a shorter checkpoint interval)",
+                    need, kScratchBytes);
+    char *base = static_cast<char *>(scratch_on_device(net->device));
+    if (!base) return fail(SNN_EDEVICE, "the scratch array's device address is unknown on device %d", net->device);
+    const size_t nl = (size_t)std::max<int64_t>(net->n_loss, 1), K = (size_t)net->rec_K;
+    const size_t nin = (size_t)net->n_in_max;
+    double *tape_x = reinterpret_cast<double *>(base + 256);
+    double *tape_g = tape_x + K * 4 * nl;
+    double *lg = tape_g + K * nin * nl;
+    double *lam = lg + K * nin * nl;
+    return run_backward(net, dL_dvbar, dL_dg, dL_dgscale, tape_x, tape_g, lg, lam, reinterpret_cast<uint32_t *>(base),
+                        true);
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@ SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_ESTATE, SNN_ERANGE = 0, -1, -2,
 POISSON, TRAUB_MILES, IZHIKEVICH = 0, 1, 2
 V, M, H, N = 0, 1, 2, 3
 U = 1   # recovery variable of an Izhikevich population
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SNN_NOALLOC_SCRATCH_BYTES of include/snn.h
 
 # Every symbol include/snn.h declares.
 EXPORTS = [
@@ -29,6 +30,7 @@ EXPORTS = [
     "snn_memory_bytes", "snn_get_launch", "snn_set_launch", "snn_time_steps", "snn_time_kernel", "snn_profile_steps",
     "snn_last_error", "snn_reset", "snn_weight_count", "snn_weight_offset", "snn_get_weights_device",
     "snn_set_weights_device", "snn_forward_record", "snn_backward", "snn_gscale_select", "snn_gscale_fit",
+    "snn_backward_noalloc",
 ]
 
 
@@ -122,6 +124,7 @@ def load():
         "snn_set_weights_device": (C.c_int, [vp, vp]),
         "snn_forward_record": (C.c_int, [vp, i32, i64, i32, vp]),
         "snn_backward": (C.c_int, [vp, vp, vp, vp, vp]),
+        "snn_backward_noalloc": (C.c_int, [vp, vp, vp, vp]),
         "snn_gscale_select": (C.c_int, [i64, vp, vp, vp, vp, i64, vp, vp, vp]),
         "snn_gscale_fit": (C.c_int, [i64, vp, vp, vp, vp]),
     }
@@ -342,6 +345,17 @@ class Network:
         _check(load().snn_backward(self.h, C.c_void_p(dvbar.data_ptr()), C.c_void_p(dg.data_ptr()),
                                    C.c_void_p(ds.data_ptr()), C.byref(mm) if check else None))
         return dg, ds, (mm.value if check else None)
+
+    def backward_noalloc(self, dvbar, dg, ds):
+        """snn_backward_noalloc into caller-owned tensors dg (float32
+        [weight_count]) and ds (float64 [n_inst]); the library allocates
+        nothing for it."""
+        t = self._torch
+        assert dvbar.dtype == t.float64 and dvbar.is_contiguous()
+        assert dg.dtype == t.float32 and dg.is_contiguous() and dg.numel() == self.weight_count
+        assert ds.dtype == t.float64 and ds.is_contiguous() and ds.numel() == self.n_instances
+        _check(load().snn_backward_noalloc(self.h, C.c_void_p(dvbar.data_ptr()), C.c_void_p(dg.data_ptr()),
+                                           C.c_void_p(ds.data_ptr())))
 
     # ----------------------------------------------------------------- state
     def _n(self, inst, pop):
