@@ -58,7 +58,8 @@ enum { SNN_HH_NPARAM = 7 };
 /* A population (Section 5.1: networks are built of populations of neurons).
  *  kind      SNN_POISSON: source i fires at step t iff the first output word
  *            of Philox-4x32-10 (Salmon et al., SC'11) with counter
- *            (i, t mod 2^32, t div 2^32, 0) and key (seed mod 2^32,
+ *            (i, t mod 2^32, t div 2^32, pop), pop the population's index in
+ *            its instance, and key (seed mod 2^32,
  *            seed div 2^32) is below floor(p * 2^32), p = rate_hz * dt_ms *
  *            1e-3 evaluated left to right in double precision (p >= 1:
  *            always fires).

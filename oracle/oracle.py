@@ -54,7 +54,7 @@ def lib():
             "orc_rest": (C.c_int, [vp, vp, vp, vp, vp]),
             "orc_philox4x32_10": (None, [vp, vp, vp]),
             "orc_poisson_threshold": (u64, [d, d]),
-            "orc_poisson_fires": (C.c_int, [u64, i64, i32, u64]),
+            "orc_poisson_fires": (C.c_int, [u64, i64, i32, i32, u64]),
             "orc_create": (vp, [d, C.c_int, d, u64]),
             "orc_add_pop": (C.c_int, [vp, C.c_int, C.c_int, d, d, vp]),
             "orc_add_proj": (C.c_int, [vp, C.c_int, C.c_int, i64, vp, vp, vp, d, d, C.c_int, d, d, d, d]),

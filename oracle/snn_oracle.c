@@ -169,9 +169,10 @@ void orc_philox4x32_10(const uint32_t *ctr_in, const uint32_t *key_in, uint32_t 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Source i of a Poisson population fires at step t iff the first Philox
- * word of counter (i, t_lo, t_hi, 0) under key (seed_lo, seed_hi) is below
- * floor(p * 2^32), p = rate_hz * dt_ms * 1e-3 (a Bernoulli draw per step). */
+/* Source i of Poisson population pop fires at step t iff the first Philox
+ * word of counter (i, t_lo, t_hi, pop) under key (seed_lo, seed_hi) is below
+ * floor(p * 2^32), p = rate_hz * dt_ms * 1e-3 (a Bernoulli draw per step).
+ * The population index keeps two populations of one instance independent. */
 uint64_t orc_poisson_threshold(double rate_hz, double dt_ms)
 {
     double p = rate_hz * dt_ms * 1e-3;
@@ -180,9 +181,10 @@ uint64_t orc_poisson_threshold(double rate_hz, double dt_ms)
     return (uint64_t)floor(p * 4294967296.0);
 }
 
-int orc_poisson_fires(uint64_t seed, int64_t t, int32_t i, uint64_t thresh)
+int orc_poisson_fires(uint64_t seed, int64_t t, int32_t i, int32_t pop, uint64_t thresh)
 {
-    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), 0u};
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32),
+                       (uint32_t)pop};
     uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
@@ -456,7 +458,7 @@ void orc_phase_neurons(orc_net *net)
         opop *P = &net->pops[p];
         if (P->kind != ORC_POISSON) continue;
         for (int i = 0; i < P->n; ++i)
-            P->spk_now[i] = (unsigned char)orc_poisson_fires(net->seed, t, i, P->thresh);
+            P->spk_now[i] = (unsigned char)orc_poisson_fires(net->seed, t, i, p, P->thresh);
     }
     if (net->rp_off) {
         for (int p = 0; p < net->n_pops; ++p) {

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         } else {
             if (active) {
                 const uint32_t w = philox_first_word((uint32_t)j, (uint32_t)((uint64_t)t & 0xffffffffu),
-                                                     (uint32_t)((uint64_t)t >> 32), 0u,
+                                                     (uint32_t)((uint64_t)t >> 32), (uint32_t)S.pop,
                                                      (uint32_t)(S.seed & 0xffffffffu), (uint32_t)(S.seed >> 32));
                 spike = (uint64_t)w < S.thresh;
             }

@@ -32,11 +32,12 @@ def say(*a):
 
 
 def test_poisson_raster_bitwise(snn):
-    say("case: poisson raster, 3 populations, 300 steps")
+    say("case: poisson raster, 4 populations, 300 steps")
     inst = dict(g_scale=1.0, seed=(7 << 33) + 5,
                 pops=[dict(name="A", kind="poisson", n=1000, rate_hz=300.0, i_ext=0.0),
                       dict(name="B", kind="poisson", n=70, rate_hz=5000.0, i_ext=0.0),
-                      dict(name="C", kind="poisson", n=3, rate_hz=20000.0, i_ext=0.0)], projs=[])
+                      dict(name="C", kind="poisson", n=3, rate_hz=20000.0, i_ext=0.0),
+                      dict(name="D", kind="poisson", n=1000, rate_hz=300.0, i_ext=0.0)], projs=[])
     spec = dict(dt=0.1, substeps=3, instances=[inst])
     T = 300
     net = snn.Network(spec, raster_steps=T)
@@ -44,12 +45,14 @@ def test_poisson_raster_bitwise(snn):
     orc = O.OracleNet(inst, log_events=True)
     orc.step(T)
     t, p, i = orc.events()
-    for pop in range(3):
+    for pop in range(4):
         ras = net.raster(0, pop, 0, T)
         for k in range(T):
             expect = np.sort(i[(t == k) & (p == pop)])
             assert np.array_equal(ras[k], expect), (pop, k)
         assert np.array_equal(net.spikes(0, pop), orc.counts(pop))
+    # two populations of one instance at the same rate draw different streams
+    assert not np.array_equal(net.spikes(0, 0), net.spikes(0, 3))
     net.close()
 
 

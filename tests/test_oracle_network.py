@@ -40,6 +40,32 @@ def test_poisson_threshold(orc):
     assert L.orc_poisson_threshold(1e6, 0.1) == 2 ** 32
 
 
+def test_poisson_draw_is_the_documented_philox_counter(orc):
+    """Source i of Poisson population pop fires at step t iff the first word
+    of Philox-4x32-10 at counter (i, t mod 2^32, t div 2^32, pop), under the
+    instance seed as key, is below floor(p 2^32): checked draw by draw against
+    the known-answer-pinned generator for two populations of one instance at
+    the same rate, whose rasters must then differ."""
+    n, T, rate = 64, 40, 2000.0
+    seed = (5 << 32) + 77
+    inst = dict(g_scale=1.0, seed=seed, pops=[dict(name="P", kind="poisson", n=n, rate_hz=rate, i_ext=0.0),
+                                               dict(name="Q", kind="poisson", n=n, rate_hz=rate, i_ext=0.0)],
+                projs=[])
+    net = orc.OracleNet(inst, log_events=True)
+    net.step(T)
+    t_ev, p_ev, i_ev = net.events()
+    thresh = orc.lib().orc_poisson_threshold(rate, 0.1)
+    key = [seed & 0xffffffff, seed >> 32]
+    for pop in (0, 1):
+        for t in range(T):
+            fired = set(i_ev[(t_ev == t) & (p_ev == pop)].tolist())
+            expect = {i for i in range(n) if orc.philox([i, t, 0, pop], key)[0] < thresh}
+            assert fired == expect, (pop, t)
+    r0 = [(t, i) for t, p, i in zip(t_ev, p_ev, i_ev) if p == 0]
+    r1 = [(t, i) for t, p, i in zip(t_ev, p_ev, i_ev) if p == 1]
+    assert r0 != r1
+
+
 def test_poisson_binomial_statistics(orc):
     """Each source's count over T steps is Binomial(T, p): the pooled mean and
     variance match T p and T p (1-p); lag-1 correlation of the population
