@@ -249,6 +249,9 @@ class Network:
         self.h = C.c_void_p()
         _check(L.snn_create(C.byref(cfg), C.byref(self.h)))
         self.n_instances = len(spec["instances"])
+        # bumped by every call that changes what a backward pass would read
+        # (the recording, the weights, g_scale): an autograd tape remembers it
+        self.tape_generation = 0
 
     # ---------------------------------------------------------------- life
     def close(self):
@@ -320,6 +323,7 @@ class Network:
     def set_weights_device(self, src):
         src = src.contiguous()
         assert src.dtype == self._torch.float32 and src.is_cuda and src.numel() == self.weight_count
+        self.tape_generation += 1
         _check(load().snn_set_weights_device(self.h, C.c_void_p(src.data_ptr())))
 
     def loss_size(self, pop):
@@ -331,6 +335,7 @@ class Network:
         t = self._torch
         if vbar is None:
             vbar = t.empty(self.loss_size(pop), dtype=t.float64, device=self.device)
+        self.tape_generation += 1
         _check(load().snn_forward_record(self.h, int(pop), int(n_steps), int(ckpt_every), C.c_void_p(vbar.data_ptr())))
         return vbar
 
@@ -429,6 +434,7 @@ class Network:
     def set_gscale(self, per_instance):
         a = np.ascontiguousarray(per_instance, np.float32)
         assert a.size == self.n_instances
+        self.tape_generation += 1
         _check(load().snn_set_gscale(self.h, _p(a)))
 
     def weights(self, inst, proj):
