@@ -732,19 +732,35 @@ template <bool kLds, class F>
 __device__ __forceinline__ long long pull_entries(const int2 *rw, int32_t depth, const uint64_t *wb, double s,
                                                   F &&after_first_loads)
 {
+    // Two batches in flight: each iteration issues the spike-word lookups of
+    // the batch it holds, then the entry loads of the next batch, then
+    // consumes the lookups, so one batch's entries travel while the previous
+    // one is added (the lookups of LDS words wait on their own counter;
+    // global ones are older than the next batch's loads, so they complete
+    // first).
     long long sum = 0;
-    for (int32_t k = 0; k < depth; k += kPullBatch) {
-        int2 e[kPullBatch];
+    int2 e[kPullBatch];
 #pragma unroll
-        for (int v = 0; v < kPullBatch; ++v) e[v] = rw[(int64_t)min(k + v, depth - 1) * kWave];
-        if (k == 0) after_first_loads();
+    for (int v = 0; v < kPullBatch; ++v) e[v] = rw[(int64_t)min(v, depth - 1) * kWave];
+    after_first_loads();
+    for (int32_t k = 0; k < depth; k += kPullBatch) {
         uint64_t bw[kPullBatch];
 #pragma unroll
         for (int v = 0; v < kPullBatch; ++v) bw[v] = wb[e[v].x >> 6];
+        const int32_t kn = k + kPullBatch;
+        int2 en[kPullBatch];
+        if (kn < depth) {
+#pragma unroll
+            for (int v = 0; v < kPullBatch; ++v) en[v] = rw[(int64_t)min(kn + v, depth - 1) * kWave];
+        }
 #pragma unroll
         for (int v = 0; v < kPullBatch; ++v)
             if (k + v < depth && ((bw[v] >> (e[v].x & (kWave - 1))) & 1ull))
                 sum += fix_increment(s, __int_as_float(e[v].y));
+        if (kn < depth) {
+#pragma unroll
+            for (int v = 0; v < kPullBatch; ++v) e[v] = en[v];
+        }
     }
     return sum;
 }
