@@ -84,13 +84,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE passes, each scaled
-    by the same counter's reading for a plain copy of known size), or None
-    when there is none or the kernel sources changed since it was taken."""
+def profiled_values(kernel, workload, what):
+    """The key: value lines of the committed counter summary
+    profiles/<kernel>_<workload>_<what>.txt, or None when there is none or the
+    kernel sources changed since its counters were taken."""
     name = f"workload{workload}" if isinstance(workload, int) else str(workload)
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{what}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -100,6 +99,17 @@ def profiled_traffic(kernel, workload):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return vals
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE passes, each scaled
+    by the same counter's reading for a plain copy of known size), or None
+    when there is none or the kernel sources changed since it was taken."""
+    vals = profiled_values(kernel, workload, "traffic")
+    if vals is None:
         return None
     try:
         return int(float(vals["traffic_bytes_per_launch"]))
@@ -280,6 +290,14 @@ def live_roofline(net, spec, n_hh, deg, profile_steps, workload):
         roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(hbm, 3), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 6)}
     roof["traffic"] = profiled_traffic("k_" + dom, workload) if workload is not None else None
+    if roof["bound"] == "alu" and workload is not None:
+        # the issue rate the counters measured (all instructions the kernel
+        # runs, not only the method's arithmetic), from the committed summary
+        v = profiled_values("k_" + dom, workload, "valu")
+        if v is not None:
+            roof["valu_issue_counted"] = {"frac": float(v["valu_issue_frac"]),
+                                          "instructions_per_wave": float(v["valu_instructions_per_wave"]),
+                                          "source": f"profiles/k_{dom}_workload{workload}_valu.txt"}
     roof["hbm"] = {"algorithmic_bytes_per_launch": per(kern[dom]["bytes"]),
                    "achieved_GBs": round(hbm, 3), "frac": round(hbm / HBM_PEAK_GBS, 6),
                    "stored_bytes_per_launch": per(kern[dom]["repr"])}
