@@ -326,8 +326,9 @@ def calibrate_bench(args):
     DN = 100, with 20 and 40 LHI, the PN->KC and the PN->LHI scale each swept.
     izh: the 4:1 Izhikevich network of Section 5.1 (800 excitatory, 200
     inhibitory neurons, 1000 Poisson inputs at 20 Hz), nConn = 100..1000
-    (step 50) recurrent connections per neuron x 25 scales of the recurrent
-    weights in [0.03, 10], criterion the excitatory avgSpike."""
+    (step 50) recurrent connections per neuron x 26 scales of the recurrent
+    weights, 10^-1.5 .. 10 in tenths of a decade, criterion the excitatory
+    avgSpike."""
     import numpy as np
     import torch
     from paper_1412_0595_amd import calibrate as cal
@@ -340,11 +341,11 @@ def calibrate_bench(args):
         workload = ("calibration sweep: nConn 100..1000 step 50 x 25 gScale in [0.1, 10]; "
                     "A = nConn/0.2 Poisson at 20 Hz, B = 1000 HH, C = 100 HH, p = 0.2/0.5")
     elif args.model == "izh":
-        gi = 10.0 ** np.linspace(np.log10(0.03), 1.0, 25)
+        gi = 10.0 ** (np.arange(-15, 11) / 10.0)     # 10^-1.5 .. 10 in tenths of a decade, 1 included
         sweeps = [("Izhikevich 4:1 network: recurrent scale, E spiking",
                    netgen.izhikevich_calibration_config(np.arange(100.0, 1001.0, 50.0), gi, steps=args.steps))]
-        workload = ("Izhikevich calibration sweep (Section 5.1): nConn 100..1000 step 50 x 25 recurrent scales in "
-                    "[0.03, 10]; 800 E + 200 I Izhikevich neurons, 1000 Poisson inputs at 20 Hz (p 0.1)")
+        workload = ("Izhikevich calibration sweep (Section 5.1): nConn 100..1000 step 50 x 26 recurrent scales "
+                    "10^-1.5..10^1; 800 E + 200 I Izhikevich neurons, 1000 Poisson inputs at 20 Hz (p 0.1)")
     else:
         n_pn = np.arange(100, 1001, 50)
         sweeps = [(f"LHI variant, {nl} LHI: PN->{sw.upper()} scale, {sw.upper()} spiking",

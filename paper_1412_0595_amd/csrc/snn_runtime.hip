@@ -1895,7 +1895,7 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
     if (net->substeps > kAdjMaxSub) return fail(SNN_EINVAL, "the adjoint supports at most %d substeps", kAdjMaxSub);
     std::vector<int32_t> lseg(net->n_inst);
     std::vector<int64_t> lbase(net->n_inst + 1, 0);
-    int n_in_max = 1, max_n = 1;
+    int n_in_max = 1;
     for (int b = 0; b < net->n_inst; ++b) {
         if (pop < 0 || pop >= (int32_t)net->seg_of[b].size()) return fail(SNN_EINVAL, "instance %d has no population %d", b, pop);
         const Seg &S = net->segs[net->seg_of[b][pop]];
@@ -1905,7 +1905,6 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
         lseg[b] = net->seg_of[b][pop];
         lbase[b + 1] = lbase[b] + S.n;
         n_in_max = std::max(n_in_max, S.n_in);
-        max_n = std::max(max_n, S.n);
     }
     const int64_t T = n_steps, K = std::min<int64_t>(ckpt_every, T);
     const int64_t nseg = (T + K - 1) / K;
@@ -1948,7 +1947,11 @@ int snn_forward_record(snn_net *net, int32_t pop, int64_t n_steps, int32_t ckpt_
     if ((rc = h2d(net, net->d_gitems, items.data(), sizeof(int4) * items.size()))) return rc;
     net->n_loss = n_loss;
     net->n_in_max = n_in_max;
-    net->loss_block = (int)align_up(max_n, kWave);
+    // the recompute's block per instance: all of its wavefronts walk a step's
+    // raster words and rows (the step's longest phase), then the first n
+    // threads update the loss neurons; a full block of kAdjMaxLoss threads
+    // spreads that walk over 16 wavefronts instead of the neurons' few
+    net->loss_block = kAdjMaxLoss;
     net->n_gitems = (int64_t)items.size();
     net->rec_pop = pop;
     net->rec_T = T;
