@@ -71,16 +71,20 @@ WORKLOADS = {
 }
 
 
+STEP_KERNEL_SOURCES = ("snn_device.h", "snn_internal.h", "snn_kernels.hip")
+
+
 def kernel_sources_sha256():
-    """Hash of the HIP sources the kernels are built from."""
+    """Hash of the device sources the step kernels (neuron update,
+    propagation, potentiation) are compiled from; the host runtime and the
+    adjoint kernels live in other files."""
     import hashlib
     d = os.path.join(ROOT, "paper_1412_0595_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in STEP_KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
