@@ -90,6 +90,7 @@ struct HHRates {
     double am, bm, ah, bh, an, bn;
 };
 
+// The rates from five device-library exponentials (any V, NaN included).
 // am, bm and an are c x / (e^x - 1) (limit c at x = 0; expm1 keeps the
 // quotient accurate near 0).  bm and bh share one exponential: with
 // x2 = (v + 25) / 5 and E = e^x2 - 1, e^(-x2) = 1 / (1 + E), so
@@ -101,7 +102,7 @@ struct HHRates {
 // the lane divides four times instead (the choice is the lane's own, so a
 // neuron's rates do not depend on the other neurons of its wavefront).  A
 // NaN voltage gives NaN rates.
-__device__ __forceinline__ HHRates hh_rates(double v)
+__device__ __noinline__ HHRates hh_rates_lib(double v)
 {
     HHRates r;
     const double x1 = (-52.0 - v) * 0.25, x2 = (v + 25.0) * 0.2, x3 = (-50.0 - v) * 0.2;
@@ -130,6 +131,70 @@ __device__ __forceinline__ HHRates hh_rates(double v)
     r.bh = e2 < 1e300 ? 4.0 * (1.0 + e2) * i4 : 4.0;
     r.ah = 0.128 * exp((-48.0 - v) * (1.0 / 18.0));
     r.bn = 0.5 * exp((-55.0 - v) * 0.025);
+    return r;
+}
+
+// x / (e^x - 1) near x = 0 by its series 1 - x/2 + x^2/12 - x^4/720 (the
+// next term, x^6/30240, is below 5e-16 for |x| < 1/64).
+__device__ __forceinline__ double xexpm1_series(double x)
+{
+    const double x2 = x * x;
+    return 1.0 - 0.5 * x + x2 * (1.0 / 12.0) - x2 * x2 * (1.0 / 720.0);
+}
+
+// The rates from one exponential.  The five exponents are linear in v with
+// slopes -1/4, 1/5, -1/5, -1/18 and -1/40, all integer multiples of 1/360, so
+// with u = e^(-v/360):
+//   e^((-52 - v)/4)  = e^-13 u^90      e^(-(v + 25)/5) = e^-5 u^72
+//   e^((-50 - v)/5)  = e^-10 u^72      e^((-48 - v)/18) = e^(-8/3) u^20
+//   e^((-55 - v)/40) = e^(-11/8) u^9
+// u's powers come from repeated products (relative error about 90 times
+// u's, near 1e-14).  am = 1.28 x1/(e^x1 - 1), an = 0.16 x3/(e^x3 - 1), and
+// bm = 1.4 x2/(e^x2 - 1) = 1.4 x2 e^-x2/(1 - e^-x2); where |x| < 1/64 the
+// quotient is its series instead (the difference would cancel).  bh =
+// 4/(e^-x2 + 1).  The four denominators share one division as in
+// hh_rates_lib.  For |v| <= 1000 mV the powers stay far from overflow;
+// beyond (a neuron running away, or NaN) the library path is used.
+__device__ __forceinline__ HHRates hh_rates(double v)
+{
+    if (!(fabs(v) <= 1000.0)) return hh_rates_lib(v);
+    constexpr double kE13 = 0x1.2f6053b981d98p-19;   // e^-13
+    constexpr double kEm5 = 0x1.b993fe00d5376p-8;    // e^-5
+    constexpr double kE10 = 0x1.7cd79b5647c9bp-15;   // e^-10
+    constexpr double kAh = 0x1.236f49a3adb34p-7;     // 0.128 e^(-8/3)
+    constexpr double kBn = 0x1.02e8620c7602cp-3;     // 0.5 e^(-11/8)
+    constexpr double kSmall = 1.0 / 64.0;
+    HHRates r;
+    const double u = exp(v * (-1.0 / 360.0));
+    const double u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
+    const double u9 = u8 * u, u18 = u16 * u2, u20 = u16 * u4, u36 = u18 * u18, u72 = u36 * u36, u90 = u72 * u18;
+    const double x1 = (-52.0 - v) * 0.25, x2 = (v + 25.0) * 0.2, x3 = (-50.0 - v) * 0.2;
+    const double e1 = kE13 * u90, em2 = kEm5 * u72, e3 = kE10 * u72;
+    const bool s1 = fabs(x1) < kSmall, s2 = fabs(x2) < kSmall, s3 = fabs(x3) < kSmall;
+    const double f1 = s1 ? 1.0 : e1 - 1.0, f2 = s2 ? 1.0 : 1.0 - em2, f3 = s3 ? 1.0 : e3 - 1.0;
+    const double f4 = em2 + 1.0;
+    const double p12 = f1 * f2, p123 = p12 * f3, prod = p123 * f4;
+    double i1, i2, i3, i4;
+    if (isfinite(prod) && prod != 0.0) {
+        const double q = 1.0 / prod;
+        i4 = q * p123;
+        const double q123 = q * f4;
+        i3 = q123 * p12;
+        const double q12 = q123 * f3;
+        i2 = q12 * f1;
+        i1 = q12 * f2;
+    } else {
+        i1 = 1.0 / f1;
+        i2 = 1.0 / f2;
+        i3 = 1.0 / f3;
+        i4 = 1.0 / f4;
+    }
+    r.am = 1.28 * (s1 ? xexpm1_series(x1) : x1 * i1);
+    r.bm = 1.4 * (s2 ? xexpm1_series(x2) : x2 * em2 * i2);
+    r.an = 0.16 * (s3 ? xexpm1_series(x3) : x3 * i3);
+    r.bh = 4.0 * i4;
+    r.ah = kAh * u20;
+    r.bn = kBn * u9;
     return r;
 }
 
