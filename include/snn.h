@@ -192,9 +192,13 @@ void snn_default_hh(double *p);
  * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL.
  * Device memory beyond the state: the CRS arrays (8 B per synapse plus row
  * starts); for every non-plastic projection a column-ordered copy used by
- * tile mode's pull delivery (12 B per synapse plus padding of its 64-column
- * slices to their longest column), built only while the weight pool has
- * fewer than 2^31 synapses; for plastic projections the column view of
+ * tile mode's pull delivery (each entry a one-byte row delta, its fp32
+ * weight and its 4-byte weight-pool position: 9 B per synapse, plus
+ * weight-0 entries bridging row gaps above 255, padding of its 64-column
+ * slices to their longest column and 4 B per column and pull unit), built
+ * only while the weight pool has fewer than 2^31 synapses and for
+ * projections whose bridging entries stay within a quarter of their
+ * synapses (the others are always pushed); for plastic projections the column view of
  * potentiation (8 B per synapse); the tile-mode partial tiles (8 B per post
  * tile column and pre spike word); the work queues. */
 int snn_create(const snn_config *cfg, snn_net **out);

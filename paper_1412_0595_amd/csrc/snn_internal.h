@@ -56,26 +56,36 @@ enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
 constexpr int kFusedCap = 512;     // chunks a block lists in LDS per round
 // Tile mode, dense activity: when at least kPullNum/kPullDen of a population
 // spiked, its non-plastic projections are delivered by pulling instead.  Each
-// such projection keeps a column-ordered copy in sliced-ELL form: its columns
-// sorted by length, 64 to a slice, lane l of a slice holding the l-th
-// column's k-th entry (pre index, weight) at slice base + 64 k + l, short
-// columns padded with (row 0, weight 0).  A pull unit is up to kPullDepth
-// consecutive k of one slice: one wavefront, one lane per column, summing
-// the weights of spiking rows.  The unit of a slice of one depth chunk adds
-// its sums into G itself, one plain read-modify-write per column (no other
-// work touches a pulled projection's conductances in that step); the units
-// of deeper slices store one partial sum per column (a coalesced store) and
-// the reduction adds them into G in groups of up to 64 units per wavefront:
-// a plain read-modify-write per column when one group covers the slice, else
-// one atomic per group and column.
+// such projection keeps a column-ordered copy in sliced-ELL form with
+// compressed row indices: a column's entries in ascending row order, each a
+// one-byte row delta (to the previous entry's row; the first entry's delta is
+// 0) and its fp32 weight, a gap of more than kPullMaxDelta rows bridged by
+// weight-0 entries of delta kPullMaxDelta.  Columns are sorted by encoded
+// length, 64 to a slice; lane l of a slice holds the l-th column.  Entries go
+// in packets of four per lane: packet p of a slice is one float4 of weights
+// at (slice packet base + p) * 64 + l and one word of four byte deltas at the
+// same index; short columns are padded with (delta 0, weight 0) to the
+// slice's depth, a multiple of 4.  A pull unit is up to kPullDepth
+// consecutive entries of one slice: one wavefront, one lane per column,
+// starting from its lane's row before the unit's first entry (a table of 64
+// rows per unit), summing the weights of spiking rows.  5 bytes per entry
+// instead of the CSR's 8.  The unit of a slice of one depth chunk adds its
+// sums into G itself, one plain read-modify-write per column (no other work
+// touches a pulled projection's conductances in that step); the units of
+// deeper slices store one partial sum per column (a coalesced store) and the
+// reduction adds them into G in groups of up to 64 units per wavefront: a
+// plain read-modify-write per column when one group covers the slice, else
+// one atomic per group and column.  A projection whose bridging entries would
+// exceed a quarter of its synapses gets no copy (it is always pushed).
 constexpr int kPullNum = 7, kPullDen = 8;
 constexpr int kPullDepth = 64;
+constexpr int kPullMaxDelta = 255;
 
 struct PullUnit {
-    int64_t e0;         // copy offset of the unit's entry (k0, lane 0)
+    int64_t pk0;        // the unit's first packet (global packet index; lane 0)
     int64_t g_base;     // conductance pool offset of the projection
     int32_t col_off;    // offset of the slice's 64 post neurons in the column table
-    int32_t depth;      // entries per lane (<= kPullDepth)
+    int32_t npk;        // packets (4 entries each) per lane, <= kPullDepth / 4
     int32_t pre_seg;    // pre population, and of it:
     int32_t inst;       //   instance (g_scale),
     int32_t wbase;      //   first spike word (global word index),
@@ -256,7 +266,9 @@ struct PropArgs {
     const PullSlice *pull_slices;
     int64_t n_pull_slices;
     const int32_t *pull_col; // [slice][64] post neuron of each lane, -1 for padding
-    const int2 *pull_rw;     // sliced-ELL entries: (pre index, weight bits)
+    const float4 *pull_w;    // sliced-ELL weights, [packet][64 lanes] x 4 entries
+    const uint32_t *pull_d;  // their row deltas, [packet][64 lanes], one byte per entry
+    const int32_t *pull_r0;  // [unit][64] lane's row before the unit's first entry
 };
 
 struct LtpArgs {
@@ -327,7 +339,7 @@ hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_
                             hipEvent_t e1 = nullptr);
 hipError_t launch_potentiate(const LtpArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);
-hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n, hipStream_t s);
+hipError_t launch_gather_weights(const float *w, const int32_t *perm, float *out, int64_t n, hipStream_t s);
 // Zero `bytes` (a multiple of 4) at p with a kernel.
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_check_weights(const float *w, const Proj *projs, int32_t n_projs, int64_t max_nnz, uint32_t *flag,

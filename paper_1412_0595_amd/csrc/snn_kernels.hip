@@ -99,12 +99,15 @@ __device__ __forceinline__ void fused_delivery(const NeuronArgs &a, int64_t t, u
 // ---------------------------------------------------------------------------
 // Neuron update + spike compaction
 // ---------------------------------------------------------------------------
+// One instantiation per delivery mode (uniform over a launch), so that each
+// carries only its own mode's emission code and kernel arguments.
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 {
     __shared__ uint32_t s_woff[16][2];
     __shared__ uint32_t s_base[2];
     __shared__ uint32_t s_tot, s_pop;            // fused: chunks of the block, next to take
-    __shared__ int4 s_fl[kFusedCap];             // fused: (projection, k0, k1, -) per chunk
+    __shared__ int4 s_fl[MODE == kModeFused ? kFusedCap : 1];   // fused: (projection, k0, k1, -) per chunk
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform: scalar loads below
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             for (int q = 0; q < kMaxIn; ++q)
                 if (q < s_nin) {
                     g[q] = a.G[s_inG[q] + jj];
-                    if (a.mode == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
+                    if constexpr (MODE == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
                 }
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 for (int q = 0; q < kMaxIn; ++q)
                     if (q < s_nin) {
                         a.G[s_inG[q] + j] = fix_decay(g[q], S.in_decay[q]);
-                        if (a.mode == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
+                        if constexpr (MODE == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
                     }
                 spike = (v0 < 0.0) && (v >= 0.0);
                 pair_split(v, a.vh[gid], a.vl[gid]);
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             for (int q = 0; q < kMaxIn; ++q)
                 if (q < s_nin) {
                     g[q] = a.G[s_inG[q] + jj];
-                    if (a.mode == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
+                    if constexpr (MODE == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
                 }
             const double iin = syn_current(S, g, v0);
             for (int k = 0; k < a.substeps; ++k) izh_substep((double)pr.x, (double)pr.y, a.hs, iin, v, u);
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 for (int q = 0; q < kMaxIn; ++q)
                     if (q < s_nin) {
                         a.G[s_inG[q] + j] = fix_decay(g[q], S.in_decay[q]);
-                        if (a.mode == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
+                        if constexpr (MODE == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
                     }
                 // threshold on the step's end value, then the reset
                 spike = v >= kIzhPeak;
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             for (int q = 0; q < kMaxTr; ++q)
                 if (q < s_ntr) a.trace[S.tr_base[q] + j] = trv[q] * S.tr_decay[q] + (spike ? 1.0f : 0.0f);
         }
-        if (ball != 0 && a.mode == kModeTiles) {
+        if (MODE == kModeTiles && ball != 0) {
             // the word is active: record it, and queue one propagation item
             // per (outgoing projection, post tile) for the next step
             if (lane == 0) {
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         if (ball != 0 && spike) {
             a.counts[gid] = cnt + 1;
             const uint32_t ch = (uint32_t)a.chunk;
-            if (a.mode != kModeTiles) {
+            if constexpr (MODE != kModeTiles) {
                 // one propagation item (fused: one chunk) per chunk of each
                 // outgoing row
                 if (s_nout > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             sl += tl;
         }
         s_tot = sq;
-        if (a.mode != kModeFused) {
+        if constexpr (MODE != kModeFused) {
             s_base[0] = sq ? atomicAdd(&a.st->qcnt[cur], sq) : 0u;
             s_base[1] = sl ? atomicAdd(&a.st->lcnt[cur], sl) : 0u;
             if (sq && (int64_t)s_base[0] + sq > a.qcap) atomicOr(&a.st->overflow, 1u);
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     }
     __syncthreads();
 
-    if (a.mode == kModeRows && nq) {
+    if (MODE == kModeRows && nq) {
         const int32_t ch = a.chunk;
         int64_t pos = (int64_t)s_base[0] + s_woff[wid][0] + (iq - nq);
         Item *qd = a.queue + (int64_t)cur * a.qcap;
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         }
     }
     // tile mode: lane 0 counted the wave's items, all lanes write
-    const uint32_t wave_nq = a.mode == kModeTiles ? __shfl(nq, 0, kWave) : 0u;
+    const uint32_t wave_nq = MODE == kModeTiles ? __shfl(nq, 0, kWave) : 0u;
     if (wave_nq) {
         const int64_t base = (int64_t)s_base[0] + s_woff[wid][0];
         const int32_t word = (int32_t)(gw - s_b / kWave);
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 if (pos < a.lcap) ld[pos] = Item{S.ltp_proj[o], j, k, min(k + ch, k1), 0, 0};
         }
     }
-    if (a.mode == kModeFused) fused_delivery(a, t, s_woff, s_tot, s_pop, s_fl, sidx, j, nq, iq, wid, lane,
+    if constexpr (MODE == kModeFused) fused_delivery(a, t, s_woff, s_tot, s_pop, s_fl, sidx, j, nq, iq, wid, lane,
                                              ra0, ra1, rb0, rb1);
 }
 
@@ -704,62 +707,95 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 constexpr int kSparseRatio = 6;   // atomics when events * kSparseRatio < tile width
 
 // Pull units.  A unit holds, for 64 post neurons (one per lane), up to
-// kPullDepth entries (pre index and weight, 8 bytes) of each one's column;
-// entries are loaded kPullBatch deep at a time (coalesced: 64 lanes read 512
-// contiguous bytes per depth), then the pre spike word of each entry's row
-// is looked up, from LDS when the pre population's words fit the wavefront's
-// tile, else from global memory.  Each lane adds the fixed-point increments
-// of its spiking rows and stores the sum as the unit's partial for its post
-// neuron, which the reduction adds into G (the only unit of a slice adds
-// them into G itself).  Padding entries carry weight 0, so they add nothing.  Integer sums: the result equals that of pushing the same
-// spikes.  A wavefront works through its units as a pipeline: while one
-// unit's first entries are in flight, the next unit's record and (for a
-// population of at most 64 words) its spike words are loaded.
-constexpr int kPullBatch = 16;
+// kPullDepth entries of each one's column, in packets of four: a float4 of
+// weights and a word of four one-byte row deltas per lane (64 lanes read
+// 1 KiB and 256 contiguous bytes per packet).  A lane starts from its row
+// before the unit's first entry and adds each delta in turn; then the pre
+// spike word of each entry's row is looked up, from LDS when the pre
+// population's words fit the wavefront's tile, else from global memory.
+// Each lane adds the fixed-point increments of its spiking rows and stores
+// the sum as the unit's partial for its post neuron, which the reduction
+// adds into G (the only unit of a slice adds them into G itself).  Padding
+// and bridging entries carry weight 0, so they add nothing.  Integer sums:
+// the result equals that of pushing the same spikes.  A wavefront works
+// through its units as a pipeline: while one unit's first entries are in
+// flight, the next unit's record and (for a population of at most 64 words)
+// its spike words are loaded.
+constexpr int kPullBatch = 4;   // packets (16 entries) per batch of loads
 
 struct PullHdr {
-    int64_t e0, g_base;
-    int32_t col_off, depth, pre_seg, inst, wbase, nwords, direct, ncols;
+    int64_t pk0, g_base;
+    int32_t col_off, npk, pre_seg, inst, wbase, nwords, direct, ncols;
 };
 
 __device__ __forceinline__ PullHdr pull_hdr(const PropArgs &a, int64_t u)
 {
     CPullUnit &U = ((CPullUnit *)a.pull_units)[u];
-    return PullHdr{U.e0, U.g_base, U.col_off, U.depth, U.pre_seg, U.inst, U.wbase, U.nwords, U.direct, U.ncols};
+    return PullHdr{U.pk0, U.g_base, U.col_off, U.npk, U.pre_seg, U.inst, U.wbase, U.nwords, U.direct, U.ncols};
+}
+
+// Spike bit of pre row r from the population's words (32-bit halves).
+__device__ __forceinline__ uint32_t spike_bit(const uint64_t *wb, int32_t r)
+{
+    return (reinterpret_cast<const uint32_t *>(wb)[r >> 5] >> (r & 31)) & 1u;
 }
 
 template <bool kLds, class F>
-__device__ __forceinline__ long long pull_entries(const int2 *rw, int32_t depth, const uint64_t *wb, double s,
-                                                  F &&after_first_loads)
+__device__ __forceinline__ long long pull_entries(const float4 *pw, const uint32_t *pd, int32_t npk, int32_t r,
+                                                  const uint64_t *wb, double s, F &&after_first_loads)
 {
-    // Two batches in flight: each iteration issues the spike-word lookups of
-    // the batch it holds, then the entry loads of the next batch, then
-    // consumes the lookups, so one batch's entries travel while the previous
-    // one is added (the lookups of LDS words wait on their own counter;
-    // global ones are older than the next batch's loads, so they complete
-    // first).
+    // Two batches in flight: each iteration decodes the rows of the batch it
+    // holds and issues their spike-bit lookups, then the loads of the next
+    // batch, then consumes the lookups, so one batch's packets travel while
+    // the previous one is added.  Packets past npk (a unit shorter than a
+    // batch) repeat the last one; their rows and weights are not used.
     long long sum = 0;
-    int2 e[kPullBatch];
+    float4 w[kPullBatch];
+    uint32_t d[kPullBatch];
 #pragma unroll
-    for (int v = 0; v < kPullBatch; ++v) e[v] = rw[(int64_t)min(v, depth - 1) * kWave];
+    for (int v = 0; v < kPullBatch; ++v) {
+        const int64_t i = (int64_t)min(v, npk - 1) * kWave;
+        w[v] = pw[i];
+        d[v] = pd[i];
+    }
     after_first_loads();
-    for (int32_t k = 0; k < depth; k += kPullBatch) {
-        uint64_t bw[kPullBatch];
+    for (int32_t p = 0; p < npk; p += kPullBatch) {
+        uint32_t bit[4 * kPullBatch];
 #pragma unroll
-        for (int v = 0; v < kPullBatch; ++v) bw[v] = wb[e[v].x >> 6];
-        const int32_t kn = k + kPullBatch;
-        int2 en[kPullBatch];
-        if (kn < depth) {
+        for (int v = 0; v < kPullBatch; ++v) {
+            const uint32_t dv = p + v < npk ? d[v] : 0u;
 #pragma unroll
-            for (int v = 0; v < kPullBatch; ++v) en[v] = rw[(int64_t)min(kn + v, depth - 1) * kWave];
+            for (int j = 0; j < 4; ++j) {
+                r += (int32_t)((dv >> (8 * j)) & 0xffu);
+                bit[4 * v + j] = spike_bit(wb, r);
+            }
+        }
+        const int32_t pn = p + kPullBatch;
+        float4 wn[kPullBatch];
+        uint32_t dn[kPullBatch];
+        if (pn < npk) {
+#pragma unroll
+            for (int v = 0; v < kPullBatch; ++v) {
+                const int64_t i = (int64_t)min(pn + v, npk - 1) * kWave;
+                wn[v] = pw[i];
+                dn[v] = pd[i];
+            }
         }
 #pragma unroll
-        for (int v = 0; v < kPullBatch; ++v)
-            if (k + v < depth && ((bw[v] >> (e[v].x & (kWave - 1))) & 1ull))
-                sum += fix_increment(s, __int_as_float(e[v].y));
-        if (kn < depth) {
+        for (int v = 0; v < kPullBatch; ++v) {
+            if (p + v < npk) {
+                const float wv[4] = {w[v].x, w[v].y, w[v].z, w[v].w};
 #pragma unroll
-            for (int v = 0; v < kPullBatch; ++v) e[v] = en[v];
+                for (int j = 0; j < 4; ++j)
+                    if (bit[4 * v + j]) sum += fix_increment(s, wv[j]);
+            }
+        }
+        if (pn < npk) {
+#pragma unroll
+            for (int v = 0; v < kPullBatch; ++v) {
+                w[v] = wn[v];
+                d[v] = dn[v];
+            }
         }
     }
     return sum;
@@ -802,9 +838,12 @@ __device__ __forceinline__ void pull_phase(const PropArgs &a, int64_t g, int64_t
             const double s = (double)a.gscale[h.inst] * kFixOne;
             // lanes past a partial slice's columns re-read lane 0's entries
             // (same cache lines: no padding traffic); their sums are dropped
-            const int2 *rw = a.pull_rw + h.e0 + (lane < h.ncols ? lane : 0);
-            const long long sum = h.nwords <= kTileMax ? pull_entries<true>(rw, h.depth, sb, s, prefetch)
-                                                       : pull_entries<false>(rw, h.depth, bits + h.wbase, s, prefetch);
+            const int ln = lane < h.ncols ? lane : 0;
+            const int32_t r0 = a.pull_r0[u * kWave + ln];
+            const float4 *pw = a.pull_w + h.pk0 * kWave + ln;
+            const uint32_t *pd = a.pull_d + h.pk0 * kWave + ln;
+            const long long sum = h.nwords <= kTileMax ? pull_entries<true>(pw, pd, h.npk, r0, sb, s, prefetch)
+                                                       : pull_entries<false>(pw, pd, h.npk, r0, bits + h.wbase, s, prefetch);
             if (h.direct) {
                 const int32_t col = a.pull_col[(int64_t)h.col_off + lane];
                 if (col >= 0 && sum != 0) a.G[h.g_base + col] += sum;
@@ -1017,46 +1056,59 @@ __global__ __launch_bounds__(256) void k_reduce_partials(PropArgs a)
     const int64_t t = a.st->t_neuron;             // set by the propagation just before
     const int prev = (int)((t + 1) & 1);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t u = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-         u < a.n_units; u += nw) {
-        CInt4 &U = ((CInt4 *)a.units)[u];
-        const int32_t proj = U.x, tile = U.y, col0 = U.z;
-        const uint32_t chunk = (uint32_t)U.w;
-        CProj &P = ((CProj *)a.projs)[proj];
-        if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;   // pulled: no partials
-        const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
-        if (na == 0) continue;
-        const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
-        const uint32_t ng = (na + gw - 1) / gw;
-        if (chunk >= ng) continue;
-        const uint32_t ge = min(ng, chunk + (uint32_t)kWave);
-        const int32_t tw = P.tile_w;
-        const int32_t c = col0 + lane;                  // column within the tile
-        const int32_t cg = tile * tw + c;               // post neuron
-        const bool valid = c < tw && cg < P.n_post;
-        const int64_t *pp = a.partial + P.P_base + (int64_t)tile * P.pre_words * tw + (valid ? c : col0);
-        const uint8_t *fl = a.pflag + P.F_base + (int64_t)tile * P.pre_words;
-        int64_t sum = 0;
-        for (uint32_t g = chunk; g < ge; g += 16) {
-            uint32_t f[16];
-            int64_t v[16];
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    // wavefront g takes units g, g + nw, ...: 64 at a time, one per lane, it
+    // finds those with partials to add (pre population pushed at t - 1 and a
+    // group chunk below its group count), then adds them one by one
+    for (int64_t r = 0; g + r * nw < a.n_units; r += kWave) {
+        const int64_t uc = g + (r + lane) * nw;
+        const int4 Ul = a.units[min(uc, a.n_units - 1)];
+        const Proj &Pl = a.projs[Ul.x];
+        const int64_t pb = Pl.pull_base;
+        const int32_t pseg = Pl.pre_seg, pwords = Pl.pre_words;
+        const uint32_t pulled = pb >= 0 ? a.pullf[prev * a.n_segs + pseg] : 0u;
+        const uint32_t nal = min(a.awcnt[prev * a.n_segs + pseg], (uint32_t)pwords);
+        const uint32_t gwl = max(1u, a.gwsel[prev * a.n_segs + pseg]);
+        const bool work = uc < a.n_units && pulled == 0u && nal > 0u && (uint32_t)Ul.w < (nal + gwl - 1) / gwl;
+        uint64_t m = __ballot(work);
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            CInt4 &U = ((CInt4 *)a.units)[g + (r + l) * nw];
+            const int32_t proj = U.x, tile = U.y, col0 = U.z;
+            const uint32_t chunk = (uint32_t)U.w;
+            CProj &P = ((CProj *)a.projs)[proj];
+            const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
+            const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
+            const uint32_t ng = (na + gw - 1) / gw;
+            const uint32_t ge = min(ng, chunk + (uint32_t)kWave);
+            const int32_t tw = P.tile_w;
+            const int32_t c = col0 + lane;                  // column within the tile
+            const int32_t cg = tile * tw + c;               // post neuron
+            const bool valid = c < tw && cg < P.n_post;
+            const int64_t *pp = a.partial + P.P_base + (int64_t)tile * P.pre_words * tw + (valid ? c : col0);
+            const uint8_t *fl = a.pflag + P.F_base + (int64_t)tile * P.pre_words;
+            int64_t sum = 0;
+            for (uint32_t gi = chunk; gi < ge; gi += 16) {
+                uint32_t f[16];
+                int64_t v[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t gg = min(g + (uint32_t)k, ge - 1);
-                f[k] = fl[gg];
-                v[k] = pp[(int64_t)gg * tw];
+                for (int k = 0; k < 16; ++k) {
+                    const uint32_t gg = min(gi + (uint32_t)k, ge - 1);
+                    f[k] = fl[gg];
+                    v[k] = pp[(int64_t)gg * tw];
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) sum += (gi + (uint32_t)k < ge && f[k]) ? v[k] : 0;
             }
-#pragma unroll
-            for (int k = 0; k < 16; ++k) sum += (g + (uint32_t)k < ge && f[k]) ? v[k] : 0;
+            if (valid && sum != 0) atomicAdd((unsigned long long *)(a.G + P.G_base + cg), (unsigned long long)sum);
         }
-        if (valid && sum != 0) atomicAdd((unsigned long long *)(a.G + P.G_base + cg), (unsigned long long)sum);
     }
     if (a.st->npull[prev] != 0 && a.n_pull_slices > 0) {
         // reduction groups of pulled slices: wavefront g takes groups g,
         // g + nw, ..., checks 64 at a time (one per lane) against their pre
         // populations' flags, and for each pulled group adds its units'
         // partial sums into G, one lane per post neuron
-        const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
         for (int64_t r = 0; g + r * nw < a.n_pull_slices; r += kWave) {
             const int64_t sl = g + (r + lane) * nw;
             const int32_t seg = a.pull_slices[min(sl, a.n_pull_slices - 1)].pre_seg;
@@ -1133,13 +1185,13 @@ __global__ __launch_bounds__(1024) void k_potentiate(LtpArgs a)
     }
 }
 
-// rw[i].y = bits of w[perm[i]], 0 where perm[i] < 0: refresh the weights of
-// a column-ordered copy.
-__global__ void k_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n)
+// out[i] = w[perm[i]], 0 where perm[i] < 0: refresh the weights of a
+// column-ordered copy.
+__global__ void k_gather_weights(const float *w, const int32_t *perm, float *out, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p = perm[i];
-        rw[i].y = __float_as_int(p >= 0 ? w[p] : 0.0f);
+        out[i] = p >= 0 ? w[p] : 0.0f;
     }
 }
 
@@ -1168,11 +1220,11 @@ __global__ void k_check_weights(const float *w, const Proj *projs, uint32_t *fla
     }
 }
 
-hipError_t launch_gather_weights(const float *w, const int32_t *perm, int2 *rw, int64_t n, hipStream_t s)
+hipError_t launch_gather_weights(const float *w, const int32_t *perm, float *out, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_gather_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, perm, rw, n);
+    hipLaunchKernelGGL(k_gather_weights, dim3((unsigned)blocks), dim3(256), 0, s, w, perm, out, n);
     return hipGetLastError();
 }
 
@@ -1200,7 +1252,12 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent
     const int64_t wpb = block / kWave;
     const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
-    SNN_LAUNCH(k_neuron, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
+    if (a.mode == kModeTiles)
+        SNN_LAUNCH(k_neuron<kModeTiles>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
+    else if (a.mode == kModeFused)
+        SNN_LAUNCH(k_neuron<kModeFused>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
+    else
+        SNN_LAUNCH(k_neuron<kModeRows>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
     return hipGetLastError();
 }
 

@@ -177,9 +177,11 @@ struct snn_net {
     PullSlice *d_pull_slices;
     int64_t n_pull_slices;
     int32_t *d_pull_col;     // [slice][64] post neuron of each lane (-1: padding)
-    int2 *d_pull_rw;         // sliced-ELL copies of non-plastic projections: (pre index, weight bits)
-    int32_t *d_pull_perm;    // and the weight's position in the weight pool (-1: padding)
-    int64_t pull_count;
+    float4 *d_pull_w;        // sliced-ELL copies of non-plastic projections: weights, [packet][64] x 4
+    uint32_t *d_pull_d;      // their one-byte row deltas, [packet][64]
+    int32_t *d_pull_r0;      // [unit][64] each lane's row before the unit's first entry
+    int32_t *d_pull_perm;    // each copied weight's position in the weight pool (-1: padding or bridge)
+    int64_t pull_count;      // packets
     uint32_t *pullf;     // arena: [2][n_segs]  populations delivered by pulling
     uint32_t *awcnt;     // arena: [2][n_segs]
     uint32_t *scnt;      // arena: [2][n_segs]
@@ -378,7 +380,9 @@ PropArgs prop_args(snn_net *net)
     p.pull_slices = net->d_pull_slices;
     p.n_pull_slices = net->n_pull_slices;
     p.pull_col = net->d_pull_col;
-    p.pull_rw = net->d_pull_rw;
+    p.pull_w = net->d_pull_w;
+    p.pull_d = net->d_pull_d;
+    p.pull_r0 = net->d_pull_r0;
     p.n_segs = (int32_t)net->segs.size();
     return p;
 }
@@ -842,14 +846,17 @@ int snn_create(const snn_config *cfg, snn_net **out)
     }
     if ((rc = check_range(net, colsum_bound, w_bound, net->gscale.data()))) return bail(rc);
     // sliced-ELL copies of the non-plastic projections (weight-pool positions
-    // must fit the int32 permutation): columns by decreasing length, 64 to a
-    // slice, a slice's depth split evenly into pull units of at most
-    // kPullDepth entries per column
-    std::vector<std::vector<int32_t>> pcol(net->projs.size()), pord(net->projs.size());
-    std::vector<int64_t> pull_slices;   // copy offset of each slice's entry (0, lane 0)
+    // must fit the int32 permutation), with one-byte row deltas: each column's
+    // encoded length is its entry count plus the weight-0 entries that bridge
+    // gaps of more than kPullMaxDelta rows; columns by decreasing encoded
+    // length, 64 to a slice, a slice's depth rounded up to whole packets of 4
+    // and split evenly into pull units of at most kPullDepth entries
+    std::vector<std::vector<int32_t>> pcol(net->projs.size()), pord(net->projs.size()), plen(net->projs.size());
+    std::vector<int64_t> pull_slices;   // first packet of each slice
+    std::vector<int32_t> slice_u0;      // first pull unit of each slice
     std::vector<PullSlice> pull_red;
     std::vector<PullUnit> pull_units;
-    int64_t pull_total = 0;
+    int64_t pull_total = 0;             // packets
     if (syn_total < ((int64_t)1 << 31)) {
         for (int b = 0, gq = 0; b < net->n_inst; ++b) {
             const snn_instance_desc &I = cfg->inst[b];
@@ -857,34 +864,54 @@ int snn_create(const snn_config *cfg, snn_net **out)
                 const snn_proj_desc &Q = I.projs[q];
                 Proj &P = net->projs[gq];
                 if (Q.stdp || Q.nnz == 0) continue;
-                std::vector<int32_t> &cp = pcol[gq], &ord = pord[gq];
+                std::vector<int32_t> &cp = pcol[gq], &ord = pord[gq], &len = plen[gq];
                 cp.assign(P.n_post + 1, 0);
-                for (int64_t k = 0; k < Q.nnz; ++k) cp[Q.col_idx[k] + 1]++;
-                for (int32_t j = 0; j < P.n_post; ++j) cp[j + 1] += cp[j];
+                len.assign(P.n_post, 0);
+                std::vector<int32_t> last(P.n_post, -1);
+                int64_t bridges = 0;
+                for (int32_t i = 0; i < P.n_pre; ++i)
+                    for (int32_t k = Q.row_ptr[i]; k < Q.row_ptr[i + 1]; ++k) {
+                        const int32_t c = Q.col_idx[k];
+                        cp[c + 1]++;
+                        if (last[c] >= 0) {
+                            const int32_t nb = (i - last[c] - 1) / kPullMaxDelta;
+                            len[c] += nb;
+                            bridges += nb;
+                        }
+                        last[c] = i;
+                    }
+                if (bridges * 4 > Q.nnz) {   // too sparse for one-byte deltas: always pushed
+                    cp.clear();
+                    len.clear();
+                    continue;
+                }
+                for (int32_t j = 0; j < P.n_post; ++j) {
+                    len[j] += cp[j + 1];
+                    cp[j + 1] += cp[j];
+                }
                 ord.resize(P.n_post);
                 for (int32_t j = 0; j < P.n_post; ++j) ord[j] = j;
-                std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-                    return cp[x + 1] - cp[x] > cp[y + 1] - cp[y];
-                });
+                std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return len[x] > len[y]; });
                 P.pull_base = (int64_t)pull_slices.size();
                 const Seg &pre = net->segs[P.pre_seg];
                 for (int32_t j0 = 0; j0 < P.n_post; j0 += kWave) {
-                    const int32_t maxlen = cp[ord[j0] + 1] - cp[ord[j0]];
+                    const int32_t npk = (len[ord[j0]] + 3) / 4;   // packets of the slice
                     const int64_t sl = (int64_t)pull_slices.size();
                     pull_slices.push_back(pull_total);
+                    slice_u0.push_back((int32_t)pull_units.size());
                     // depth split into equal chunks of at most kPullDepth;
                     // reduction groups of up to 64 chunks
-                    const int32_t nch = (maxlen + kPullDepth - 1) / kPullDepth;
+                    const int32_t nch = (4 * npk + kPullDepth - 1) / kPullDepth;
                     for (int32_t c0 = 0; nch > 1 && c0 < nch; c0 += kWave)
                         pull_red.push_back(PullSlice{P.G_base, (int32_t)pull_units.size() + c0, std::min(kWave, nch - c0),
                                                      (int32_t)(sl * kWave), P.pre_seg, nch > kWave ? 1 : 0, 0});
                     for (int32_t c = 0; c < nch; ++c) {
-                        const int32_t k0 = (int32_t)((int64_t)c * maxlen / nch), k1 = (int32_t)((int64_t)(c + 1) * maxlen / nch);
+                        const int32_t p0 = (int32_t)((int64_t)c * npk / nch), p1 = (int32_t)((int64_t)(c + 1) * npk / nch);
                         PullUnit U{};
-                        U.e0 = pull_total + (int64_t)k0 * kWave;
+                        U.pk0 = pull_total + p0;
                         U.g_base = P.G_base;
                         U.col_off = (int32_t)(sl * kWave);
-                        U.depth = k1 - k0;
+                        U.npk = p1 - p0;
                         U.pre_seg = P.pre_seg;
                         U.inst = P.inst;
                         U.wbase = (int32_t)(pre.base / kWave);
@@ -893,7 +920,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
                         U.ncols = std::min(kWave, P.n_post - j0);
                         pull_units.push_back(U);
                     }
-                    pull_total += (int64_t)maxlen * kWave;
+                    pull_total += npk;
                 }
                 net->segs[P.pre_seg].pullable = 1;
             }
@@ -1006,14 +1033,16 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->n_pull_slices = (int64_t)pull_red.size();
     net->d_pull_slices = (PullSlice *)dev_alloc(net, sizeof(PullSlice) * std::max<size_t>(pull_red.size(), 1));
     net->d_pull_col = (int32_t *)dev_alloc(net, 4 * (size_t)kWave * std::max<size_t>(pull_slices.size(), 1));
-    net->d_pull_rw = (int2 *)dev_alloc(net, 8 * std::max<int64_t>(pull_total, 1));
-    net->d_pull_perm = (int32_t *)dev_alloc(net, 4 * std::max<int64_t>(pull_total, 1));
+    net->d_pull_w = (float4 *)dev_alloc(net, 16 * (size_t)kWave * std::max<int64_t>(pull_total, 1));
+    net->d_pull_d = (uint32_t *)dev_alloc(net, 4 * (size_t)kWave * std::max<int64_t>(pull_total, 1));
+    net->d_pull_r0 = (int32_t *)dev_alloc(net, 4 * (size_t)kWave * std::max<size_t>(pull_units.size(), 1));
+    net->d_pull_perm = (int32_t *)dev_alloc(net, 16 * (size_t)kWave * std::max<int64_t>(pull_total, 1));
     net->d_izp = (float4 *)dev_alloc(net, sizeof(float4) * (size_t)std::max<int64_t>(izp_total, 1));
     if (!net->d_izp) return bail(fail(SNN_ENOMEM, "device allocation failed"));
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
         !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
-        !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_rw ||
-        !net->d_pull_perm)
+        !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_w ||
+        !net->d_pull_d || !net->d_pull_r0 || !net->d_pull_perm)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -1092,7 +1121,10 @@ int snn_create(const snn_config *cfg, snn_net **out)
             }
             if (P.pull_base >= 0) {
                 // sliced-ELL copy: lane l of slice j holds column ord[64 j + l],
-                // its entries in ascending row order at k = 0, 1, ...
+                // its entries in ascending row order, each the row's delta to
+                // the previous entry's row (0 for the first) with gaps above
+                // kPullMaxDelta bridged by weight-0 entries; each unit's lanes
+                // start from their row before its first entry
                 const std::vector<int32_t> &cp = pcol[gq], &ord = pord[gq];
                 std::vector<int32_t> fill(cp.begin(), cp.end() - 1), rows(Q.nnz), at(Q.nnz);
                 for (int32_t i = 0; i < P.n_pre; ++i)
@@ -1102,26 +1134,50 @@ int snn_create(const snn_config *cfg, snn_net **out)
                         at[e] = k;
                     }
                 const int32_t n_sl = (P.n_post + kWave - 1) / kWave;
-                const int64_t e0 = pull_slices[P.pull_base];
-                const int64_t e1 = P.pull_base + n_sl < (int64_t)pull_slices.size() ? pull_slices[P.pull_base + n_sl]
-                                                                                     : pull_total;
-                std::vector<int2> erw(e1 - e0, make_int2(0, 0));
-                std::vector<int32_t> ep(e1 - e0, -1), lc((size_t)n_sl * kWave, -1);
+                const int64_t gs_end = P.pull_base + n_sl;
+                const int64_t pk_a = pull_slices[P.pull_base];
+                const int64_t pk_b = gs_end < (int64_t)pull_slices.size() ? pull_slices[gs_end] : pull_total;
+                const int32_t u_a = slice_u0[P.pull_base];
+                const int32_t u_b = gs_end < (int64_t)slice_u0.size() ? slice_u0[gs_end] : (int32_t)pull_units.size();
+                const size_t n_pk = (size_t)(pk_b - pk_a);
+                std::vector<float> ew(n_pk * kWave * 4, 0.0f);
+                std::vector<uint32_t> ed(n_pk * kWave, 0u);
+                std::vector<int32_t> ep(n_pk * kWave * 4, -1), lc((size_t)n_sl * kWave, -1);
+                std::vector<int32_t> er0((size_t)(u_b - u_a) * kWave, 0), rbefore;
                 for (int32_t j = 0; j < P.n_post; ++j) {
                     const int32_t c = ord[j], sl = j / kWave, l = j % kWave;
+                    const int64_t gs = P.pull_base + sl;
                     lc[j] = c;
-                    const int64_t b0 = pull_slices[P.pull_base + sl] - e0;
-                    for (int32_t k = 0; k < cp[c + 1] - cp[c]; ++k) {
-                        const int64_t e = b0 + (int64_t)k * kWave + l;
-                        float g = Q.g[at[cp[c] + k]];
-                        int32_t gb;
-                        std::memcpy(&gb, &g, 4);
-                        erw[e] = make_int2(rows[cp[c] + k], gb);
-                        ep[e] = (int32_t)(P.syn_base + at[cp[c] + k]);
+                    const int64_t pb = pull_slices[gs] - pk_a;
+                    const int64_t pe = (gs + 1 < (int64_t)pull_slices.size() ? pull_slices[gs + 1] : pull_total) - pk_a;
+                    const int32_t depth = (int32_t)(4 * (pe - pb));
+                    rbefore.assign(depth + 1, 0);
+                    int32_t R = cp[c + 1] > cp[c] ? rows[cp[c]] : 0, ke = 0;
+                    auto emit = [&](int32_t delta, float w, int32_t pos) {
+                        const size_t idx = (size_t)(pb + ke / 4) * kWave + l;
+                        rbefore[ke] = R;
+                        ed[idx] |= (uint32_t)delta << (8 * (ke % 4));
+                        ew[idx * 4 + ke % 4] = w;
+                        ep[idx * 4 + ke % 4] = pos;
+                        R += delta;
+                        ++ke;
+                    };
+                    for (int32_t k = cp[c]; k < cp[c + 1]; ++k) {
+                        int32_t gap = k == cp[c] ? 0 : rows[k] - rows[k - 1];
+                        while (gap > kPullMaxDelta) {
+                            emit(kPullMaxDelta, 0.0f, -1);
+                            gap -= kPullMaxDelta;
+                        }
+                        emit(gap, Q.g[at[k]], (int32_t)(P.syn_base + at[k]));
                     }
+                    for (int32_t k = ke; k <= depth; ++k) rbefore[k] = R;
+                    for (int32_t u = slice_u0[gs]; u < u_b && pull_units[u].col_off == (int32_t)(gs * kWave); ++u)
+                        er0[(size_t)(u - u_a) * kWave + l] = rbefore[4 * (pull_units[u].pk0 - pull_slices[gs])];
                 }
-                if ((rc = up(net->d_pull_rw + e0, erw.data(), 8 * erw.size()))) return bail(rc);
-                if ((rc = up(net->d_pull_perm + e0, ep.data(), 4 * ep.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_w + pk_a * kWave, ew.data(), 4 * ew.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_d + pk_a * kWave, ed.data(), 4 * ed.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_perm + pk_a * kWave * 4, ep.data(), 4 * ep.size()))) return bail(rc);
+                if ((rc = up(net->d_pull_r0 + (int64_t)u_a * kWave, er0.data(), 4 * er0.size()))) return bail(rc);
                 if ((rc = up(net->d_pull_col + P.pull_base * kWave, lc.data(), 4 * lc.size()))) return bail(rc);
             }
             if (Q.stdp) {
@@ -1874,7 +1930,8 @@ int snn_set_weights_device(snn_net *net, const float *src)
             return fail(SNN_ERANGE, "projection %zu: g_scale * column sum / (1 - decay) exceeds %g uS", q, kGLimit);
     }
     HIP_OK(hipMemcpyAsync(net->d_w, src, 4 * (size_t)net->w_count, hipMemcpyDeviceToDevice, net->stream));
-    HIP_OK(launch_gather_weights(net->d_w, net->d_pull_perm, net->d_pull_rw, net->pull_count, net->stream));
+    HIP_OK(launch_gather_weights(net->d_w, net->d_pull_perm, (float *)net->d_pull_w, 4 * kWave * net->pull_count,
+                                 net->stream));
     if (net->launch.mode != kModeFused) return SNN_OK;
     // fused mode: the pending deliveries of S(t-1) were made with the old
     // weights; the other modes deliver them at step t with the new ones

@@ -487,7 +487,9 @@ def test_pull_delivery_paths(snn):
     looked up in global memory (a pulled population of 70 000 neurons), copied
     into LDS in a loop (65 to 1024 words), single-chunk slices adding into G
     directly, deep slices reduced in one group and in several groups with
-    atomics (columns of 5000 entries), and a partial last slice."""
+    atomics (columns of 5000 entries), a partial last slice, and a projection
+    too sparse for one-byte row deltas (no copy: pushed while its population
+    is pulled elsewhere)."""
     say("case: pull delivery paths")
     rng = np.random.default_rng(21)
     pops = [dict(name="A", kind="poisson", n=70000, rate_hz=9500.0, i_ext=0.0),
@@ -495,8 +497,9 @@ def test_pull_delivery_paths(snn):
             dict(name="C", kind="hh", n=100, rate_hz=0.0, i_ext=0.0),
             dict(name="D", kind="poisson", n=6000, rate_hz=9500.0, i_ext=0.0)]
     projs = []
-    for pre, post, p, tau, erev in [(0, 1, 0.0005, netgen.TAU_AB, netgen.E_EXC), (3, 1, 0.02, netgen.TAU_AB, netgen.E_EXC),
-                                    (1, 2, 1.0, netgen.TAU_BC, netgen.E_EXC), (2, 2, 1.0, netgen.TAU_CC, netgen.E_INH)]:
+    for pre, post, p, tau, erev in [(0, 1, 0.01, netgen.TAU_AB, netgen.E_EXC), (3, 1, 0.02, netgen.TAU_AB, netgen.E_EXC),
+                                    (1, 2, 1.0, netgen.TAU_BC, netgen.E_EXC), (2, 2, 1.0, netgen.TAU_CC, netgen.E_INH),
+                                    (0, 2, 0.0005, netgen.TAU_AB, netgen.E_EXC)]:
         n_pre, n_post = pops[pre]["n"], pops[post]["n"]
         rp, ci = netgen.bernoulli_csr(rng, n_pre, n_post, p, no_self=(pre == post))
         projs.append(dict(pre=pre, post=post, row_ptr=rp, col_idx=ci,
@@ -521,6 +524,70 @@ def test_pull_delivery_paths(snn):
     assert a.nan_counts()[0] == 0
     a.close()
     b.close()
+
+
+def _csr_from_columns(n_pre, columns):
+    """CSR (ascending columns per row) of the connectivity whose column j
+    holds the pre rows columns[j]."""
+    pairs = sorted((int(r), j) for j, rows in enumerate(columns) for r in rows)
+    counts = np.zeros(n_pre, np.int64)
+    for r, _ in pairs:
+        counts[r] += 1
+    rp = np.zeros(n_pre + 1, np.int64)
+    np.cumsum(counts, out=rp[1:])
+    return rp.astype(np.int32), np.array([j for _, j in pairs], np.int32)
+
+
+@pytest.mark.parametrize("n_pre", [3000, 70000])
+def test_pull_row_delta_edges(snn, n_pre):
+    """The pull copy stores each column's rows as one-byte deltas, gaps above
+    255 bridged by weight-0 entries.  With integer weights, one pulled
+    delivery equals the oracle's bit for bit on columns built at the edges
+    of that encoding: gaps of 254, 255, 256, 510, 511 and 765 rows, a first
+    row far from 0, a single entry at the last row, the first and last row
+    only, every row (a slice of several pull units), empty columns, and
+    random columns of density 0.003 to 0.5 (in LDS and, at 70 000 pre
+    neurons, global spike words)."""
+    say(f"case: pull delta edges, {n_pre} pre neurons")
+    rng = np.random.default_rng(31 + n_pre)
+    n_post = 300
+    cols = [np.arange(0, n_pre, 255), np.arange(7, n_pre, 256), np.arange(3, n_pre, 254),
+            np.cumsum(np.tile([510, 511, 765], n_pre // 1786 + 1))[: n_pre // 600] % n_pre,
+            np.array([n_pre - 1]), np.array([0, n_pre - 1]), np.arange(n_pre), np.array([], np.int64),
+            np.array([1000, 1255, 1511])]
+    while len(cols) < n_post:
+        d = 10 ** rng.uniform(np.log10(0.003), np.log10(0.5))
+        if rng.random() < 0.05:
+            cols.append(np.array([], np.int64))
+        else:
+            cols.append(np.nonzero(rng.random(n_pre) < d)[0])
+    cols = [np.unique(c) for c in cols]
+    rp, ci = _csr_from_columns(n_pre, cols)
+    # integer weights up to 3 and a 1 ms decay keep the full column's
+    # reachable conductance within the library's fixed-point range
+    g = rng.integers(0, 4, ci.size).astype(np.float32)
+    pops = [dict(name="A", kind="poisson", n=n_pre, rate_hz=0.0, i_ext=0.0),
+            dict(name="B", kind="hh", n=n_post, rate_hz=0.0, i_ext=0.0)]
+    projs = [dict(pre=0, post=1, row_ptr=rp, col_idx=ci, g=g, e_rev=0.0, tau=1.0, stdp=None)]
+    inst = dict(g_scale=1.0, seed=99, pops=pops, projs=projs)
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    net = snn.Network(spec)
+    net.set_launch(mode=1)
+    orc = O.OracleNet(inst)
+    for frac in (1.0, 0.9):
+        flags = np.ones(n_pre, np.uint8)
+        if frac < 1.0:
+            flags[rng.choice(n_pre, int(round((1 - frac) * n_pre)), replace=False)] = 0
+        net.set_last_spikes(0, 0, flags)
+        orc.set_last_spikes(0, flags)
+        net.set_conductance(0, 0, np.zeros(n_post))
+        orc.set_G(0, np.zeros(n_post))
+        net.step(1)
+        orc.step(1)
+        g_gpu = net.conductance(0, 0) * FIX
+        g_orc = np.rint(orc.G(0) * FIX)
+        assert np.array_equal(g_gpu, g_orc), np.nonzero(g_gpu != g_orc)[0][:10]
+    net.close()
 
 
 def _same_network_state(a, b, spec):
