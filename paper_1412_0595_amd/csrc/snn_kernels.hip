@@ -121,8 +121,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     uint32_t wslot = 0;            // slot of this wave's word in the active list
     uint64_t wball = 0;            // this wave's spike word
     int32_t j = 0;
-    uint32_t cnt = 0;              // prefetched spike count
-    int32_t ra0 = 0, ra1 = 0, rb0 = 0, rb1 = 0;   // prefetched rows of outgoing projections 0 and 1
+    int32_t ra0 = 0, ra1 = 0, rb0 = 0, rb1 = 0;   // rows of outgoing projections 0 and 1 (spiking lanes)
     float trv[kMaxTr] = {};        // prefetched traces
 
     // The population record's fields that the update reads, loaded together
@@ -148,20 +147,12 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         const bool active = j < s_n;
         // Every load of the update is issued up front and unconditionally,
         // so that they share one memory round trip: padded arrays at gid,
-        // unpadded ones (conductances, traces, row starts) at jj, the index
-        // clamped into the population.  Lanes past the population compute on
-        // that data and store nothing.
+        // unpadded ones (conductances, traces) at jj, the index clamped into
+        // the population.  Lanes past the population compute on that data and
+        // store nothing.  What only a spiking neuron needs (its spike count,
+        // its outgoing row bounds) is read after the spike test, by the
+        // spiking lanes alone.
         const int32_t jj = active ? j : s_n - 1;
-        cnt = a.counts[gid];
-        {
-            // (used in rows mode; a missing projection reads rp_pool[0..1])
-            const int32_t *rpa = a.rp_pool + (s_nout > 0 ? s_rp0 + jj : 0);
-            const int32_t *rpb = a.rp_pool + (s_nout > 1 ? s_rp1 + jj : 0);
-            ra0 = rpa[0];
-            ra1 = rpa[1];
-            rb0 = rpb[0];
-            rb1 = rpb[1];
-        }
 #pragma unroll
         for (int q = 0; q < kMaxTr; ++q)
             if (q < s_ntr) trv[q] = a.trace[S.tr_base[q] + jj];
@@ -291,9 +282,16 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
             }
         }
         if (ball != 0 && spike) {
-            a.counts[gid] = cnt + 1;
+            a.counts[gid] += 1;
             const uint32_t ch = (uint32_t)a.chunk;
             if constexpr (MODE != kModeTiles) {
+                // (a missing projection reads rp_pool[0..1])
+                const int32_t *rpa = a.rp_pool + (s_nout > 0 ? s_rp0 + j : 0);
+                const int32_t *rpb = a.rp_pool + (s_nout > 1 ? s_rp1 + j : 0);
+                ra0 = rpa[0];
+                ra1 = rpa[1];
+                rb0 = rpb[0];
+                rb1 = rpb[1];
                 // one propagation item (fused: one chunk) per chunk of each
                 // outgoing row
                 if (s_nout > 0) nq += ((uint32_t)(ra1 - ra0) + ch - 1) / ch;
