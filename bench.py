@@ -432,6 +432,8 @@ def parse():
                     help="JSON file of tuned launch shapes per network signature (read, and written after tuning)")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="leave out the forced-activity delivery points of a batched workload's line")
     ap.add_argument("--profile-steps", type=int, default=500)
     ap.add_argument("--sweep", action="store_true",
                     help="forced-activity sweep of the propagation kernel instead of the step benchmark")
@@ -492,23 +494,20 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return gbs
 
 
-def sweep(args):
-    """Propagation kernel alone on a workload's connectivity with seeded
-    synthetic spike sets: every input (A) row and a fraction of the hidden (B)
-    rows spiking; one hipEvent pair around back-to-back launches."""
+def sweep_points(spec, fractions, configs, seed=7):
+    """Propagation alone on a network's connectivity with seeded synthetic
+    spike sets: every input (A) row and a fraction of the hidden (B) rows
+    spiking, C silent, plasticity off (pure delivery); one hipEvent pair
+    around back-to-back launches of one step's delivery per launch shape."""
     import numpy as np
     from paper_1412_0595_amd import netgen, snn
-    copy_gbs = copy_bandwidth()
-    print(json.dumps({"sweep": "copy", "bytes": 1 << 30, "copy_GBs": copy_gbs,
-                      "frac_of_hbm": copy_gbs / HBM_PEAK_GBS}), flush=True)
-    spec = netgen.make_config(args.sweep_workload, n_instances=args.instances)
-    for inst in spec["instances"]:
-        for q in inst["projs"]:
-            q["stdp"] = None      # pure delivery: no depression writes
+    spec = dict(spec, instances=[dict(inst, projs=[dict(q, stdp=None) for q in inst["projs"]])
+                                 for inst in spec["instances"]])
     net = snn.Network(spec, autotune=False)
-    rng = np.random.default_rng(7)
+    rng = np.random.default_rng(seed)
     deg = out_degree_table(spec)
-    for frac in (0.001, 0.01, 0.1, 1.0):
+    out = []
+    for frac in fractions:
         ev = rows = 0
         for b, inst in enumerate(spec["instances"]):
             n_a, n_b = inst["pops"][0]["n"], inst["pops"][1]["n"]
@@ -520,18 +519,33 @@ def sweep(args):
             net.set_last_spikes(b, 2, np.zeros(inst["pops"][2]["n"], np.uint8))
             ev += int(deg[b][0].sum() + deg[b][1][fb.astype(bool)].sum())
             rows += n_a + int(fb.sum())
-        for L in (dict(mode=0, prop_blocks=1024, prop_block=256), dict(mode=0, prop_blocks=4096, prop_block=256),
-                  dict(mode=1, prop_blocks=1024), dict(mode=1, prop_blocks=2048), dict(mode=1, prop_blocks=4096)):
+        for L in configs:
             net.set_launch(**L)
             launches = 20 if ev > 1e7 else 200
             ms = net.time_kernel(0, launches)
             byt = PROP_BYTES_PER_EVENT * ev + PROP_BYTES_PER_ROW * rows
             gbs = byt / (ms * 1e-3) / 1e9
-            print(json.dumps({"sweep": "propagation", "workload": args.sweep_workload, "hidden_fraction": frac,
-                              "events_per_launch": ev, "rows": rows, "ms_per_launch": ms, "launch": net.launch,
-                              "events_per_s": ev / (ms * 1e-3), "achieved_GBs": gbs,
-                              "frac_of_hbm": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}), flush=True)
+            out.append({"hidden_fraction": frac, "events_per_launch": ev, "rows": rows, "ms_per_launch": ms,
+                        "launch": net.launch, "events_per_s": ev / (ms * 1e-3), "achieved_GBs": gbs,
+                        "frac_of_hbm": gbs / HBM_PEAK_GBS})
     net.close()
+    return out
+
+
+def sweep(args):
+    """Forced-activity sweep of the propagation on a workload's connectivity
+    (every input row and 0.1 / 1 / 10 / 100% of the hidden rows spiking), in
+    both delivery modes and several launch shapes; one JSON line per point."""
+    from paper_1412_0595_amd import netgen
+    copy_gbs = copy_bandwidth()
+    print(json.dumps({"sweep": "copy", "bytes": 1 << 30, "copy_GBs": copy_gbs,
+                      "frac_of_hbm": copy_gbs / HBM_PEAK_GBS}), flush=True)
+    spec = netgen.make_config(args.sweep_workload, n_instances=args.instances)
+    configs = (dict(mode=0, prop_blocks=1024, prop_block=256), dict(mode=0, prop_blocks=4096, prop_block=256),
+               dict(mode=1, prop_blocks=1024), dict(mode=1, prop_blocks=2048), dict(mode=1, prop_blocks=4096))
+    for pt in sweep_points(spec, (0.001, 0.01, 0.1, 1.0), configs):
+        print(json.dumps(dict({"sweep": "propagation", "workload": args.sweep_workload}, **pt,
+                              frac_of_copy=pt["achieved_GBs"] / copy_gbs)), flush=True)
 
 
 def note(msg):
@@ -718,6 +732,18 @@ def step_bench(args):
                                     "batched_speedup": loop_ms / ms,
                                     "how": "every instance alone on the same kernels (autotuned, graphs), "
                                            "one after the other, same pre-roll and step count; step time only"}
+    if len(spec["instances"]) > 1 and not args.no_sweep:
+        # the propagation target (>= 60% of HBM peak) on this workload's own
+        # connectivity: forced activity at the 10% and 100% hidden points
+        note("forced-activity delivery on this workload's connectivity")
+        pts = sweep_points(spec, (0.1, 1.0), (dict(mode=1, prop_blocks=4096),))
+        rec["propagation_sweep"] = {
+            "how": "every input row and a seeded fraction of the hidden rows spiking, one step's delivery timed "
+                   "20 times back to back (hipEvent pair), tile mode with pull, 4096 blocks; bytes are the "
+                   "method's CSR bytes, 8 B per synaptic event + 16 B per spiking row",
+            "points": [{"hidden_fraction": p["hidden_fraction"], "events_per_launch": p["events_per_launch"],
+                        "ms_per_launch": round(p["ms_per_launch"], 6), "achieved_GBs": round(p["achieved_GBs"], 1),
+                        "frac_of_hbm": round(p["frac_of_hbm"], 4)} for p in pts]}
     if not args.no_cpu:
         note("oracle sample on the host cores")
     rec["cpu_baseline"] = None if args.no_cpu else cpu_baseline(spec, args.cpu_seconds)

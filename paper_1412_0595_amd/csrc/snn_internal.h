@@ -231,7 +231,15 @@ struct NeuronArgs {
     int32_t *awl;            // [2][n_waves]
     int32_t n_segs;
     const float4 *izp;       // Izhikevich (a, b, c, d) per neuron, at Seg::izp_base + index
+    int32_t feat;            // kFeat* bits: what the network's populations use
 };
+
+// What a network's populations use beyond Traub-Miles and Poisson neurons;
+// the neuron update is instantiated per combination, so a network without
+// them runs none of their code and holds none of their values.
+constexpr int kFeatIzh = 1;       // Izhikevich populations
+constexpr int kFeatPlastic = 2;   // STDP traces and potentiation work
+constexpr int kFeatRec = 4;       // voltage sums recorded for the adjoint's loss
 
 struct PropArgs {
     int32_t mode;

@@ -99,9 +99,10 @@ __device__ __forceinline__ void fused_delivery(const NeuronArgs &a, int64_t t, u
 // ---------------------------------------------------------------------------
 // Neuron update + spike compaction
 // ---------------------------------------------------------------------------
-// One instantiation per delivery mode (uniform over a launch), so that each
-// carries only its own mode's emission code and kernel arguments.
-template <int MODE>
+// One instantiation per delivery mode (uniform over a launch) and per set of
+// population features (kFeat*, fixed at create), so that each carries only
+// the code and the kernel arguments its network needs.
+template <int MODE, int FEAT>
 __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 {
     __shared__ uint32_t s_woff[16][2];
@@ -130,14 +131,18 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
     // last wave's record and store nothing.
     const int sidx = __builtin_amdgcn_readfirstlane(a.wave_seg[min(gw, a.n_waves - 1)]);
     const Seg &S = a.segs[sidx];
+    constexpr bool kIzhOn = (FEAT & kFeatIzh) != 0, kPlastic = (FEAT & kFeatPlastic) != 0, kRec = (FEAT & kFeatRec) != 0;
     const int64_t s_b = S.base;
-    const int32_t s_n = S.n, s_kind = S.kind, s_nout = S.n_out, s_nin = S.n_in, s_ntr = S.n_tr, s_nltp = S.n_ltp;
-    const int32_t s_rec = S.record_vbar, s_op0 = S.out_proj[0], s_op1 = S.out_proj[1], s_inst = S.inst;
+    const int32_t s_n = S.n, s_kind = S.kind, s_nout = S.n_out, s_nin = S.n_in;
+    const int32_t s_ntr = kPlastic ? S.n_tr : 0, s_nltp = kPlastic ? S.n_ltp : 0, s_rec = kRec ? S.record_vbar : 0;
+    const int32_t s_op0 = S.out_proj[0], s_op1 = S.out_proj[1], s_inst = S.inst;
     const int64_t s_rp0 = S.out_rp[0], s_rp1 = S.out_rp[1];
     int64_t s_inG[kMaxIn];
 #pragma unroll
     for (int q = 0; q < kMaxIn; ++q) s_inG[q] = S.in_G[q];
-    asm volatile("" ::"s"(s_b), "s"(s_n), "s"(s_kind), "s"(s_nout), "s"(s_nin), "s"(s_ntr), "s"(s_nltp), "s"(s_rec));
+    asm volatile("" ::"s"(s_b), "s"(s_n), "s"(s_kind), "s"(s_nout), "s"(s_nin));
+    if constexpr (kPlastic) asm volatile("" ::"s"(s_ntr), "s"(s_nltp));
+    if constexpr (kRec) asm volatile("" ::"s"(s_rec));
     asm volatile("" ::"s"(s_op0), "s"(s_op1), "s"(s_rp0), "s"(s_rp1), "s"(s_inG[0]), "s"(s_inG[1]), "s"(s_inG[2]),
                  "s"(s_inG[3]), "s"(s_inst));
 
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 if (fits_fp32(v0) && !fits_fp32(v)) atomicAdd(&a.nan_count[s_inst], 1);
                 if (s_rec) a.vsum[gid] = vs + v;
             }
-        } else if (s_kind == kIzh) {
+        } else if (kIzhOn && s_kind == kIzh) {
             // Izhikevich: v in the V pair, u in the M pair, (a, b, c, d) from
             // the parameter pool; the same conductance handling as above
             const double vs = s_rec ? a.vsum[gid] : 0.0;
@@ -1250,12 +1255,20 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent
     const int64_t wpb = block / kWave;
     const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
     if (blocks == 0) return hipSuccess;
-    if (a.mode == kModeTiles)
-        SNN_LAUNCH(k_neuron<kModeTiles>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
-    else if (a.mode == kModeFused)
-        SNN_LAUNCH(k_neuron<kModeFused>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
-    else
-        SNN_LAUNCH(k_neuron<kModeRows>, dim3((unsigned)blocks), dim3(block), s, e0, e1, a);
+    const dim3 g((unsigned)blocks), b(block);
+    switch (a.mode * 8 + (a.feat & 7)) {
+#define SNN_NEURON_CASE(M, F) \
+    case M * 8 + F: SNN_LAUNCH((k_neuron<M, F>), g, b, s, e0, e1, a); break;
+#define SNN_NEURON_FEATS(M) \
+    SNN_NEURON_CASE(M, 0) SNN_NEURON_CASE(M, 1) SNN_NEURON_CASE(M, 2) SNN_NEURON_CASE(M, 3) \
+    SNN_NEURON_CASE(M, 4) SNN_NEURON_CASE(M, 5) SNN_NEURON_CASE(M, 6) SNN_NEURON_CASE(M, 7)
+        SNN_NEURON_FEATS(kModeRows)
+        SNN_NEURON_FEATS(kModeTiles)
+        SNN_NEURON_FEATS(kModeFused)
+#undef SNN_NEURON_FEATS
+#undef SNN_NEURON_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -343,6 +343,12 @@ NeuronArgs neuron_args(snn_net *net)
     a.gscale = net->d_gscale;
     a.n_segs = (int32_t)net->segs.size();
     a.izp = net->d_izp;
+    a.feat = 0;
+    for (const Seg &S : net->segs) {
+        if (S.kind == kIzh) a.feat |= kFeatIzh;
+        if (S.n_tr > 0 || S.n_ltp > 0) a.feat |= kFeatPlastic;
+        if (S.record_vbar) a.feat |= kFeatRec;
+    }
     return a;
 }
 
