@@ -79,13 +79,14 @@ constexpr int kFusedCap = 512;     // chunks a block lists in LDS per round
 // exceed a quarter of its synapses gets no copy (it is always pushed).
 constexpr int kPullNum = 7, kPullDen = 8;
 constexpr int kPullDepth = 64;
+constexpr int64_t kPullUnitsMin = 32768;   // pull units of all copies together, at least (unit depth choice)
 constexpr int kPullMaxDelta = 255;
 
 struct PullUnit {
     int64_t pk0;        // the unit's first packet (global packet index; lane 0)
     int64_t g_base;     // conductance pool offset of the projection
     int32_t col_off;    // offset of the slice's 64 post neurons in the column table
-    int32_t npk;        // packets (4 entries each) per lane, <= kPullDepth / 4
+    int32_t npk;        // packets (4 entries each) per lane, <= 4 kPullDepth / 4
     int32_t pre_seg;    // pre population, and of it:
     int32_t inst;       //   instance (g_scale),
     int32_t wbase;      //   first spike word (global word index),

@@ -856,7 +856,11 @@ int snn_create(const snn_config *cfg, snn_net **out)
     // encoded length is its entry count plus the weight-0 entries that bridge
     // gaps of more than kPullMaxDelta rows; columns by decreasing encoded
     // length, 64 to a slice, a slice's depth rounded up to whole packets of 4
-    // and split evenly into pull units of at most kPullDepth entries
+    // and split evenly into pull units of at most `unit_depth` entries: the
+    // largest of kPullDepth, 2 kPullDepth and 4 kPullDepth that still cuts
+    // all copies together into kPullUnitsMin units (a deeper unit reads more
+    // per record and leaves fewer slices to partial sums, but there must be
+    // enough units to fill the chip)
     std::vector<std::vector<int32_t>> pcol(net->projs.size()), pord(net->projs.size()), plen(net->projs.size());
     std::vector<int64_t> pull_slices;   // first packet of each slice
     std::vector<int32_t> slice_u0;      // first pull unit of each slice
@@ -898,6 +902,22 @@ int snn_create(const snn_config *cfg, snn_net **out)
                 ord.resize(P.n_post);
                 for (int32_t j = 0; j < P.n_post; ++j) ord[j] = j;
                 std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return len[x] > len[y]; });
+            }
+        }
+    }
+    int64_t pull_entries = 0;
+    for (size_t gq = 0; gq < plen.size(); ++gq)
+        for (int32_t j0 = 0; j0 < (int32_t)plen[gq].size(); j0 += kWave)
+            pull_entries += (int64_t)kWave * 4 * ((plen[gq][pord[gq][j0]] + 3) / 4);
+    int32_t unit_depth = kPullDepth;
+    while (unit_depth < 4 * kPullDepth && pull_entries / ((int64_t)kWave * 2 * unit_depth) >= kPullUnitsMin) unit_depth *= 2;
+    if (syn_total < ((int64_t)1 << 31)) {
+        for (int b = 0, gq = 0; b < net->n_inst; ++b) {
+            const snn_instance_desc &I = cfg->inst[b];
+            for (int q = 0; q < I.n_projs; ++q, ++gq) {
+                Proj &P = net->projs[gq];
+                if (plen[gq].empty()) continue;
+                const std::vector<int32_t> &ord = pord[gq], &len = plen[gq];
                 P.pull_base = (int64_t)pull_slices.size();
                 const Seg &pre = net->segs[P.pre_seg];
                 for (int32_t j0 = 0; j0 < P.n_post; j0 += kWave) {
@@ -905,9 +925,9 @@ int snn_create(const snn_config *cfg, snn_net **out)
                     const int64_t sl = (int64_t)pull_slices.size();
                     pull_slices.push_back(pull_total);
                     slice_u0.push_back((int32_t)pull_units.size());
-                    // depth split into equal chunks of at most kPullDepth;
+                    // depth split into equal chunks of at most unit_depth;
                     // reduction groups of up to 64 chunks
-                    const int32_t nch = (4 * npk + kPullDepth - 1) / kPullDepth;
+                    const int32_t nch = (4 * npk + unit_depth - 1) / unit_depth;
                     for (int32_t c0 = 0; nch > 1 && c0 < nch; c0 += kWave)
                         pull_red.push_back(PullSlice{P.G_base, (int32_t)pull_units.size() + c0, std::min(kWave, nch - c0),
                                                      (int32_t)(sl * kWave), P.pre_seg, nch > kWave ? 1 : 0, 0});

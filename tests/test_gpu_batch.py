@@ -286,6 +286,37 @@ def test_full_size_batch_sampled_parity(snn):
     net.close()
 
 
+def test_full_size_pull_delivery_bitwise(snn):
+    """Workload 4 at its full size, where the column copies are cut into pull
+    units up to 256 entries deep: with every input and hidden neuron of eight
+    instances spiking (both populations pulled in tile mode; the input
+    columns are single units that add into G, the hidden-to-output columns
+    several units reduced from partial sums), one step's conductances equal
+    row mode's (atomic pushes of the same spikes) bit for bit, in every
+    instance."""
+    spec = netgen.make_config(4)
+    pick = _spread_instances(spec)[:8]
+    say(f"case: workload 4 full size, forced pull delivery in instances {pick}")
+    nets = []
+    for mode in (1, 0):
+        net = snn.Network(spec)
+        net.set_launch(mode=mode, prop_blocks=4096)
+        for k in pick:
+            inst = spec["instances"][k]
+            net.set_last_spikes(k, 0, np.ones(inst["pops"][0]["n"], np.uint8))
+            net.set_last_spikes(k, 1, np.ones(inst["pops"][1]["n"], np.uint8))
+        net.step(1)
+        nets.append(net)
+    a, b = nets
+    for k, inst in enumerate(spec["instances"]):
+        for q in range(len(inst["projs"])):
+            assert np.array_equal(a.conductance(k, q), b.conductance(k, q)), (k, q)
+    for k in pick:
+        assert float(np.abs(a.conductance(k, 0)).sum()) > 0.0 and float(np.abs(a.conductance(k, 1)).sum()) > 0.0
+    a.close()
+    b.close()
+
+
 def test_full_size_stdp_workload3(snn):
     """Workload 3 at its full size (A=2000 @30 Hz, B=100000, C=1000; 91 M
     synapses, plastic B->C) in the autotuned launch shape: 400 steps (C's
