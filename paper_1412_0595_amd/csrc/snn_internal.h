@@ -171,16 +171,29 @@ struct Proj {
 struct StepState {
     int64_t t_prop;      // step index seen by propagation / potentiation
     int64_t t_neuron;    // step index seen by the neuron update
-    uint32_t qcnt[2];    // propagation work items produced at step t (slot t & 1)
+    uint32_t qcnt[2];    // host-built propagation work items at the start of slot t & 1
     uint32_t lcnt[2];    // potentiation work items produced at step t
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
-    uint32_t fdone;      // fused mode: blocks of the running update that finished
+    uint32_t fdone;      // fused mode: buckets of blocks of the running update that finished
     uint32_t npull[2];   // tile mode: populations to pull, per step slot
     uint32_t pad_[2];
 };
 // Per step slot and population, how many of its spike words held a spike
 // (active-word counts, [2][n_segs]) and which ([2][n_waves], population
 // words at the population's own word offset).
+
+// Work-queue reservation.  The neuron update reserves queue space once per
+// block; one returning atomic per block on a single counter serialises the
+// whole grid (about 11 ns each on the MI355X: 8 400 blocks take 97 us), so
+// block b reserves on counter b mod kQBuckets, the counters 4 KiB apart.
+// Bucket x owns a fixed range of each queue slot, sized to the worst case of
+// its blocks (every neuron spiking; rows: every outgoing row in chunks of
+// kMinChunk, tiles: one item per outgoing projection and post tile), for the
+// current block size and mode.  Host-built work (after a mode switch or
+// spikes set from the host) sits contiguously at the start of a slot with
+// its own count (StepState::qcnt) and empty buckets.
+constexpr int kQBuckets = 64;
+constexpr int kQBucketStride = 1024;   // uint32 words between two bucket counters
 
 // A work item.  Row mode: synapses [k0, k1) of row `row` of projection
 // `proj`, whose instance is `aux` (so that its g_scale is read alongside
@@ -213,6 +226,9 @@ struct NeuronArgs {
     const int32_t *cp_pool;
     Item *queue;             // 2 slots of qcap
     int64_t qcap;
+    uint32_t *qb_cnt;        // [3][kQBuckets] counters kQBucketStride apart: reservations of the two
+                             // queue slots, the fused update's per-bucket done counts
+    const int64_t *qb_base;  // kQBuckets + 1 bucket offsets into a queue slot
     Item *lqueue;            // 2 slots of lcap
     int64_t lcap;
     int32_t chunk;
@@ -248,6 +264,8 @@ struct PropArgs {
     const Seg *segs;
     const Item *queue;
     int64_t qcap;
+    const uint32_t *qb_cnt;  // [2][kQBuckets] items reserved in each bucket, kQBucketStride apart
+    const int64_t *qb_base;  // kQBuckets + 1 bucket offsets into a queue slot
     const int32_t *rp_pool;
     const int32_t *tp_pool;
     const int32_t *col_pool;

@@ -89,10 +89,23 @@ __device__ __forceinline__ void fused_delivery(const NeuronArgs &a, int64_t t, u
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && atomicAdd(&a.st->fdone, 1u) == gridDim.x - 1) {
-        a.st->fdone = 0;
-        a.st->t_prop = t + 1;
-        a.st->t_neuron = t + 1;
+    // done counts in two levels, so that no address takes one returning
+    // atomic per block: the last block of bucket blockIdx mod kQBuckets
+    // (counters of the third bucket slot, 4 KiB apart) counts its bucket
+    // done, the last bucket advances the step counters
+    if (threadIdx.x == 0) {
+        const uint32_t x = blockIdx.x % kQBuckets;
+        const uint32_t in_x = (gridDim.x - 1u - x) / kQBuckets + 1u;   // blocks of bucket x
+        uint32_t *c = a.qb_cnt + ((int64_t)2 * kQBuckets + x) * kQBucketStride;
+        if (atomicAdd(c, 1u) == in_x - 1u) {
+            *c = 0u;
+            const uint32_t buckets = min(gridDim.x, (uint32_t)kQBuckets);
+            if (atomicAdd(&a.st->fdone, 1u) == buckets - 1u) {
+                a.st->fdone = 0;
+                a.st->t_prop = t + 1;
+                a.st->t_neuron = t + 1;
+            }
+        }
     }
 }
 
@@ -334,9 +347,14 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         }
         s_tot = sq;
         if constexpr (MODE != kModeFused) {
-            s_base[0] = sq ? atomicAdd(&a.st->qcnt[cur], sq) : 0u;
+            // one reservation in this block's bucket (counters 4 KiB apart, so
+            // the blocks' atomics do not queue on one address)
+            const int x = (int)(blockIdx.x % kQBuckets);
+            const int64_t qb0 = a.qb_base[x], qb1 = a.qb_base[x + 1];
+            const uint32_t r = sq ? atomicAdd(&a.qb_cnt[((int64_t)cur * kQBuckets + x) * kQBucketStride], sq) : 0u;
+            s_base[0] = (uint32_t)(qb0 + r);
             s_base[1] = sl ? atomicAdd(&a.st->lcnt[cur], sl) : 0u;
-            if (sq && (int64_t)s_base[0] + sq > a.qcap) atomicOr(&a.st->overflow, 1u);
+            if (sq && qb0 + (int64_t)r + sq > qb1) atomicOr(&a.st->overflow, 1u);
             if (sl && (int64_t)s_base[1] + sl > a.lcap) atomicOr(&a.st->overflow, 2u);
             if (blockIdx.x == 0) {
                 a.st->qcnt[cur ^ 1] = 0;    // consumed by this step's propagation
@@ -344,6 +362,11 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
                 a.st->t_prop = t + 1;
             }
         }
+    }
+    if constexpr (MODE != kModeFused) {
+        // the buckets of the slot this step's propagation consumed
+        if (blockIdx.x == 0 && threadIdx.x < kQBuckets)
+            a.qb_cnt[((int64_t)(cur ^ 1) * kQBuckets + threadIdx.x) * kQBucketStride] = 0u;
     }
     __syncthreads();
 
@@ -612,6 +635,29 @@ using CPullUnit = const __attribute__((address_space(4))) PullUnit;
 using CPullSlice = const __attribute__((address_space(4))) PullSlice;
 using CInt4 = const __attribute__((address_space(4))) int4;
 
+// The work items of queue slot `prev` that wavefront g of nw takes: the nc
+// contiguous host-built ones (g, g + nw, ...), then the reserved ones bucket
+// by bucket.  With at least kQBuckets wavefronts, nw / kQBuckets of them
+// share each bucket (wavefront g takes bucket g mod kQBuckets and its items
+// g / kQBuckets, + nw / kQBuckets, ...); with fewer, wavefront g takes
+// buckets g, g + nw, ... whole.  A count beyond its bucket's range (an
+// overflow, flagged by the neuron update) is cut to the range.
+template <class F>
+__device__ __forceinline__ void visit_items(const PropArgs &a, int prev, uint32_t g, uint32_t nw, uint32_t nc, F &&f)
+{
+    using CU32 = const __attribute__((address_space(4))) uint32_t;
+    using CI64 = const __attribute__((address_space(4))) int64_t;
+    for (uint32_t it = g; it < nc; it += nw) f((int64_t)it);
+    const uint32_t per = nw / kQBuckets;
+    if (per && g >= kQBuckets * per) return;
+    for (uint32_t x = per ? g % kQBuckets : g; x < (uint32_t)kQBuckets; x += per ? kQBuckets : nw) {
+        const uint32_t cnt = ((CU32 *)a.qb_cnt)[((int64_t)prev * kQBuckets + x) * kQBucketStride];
+        const int64_t b0 = ((CI64 *)a.qb_base)[x], b1 = ((CI64 *)a.qb_base)[x + 1];
+        const int64_t n = min((int64_t)cnt, b1 - b0);
+        for (int64_t k = per ? g / kQBuckets : 0; k < n; k += per ? per : 1) f(b0 + k);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CSR propagation, row mode: one wavefront per work item = a chunk of one
 // spiking row; 64-bit atomics add the fixed-point weights into G (+ the
@@ -626,36 +672,19 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
     CItem *queue = (CItem *)a.queue;
     CProj *projs = (CProj *)a.projs;
     CFloat *gscale = (CFloat *)a.gscale;
-    // The wavefront's first item in both slots, the step counter and both
-    // slots' item counts are read together (one round trip); the slot of
-    // step t - 1 is picked after.
-    const int64_t i0 = min((int64_t)it0, a.qcap - 1);
-    CItem &F0 = queue[i0];
-    CItem &F1 = queue[a.qcap + i0];
-    const int32_t f0p = F0.proj, f0a = F0.k0, f0b = F0.k1, f0i = (int32_t)F0.aux;
-    const int32_t f1p = F1.proj, f1a = F1.k0, f1b = F1.k1, f1i = (int32_t)F1.aux;
+    // the step counter and both slots' counts of host-built items are read
+    // together; the slot of step t - 1 is picked after
     const int64_t t = a.st->t_prop;
     const uint32_t c0 = a.st->qcnt[0], c1 = a.st->qcnt[1];
-    asm volatile("" ::"s"(t), "s"(c0), "s"(c1), "s"(f0p), "s"(f0a), "s"(f0b), "s"(f0i), "s"(f1p), "s"(f1a), "s"(f1b),
-                 "s"(f1i), "s"(projs), "s"(gscale), "s"(a.col_pool), "s"(a.w_pool), "s"(a.G));
+    asm volatile("" ::"s"(t), "s"(c0), "s"(c1), "s"(projs), "s"(gscale), "s"(a.col_pool), "s"(a.w_pool), "s"(a.G));
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
-    const uint32_t n = min((uint32_t)a.qcap, prev ? c1 : c0);
+    const uint32_t nc = min((uint32_t)a.qcap, prev ? c1 : c0);
     CItem *q = queue + (int64_t)prev * a.qcap;
 
-    for (uint32_t it = it0; it < n; it += nw) {
-        int32_t proj, k0, k1, inst;
-        if (it == it0) {
-            proj = prev ? f1p : f0p;
-            k0 = prev ? f1a : f0a;
-            k1 = prev ? f1b : f0b;
-            inst = prev ? f1i : f0i;
-        } else {
-            proj = q[it].proj;
-            k0 = q[it].k0;
-            k1 = q[it].k1;
-            inst = (int32_t)q[it].aux;
-        }
-        if (inst < 0 || inst >= a.n_inst) continue;   // malformed item
+    visit_items(a, prev, it0, nw, nc, [&](int64_t at) {
+        if (at >= a.qcap) return;                     // malformed range
+        const int32_t proj = q[at].proj, k0 = q[at].k0, k1 = q[at].k1, inst = (int32_t)q[at].aux;
+        if (inst < 0 || inst >= a.n_inst) return;   // malformed item
         // the projection record's fields and the instance's g_scale, read
         // together
         CProj &P = projs[proj];
@@ -663,7 +692,7 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
         const int32_t p_inst = P.inst, stdp = P.stdp;
         const float gs = gscale[inst];
         asm volatile("" ::"s"(nnz), "s"(syn_base), "s"(G_base), "s"(p_inst), "s"(stdp), "s"(gs));
-        if (k0 < 0 || k1 > nnz || k0 > k1 || p_inst != inst) continue;   // malformed item
+        if (k0 < 0 || k1 > nnz || k0 > k1 || p_inst != inst) return;   // malformed item
         const double s = (double)gs * kFixOne;
         const int32_t *col = a.col_pool + syn_base;
         float *w = a.w_pool + syn_base;
@@ -696,7 +725,7 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
                 }
             }
         }
-    }
+    });
     if (blockIdx.x == 0 && threadIdx.x == 0) a.st->t_neuron = t;
 }
 
@@ -868,22 +897,23 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform: scalar indexing
     const int64_t t = a.st->t_prop;
     const int prev = (int)((t + 1) & 1);          // slot of step t - 1
-    const uint32_t n = min((uint32_t)a.qcap, a.st->qcnt[prev]);
+    const uint32_t nc = min((uint32_t)a.qcap, a.st->qcnt[prev]);
     const Item *q = a.queue + (int64_t)prev * a.qcap;
     const uint32_t nw = gridDim.x * kPropWaves;
     long long *acc = s_acc[wid];
 
-    for (uint32_t it = blockIdx.x * kPropWaves + wid; it < n; it += nw) {
-        CItem &I = ((CItem *)q)[it];
+    visit_items(a, prev, blockIdx.x * kPropWaves + wid, nw, nc, [&](int64_t at) {
+        if (at >= a.qcap) return;                     // malformed range
+        CItem &I = ((CItem *)q)[at];
         const int32_t proj = I.proj, word0 = I.row, tile = I.k0, slot = I.k1;
         const uint64_t bits0 = I.bits;
         CProj &P = ((CProj *)a.projs)[proj];
-        if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) continue;   // malformed item
-        if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) continue;         // pulled instead
+        if (slot >= P.pre_words || tile >= P.n_tiles || word0 >= P.pre_words) return;   // malformed item
+        if (P.pull_base >= 0 && a.pullf[prev * a.n_segs + P.pre_seg]) return;         // pulled instead
         // the item of the first slot of each group processes the whole group
         const uint32_t na = min(a.awcnt[prev * a.n_segs + P.pre_seg], (uint32_t)P.pre_words);
         const uint32_t gw = max(1u, a.gwsel[prev * a.n_segs + P.pre_seg]);
-        if ((uint32_t)slot % gw != 0 || (uint32_t)slot >= na) continue;
+        if ((uint32_t)slot % gw != 0 || (uint32_t)slot >= na) return;
         const uint32_t group = (uint32_t)slot / gw;
         const uint32_t nwords = min(gw, na - (uint32_t)slot);
         const int32_t tw = P.tile_w;
@@ -915,7 +945,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
                 // sparse: straight into G with atomics
                 word_to_global((unsigned long long *)(a.G + P.G_base), col, w, bits0, b0, b1, s, lane);
                 if (lane == 0) *flag = 0;
-                continue;
+                return;
             }
         }
         for (int i = lane; i < tw; i += kWave) acc[i] = 0;
@@ -971,7 +1001,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
             int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
             for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
             if (lane == 0) *flag = 1;
-            continue;
+            return;
         }
         // plastic rows: one word at a time, one row at a time
         for (uint32_t wi = 0; wi < nwords; ++wi) {
@@ -1026,7 +1056,7 @@ __global__ __launch_bounds__(kPropWaves * kWave) void k_propagate_tiles(PropArgs
         int64_t *out = a.partial + P.P_base + ((int64_t)tile * P.pre_words + group) * tw;
         for (int i = lane; i < tw; i += kWave) out[i] = acc[i];
         if (lane == 0) *flag = 1;
-    }
+    });
     if (a.st->npull[prev] != 0 && a.n_pull_units > 0) {
         // pull units: wavefront g takes units g, g + nw, g + 2 nw, ... (so
         // the units of the pulled populations spread over every wavefront)

@@ -170,6 +170,10 @@ struct snn_net {
     int64_t *d_partial;
     uint8_t *d_pflag;
     int4 *d_units;           // tile-mode reduction units
+    uint32_t *qb_cnt;        // arena: [3][kQBuckets] counters kQBucketStride apart: reservations of
+                             // the two queue slots, the fused update's per-bucket done counts
+    int64_t *d_qb_base;      // kQBuckets + 1 bucket offsets into a queue slot (current block size and mode)
+    std::vector<int64_t> wave_items_rows, wave_items_tiles;   // worst-case work items of each wave's neurons
     int64_t n_units;
     PullUnit *d_pull_units;  // tile-mode pull units
     int64_t n_pull_units;
@@ -324,6 +328,8 @@ NeuronArgs neuron_args(snn_net *net)
     a.cp_pool = net->d_cp;
     a.queue = net->queue;
     a.qcap = net->qcap;
+    a.qb_cnt = net->qb_cnt;
+    a.qb_base = net->d_qb_base;
     a.lqueue = net->lqueue;
     a.lcap = net->lcap;
     a.chunk = net->launch.chunk;
@@ -360,6 +366,8 @@ PropArgs prop_args(snn_net *net)
     p.segs = net->d_segs;
     p.queue = net->queue;
     p.qcap = net->qcap;
+    p.qb_cnt = net->qb_cnt;
+    p.qb_base = net->d_qb_base;
     p.rp_pool = net->d_rp;
     p.tp_pool = net->d_tp;
     p.col_pool = net->d_col;
@@ -697,6 +705,8 @@ void snn_default_hh(double *p)
 
 const char *snn_last_error(void) { return g_err.c_str(); }
 
+static int update_qbuckets(snn_net *net);
+
 int snn_create(const snn_config *cfg, snn_net **out)
 {
     if (!out) return fail(SNN_EINVAL, "out is NULL");
@@ -965,6 +975,18 @@ int snn_create(const snn_config *cfg, snn_net **out)
     for (const HostProj &H : net->hprojs)
         for (int32_t i = 0; i < H.n_pre; ++i) qcap_rows += (H.row_ptr[i + 1] - H.row_ptr[i] + kMinChunk - 1) / kMinChunk;
     const int64_t qcap = std::max(qcap_tiles, qcap_rows);
+    // the same worst cases per wave of pre neurons, for the reservation buckets
+    net->wave_items_rows.assign(net->n_waves, 0);
+    net->wave_items_tiles.assign(net->n_waves, 0);
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        const Proj &P = net->projs[q];
+        const HostProj &H = net->hprojs[q];
+        const Seg &pre = net->segs[P.pre_seg];
+        for (int32_t i = 0; i < H.n_pre; ++i)
+            net->wave_items_rows[(pre.base + i) / kWave] += (H.row_ptr[i + 1] - H.row_ptr[i] + kMinChunk - 1) / kMinChunk;
+        for (int64_t w = pre.base / kWave; w < (pre.base + align_up(pre.n, kWave)) / kWave; ++w)
+            net->wave_items_tiles[w] += P.n_tiles;
+    }
     // column lengths of plastic projections
     std::vector<std::vector<int32_t>> colptrs(net->projs.size());
     for (int b = 0, gq = 0; b < net->n_inst; ++b) {
@@ -1016,6 +1038,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     Part p_queue = part(2 * net->qcap * (int64_t)sizeof(Item));
     Part p_lqueue = part(2 * net->lcap * (int64_t)sizeof(Item));
     Part p_st = part(sizeof(StepState));
+    Part p_qb = part(4 * 3 * (int64_t)kQBuckets * kQBucketStride);   // two queue slots, fused done counts
     Part p_awcnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_scnt = part(2 * (int64_t)net->segs.size() * 4);
     Part p_awl = part(2 * W * 4);
@@ -1052,6 +1075,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     }
     net->n_units = (int64_t)units.size();
     net->d_units = (int4 *)dev_alloc(net, sizeof(int4) * std::max<size_t>(units.size(), 1));
+    net->d_qb_base = (int64_t *)dev_alloc(net, 8 * (size_t)(kQBuckets + 1));
     net->pull_count = pull_total;
     net->n_pull_units = (int64_t)pull_units.size();
     net->d_pull_units = (PullUnit *)dev_alloc(net, sizeof(PullUnit) * std::max<size_t>(pull_units.size(), 1));
@@ -1068,7 +1092,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
         !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
         !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_w ||
-        !net->d_pull_d || !net->d_pull_r0 || !net->d_pull_perm)
+        !net->d_pull_d || !net->d_pull_r0 || !net->d_pull_perm || !net->d_qb_base)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -1083,6 +1107,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     net->queue = (Item *)(A + p_queue.off);
     net->lqueue = (Item *)(A + p_lqueue.off);
     net->st = (StepState *)(A + p_st.off);
+    net->qb_cnt = (uint32_t *)(A + p_qb.off);
     net->awcnt = (uint32_t *)(A + p_awcnt.off);
     net->scnt = (uint32_t *)(A + p_scnt.off);
     net->awl = (int32_t *)(A + p_awl.off);
@@ -1276,6 +1301,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
         (void)hipGetLastError();
         return bail(fail(SNN_EDEVICE, "device synchronisation failed"));
     }
+    if ((rc = update_qbuckets(net))) return bail(rc);
     net->t = 0;
     *out = net;
     if (cfg->autotune) {
@@ -1472,6 +1498,31 @@ int snn_get_last_spikes(snn_net *net, int32_t inst, int32_t pop, uint8_t *out)
     return SNN_OK;
 }
 
+// Bucket offsets of the queue slots for the current block size and mode:
+// block b of the neuron update reserves in bucket b mod kQBuckets, sized to
+// the worst case of its waves' neurons.
+static int update_qbuckets(snn_net *net)
+{
+    const int64_t wpb = net->launch.neuron_block / kWave;
+    const std::vector<int64_t> &items = net->launch.mode == kModeTiles ? net->wave_items_tiles : net->wave_items_rows;
+    std::vector<int64_t> base(kQBuckets + 1, 0);
+    for (int64_t w = 0; w < net->n_waves; ++w) base[(w / wpb) % kQBuckets + 1] += items[w];
+    for (int x = 0; x < kQBuckets; ++x) base[x + 1] += base[x];
+    if (base[kQBuckets] > net->qcap) return fail(SNN_EDEVICE, "queue buckets exceed the queue (internal)");
+    return h2d(net, net->d_qb_base, base.data(), 8 * base.size());
+}
+
+// Zero the reservation counters of queue slot `slot` (-1: both slots and
+// the fused done counts).
+static int clear_qbuckets(snn_net *net, int slot)
+{
+    const size_t words = (size_t)kQBuckets * kQBucketStride;
+    HIP_OK(launch_fill_zero(net->qb_cnt + (slot < 0 ? 0 : (size_t)slot * words), 4 * words * (slot < 0 ? 3 : 1),
+                            net->stream));
+    HIP_OK(hipStreamSynchronize(net->stream));
+    return SNN_OK;
+}
+
 // Rebuild the propagation work of the pending step from the spike bitmasks
 // of the slot it consumes, in the current delivery mode (rows: chunk items
 // per spiking row; tiles: active-word lists, spike counts and one item per
@@ -1528,6 +1579,7 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     }
     if ((int64_t)items.size() > net->qcap) return fail(SNN_ERANGE, "too many work items");
     if ((rc = h2d(net, net->queue + (int64_t)slot * net->qcap, items.data(), sizeof(Item) * items.size()))) return rc;
+    if ((rc = clear_qbuckets(net, slot))) return rc;   // the rebuilt work is all contiguous
     std::vector<uint32_t> zero(nseg, 0);
     if ((rc = h2d(net, net->awcnt + (int64_t)slot * nseg, cnt.data(), 4 * nseg))) return rc;
     if ((rc = h2d(net, net->scnt + (int64_t)slot * nseg, spk.data(), 4 * nseg))) return rc;
@@ -1585,6 +1637,7 @@ static int clear_queues(snn_net *net)
     st.qcnt[0] = st.qcnt[1] = 0;
     st.lcnt[0] = st.lcnt[1] = 0;
     st.npull[0] = st.npull[1] = 0;
+    if ((rc = clear_qbuckets(net, -1))) return rc;
     std::vector<uint32_t> zero(2 * net->segs.size(), 0);
     if ((rc = h2d(net, net->pullf, zero.data(), 4 * zero.size()))) return rc;
     return h2d(net, net->st, &st, sizeof st);
@@ -1773,18 +1826,26 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
         return fail(SNN_EINVAL, "mode must be 0 (rows), 1 (tiles) or 2 (fused)");
     if (in->mode == kModeFused && net->plastic)
         return fail(SNN_EINVAL, "mode 2 (fused) needs a network without plastic projections");
-    const int old = net->launch.mode;
+    const snn_launch prev = net->launch;
     net->launch = *in;
-    // the pending work of the next step was laid out for the old mode
-    if (old != in->mode) {
-        if (in->mode == kModeFused)
-            rc = deliver_queued_to_fused(net, old);
-        else if (old == kModeFused)
-            rc = leave_fused(net);
-        else
+    if ((rc = update_qbuckets(net))) return rc;
+    // The pending work of the next step was laid out for the old mode and in
+    // the buckets of the old block size: it is laid out again from the spike
+    // bitmasks, contiguously (entering fused mode: as rows work, run at once
+    // into the fused buffer).
+    if (in->mode == kModeFused) {
+        if (prev.mode != kModeFused) {
+            net->launch.mode = kModeRows;
             rc = rebuild_pending(net, -1, nullptr);
-        if (rc) return rc;
+            net->launch.mode = kModeFused;
+            if (!rc) rc = deliver_queued_to_fused(net, kModeRows);
+        }
+    } else if (prev.mode == kModeFused) {
+        rc = leave_fused(net);
+    } else if (prev.mode != in->mode || prev.neuron_block != in->neuron_block) {
+        rc = rebuild_pending(net, -1, nullptr);
     }
+    if (rc) return rc;
     drop_graphs(net);
     return SNN_OK;
 }
