@@ -190,6 +190,8 @@ void snn_default_hh(double *p);
  * steady-state membrane current in [-80, -60] mV), every Izhikevich neuron
  * to v = -65 mV, u = b v, conductances and traces
  * to 0, step counter to 0.  All-or-nothing: on failure *out = NULL.
+ * SNN_ERANGE for more than 2^29 neurons in all (each population padded to a
+ * multiple of 64), or for weights outside the conductance range.
  * Device memory beyond the state: the CRS arrays (8 B per synapse plus row
  * starts); for every non-plastic projection a column-ordered copy used by
  * tile mode's pull delivery (each entry a one-byte row delta, its fp32

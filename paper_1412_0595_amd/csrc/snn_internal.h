@@ -178,9 +178,9 @@ struct StepState {
     uint32_t npull[2];   // tile mode: populations to pull, per step slot
     uint32_t pad_[2];
 };
-// Per step slot and population, how many of its spike words held a spike
-// (active-word counts, [2][n_segs]) and which ([2][n_waves], population
-// words at the population's own word offset).
+// Largest total of neurons (each population padded to a multiple of 64):
+// byte offsets into the 8-byte per-neuron arrays stay below 2^32.
+constexpr int64_t kMaxNeuronsPadded = int64_t(1) << 29;
 
 // Work-queue reservation.  The neuron update reserves queue space once per
 // block; one returning atomic per block on a single counter serialises the
@@ -243,9 +243,9 @@ struct NeuronArgs {
     const float *gscale;
     uint32_t *gwsel;         // [2][n_segs]  words per group chosen at emission
     uint32_t *pullf;         // [2][n_segs]  1: the population's projections are pulled
-    uint32_t *awcnt;         // [2][n_segs]  active spike words
+    uint32_t *awcnt;         // [2][n_segs]  per step slot and population: spike words that held a spike
     uint32_t *scnt;          // [2][n_segs]  spikes
-    int32_t *awl;            // [2][n_waves]
+    int32_t *awl;            // [2][n_waves] which words, at the population's own word offset
     int32_t n_segs;
     const float4 *izp;       // Izhikevich (a, b, c, d) per neuron, at Seg::izp_base + index
     int32_t feat;            // kFeat* bits: what the network's populations use

@@ -109,14 +109,49 @@ __device__ __forceinline__ void fused_delivery(const NeuronArgs &a, int64_t t, u
     }
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: the address is
+// the base (scalar registers) plus the offset (one vector register), so the
+// loads and stores of several arrays at the same index share one register
+// instead of holding a 64-bit address each.
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+// A conductance array of one projection (pool + offset), kept in scalar
+// registers.
+__device__ __forceinline__ int64_t *gbase(int64_t *pool, int64_t off)
+{
+    return reinterpret_cast<int64_t *>(uniform_u64(reinterpret_cast<uint64_t>(pool + off)));
+}
+__device__ __forceinline__ double pair_at(const float *hi, const float *lo, uint32_t off)
+{
+    return (double)ld_at(hi, off) + (double)ld_at(lo, off);
+}
+__device__ __forceinline__ void split_at(double x, float *hi, float *lo, uint32_t off)
+{
+    const float h = (float)x;
+    st_at(hi, off, h);
+    st_at(lo, off, (float)(x - (double)h));
+}
+
 // ---------------------------------------------------------------------------
 // Neuron update + spike compaction
 // ---------------------------------------------------------------------------
 // One instantiation per delivery mode (uniform over a launch) and per set of
 // population features (kFeat*, fixed at create), so that each carries only
-// the code and the kernel arguments its network needs.
+// the code and the kernel arguments its network needs.  The plain Traub-Miles
+// instantiations are held to 96 VGPRs, five wavefronts per SIMD: their state
+// is addressed as one 32-bit offset from uniform bases (ld_at/st_at), and the
+// two 8-byte spills this leaves sit outside the substep loop.
 template <int MODE, int FEAT>
-__global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 5 : 4, 8)))
+void k_neuron(NeuronArgs a)
 {
     __shared__ uint32_t s_woff[16][2];
     __shared__ uint32_t s_base[2];
@@ -175,12 +210,17 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
         for (int q = 0; q < kMaxTr; ++q)
             if (q < s_ntr) trv[q] = a.trace[S.tr_base[q] + jj];
 
+        // byte offsets of the lane's elements: padded state arrays at gid,
+        // conductances at jj (stores at j), from wave-uniform bases (the
+        // library keeps the padded neuron count below 2^29)
+        const uint32_t o4 = (uint32_t)gid * 4u, o8 = (uint32_t)gid * 8u;
+        const uint32_t g8 = (uint32_t)jj * 8u, s8 = (uint32_t)j * 8u;
         if (s_kind == kHH) {
-            const double vs = s_rec ? a.vsum[gid] : 0.0;
-            double v = pair_load(a.vh, a.vl, gid);
-            double m = pair_load(a.mh, a.ml, gid);
-            double h = pair_load(a.hh, a.hl, gid);
-            double n = pair_load(a.nh, a.nl, gid);
+            const double vs = s_rec ? ld_at(a.vsum, o8) : 0.0;
+            double v = pair_at(a.vh, a.vl, o4);
+            double m = pair_at(a.mh, a.ml, o4);
+            double h = pair_at(a.hh, a.hl, o4);
+            double n = pair_at(a.nh, a.nl, o4);
             const double v0 = v;
             // delivered conductance: in G (rows and tile modes), G plus this
             // step's slot of the delivery buffer (fused mode)
@@ -189,8 +229,8 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 #pragma unroll
             for (int q = 0; q < kMaxIn; ++q)
                 if (q < s_nin) {
-                    g[q] = a.G[s_inG[q] + jj];
-                    if constexpr (MODE == kModeFused) g[q] += a.D[dcur + s_inG[q] + jj];
+                    g[q] = ld_at(gbase(a.G, s_inG[q]), g8);
+                    if constexpr (MODE == kModeFused) g[q] += ld_at(gbase(a.D, dcur + s_inG[q]), g8);
                 }
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
@@ -201,16 +241,16 @@ __global__ __launch_bounds__(1024) void k_neuron(NeuronArgs a)
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
                     if (q < s_nin) {
-                        a.G[s_inG[q] + j] = fix_decay(g[q], S.in_decay[q]);
-                        if constexpr (MODE == kModeFused) a.D[dcur + s_inG[q] + j] = 0;
+                        st_at(gbase(a.G, s_inG[q]), s8, fix_decay(g[q], S.in_decay[q]));
+                        if constexpr (MODE == kModeFused) st_at(gbase(a.D, dcur + s_inG[q]), s8, (int64_t)0);
                     }
                 spike = (v0 < 0.0) && (v >= 0.0);
-                pair_split(v, a.vh[gid], a.vl[gid]);
-                pair_split(m, a.mh[gid], a.ml[gid]);
-                pair_split(h, a.hh[gid], a.hl[gid]);
-                pair_split(n, a.nh[gid], a.nl[gid]);
+                split_at(v, a.vh, a.vl, o4);
+                split_at(m, a.mh, a.ml, o4);
+                split_at(h, a.hh, a.hl, o4);
+                split_at(n, a.nh, a.nl, o4);
                 if (fits_fp32(v0) && !fits_fp32(v)) atomicAdd(&a.nan_count[s_inst], 1);
-                if (s_rec) a.vsum[gid] = vs + v;
+                if (s_rec) st_at(a.vsum, o8, vs + v);
             }
         } else if (kIzhOn && s_kind == kIzh) {
             // Izhikevich: v in the V pair, u in the M pair, (a, b, c, d) from

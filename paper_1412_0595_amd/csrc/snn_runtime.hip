@@ -762,6 +762,11 @@ int snn_create(const snn_config *cfg, snn_net **out)
             net->seg_of[b].push_back((int32_t)net->segs.size());
             net->segs.push_back(S);
             base += align_up(P.n, kWave);
+            // the neuron update addresses 8-byte per-neuron arrays by 32-bit
+            // byte offsets
+            if (base > kMaxNeuronsPadded)
+                return bail(fail(SNN_ERANGE, "more than %lld neurons (padded to 64 per population)",
+                                 (long long)kMaxNeuronsPadded));
             if (S.kind == kHH) net->n_hh += P.n;
             if (S.kind == kIzh) {
                 net->segs.back().izp_base = izp_total;

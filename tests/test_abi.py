@@ -219,3 +219,14 @@ def test_header_compiles_as_c_and_host_routines_run(tmp_path):
     assert k3 == pytest.approx(-0.28, rel=1e-7) and mape < 1e-6
     # nConn 10 -> run 0 (the reference); nConn 20 -> run 1 (|5.5 - 5| = |4 - 5| / 2; run 3 has NaNs)
     assert sel.split() == ["2", "10", "0", "20", "1"]
+
+
+def test_neuron_count_limit_rejected():
+    """The neuron update addresses its 8-byte per-neuron arrays by 32-bit byte
+    offsets, so more than 2^29 neurons (each population padded to 64) are
+    refused before any device call."""
+    pops = [dict(name="A", kind="poisson", n=1 << 29, rate_hz=1.0, i_ext=0.0),
+            dict(name="B", kind="hh", n=1, rate_hz=0.0, i_ext=0.0)]
+    spec = dict(dt=0.1, substeps=3, instances=[dict(g_scale=1.0, seed=1, pops=pops, projs=[])])
+    rc, msg = snn.create_status(spec)
+    assert rc == snn.SNN_ERANGE and "neurons" in msg, msg
