@@ -235,8 +235,8 @@ void k_neuron(NeuronArgs a)
             // synaptic current from the start-of-step voltage, held fixed
             // over the substeps; then the conductances decay
             const double iin = syn_current(S, g, v0);
-            const double hc = a.hs * S.inv_c;
-            for (int k = 0; k < a.substeps; ++k) hh_substep(S, a.hs, hc, iin, v, m, h, n);
+            // the decayed conductances are stored before the substeps, so
+            // that they are not held in registers across them
             if (active) {
 #pragma unroll
                 for (int q = 0; q < kMaxIn; ++q)
@@ -244,13 +244,22 @@ void k_neuron(NeuronArgs a)
                         st_at(gbase(a.G, s_inG[q]), s8, fix_decay(g[q], S.in_decay[q]));
                         if constexpr (MODE == kModeFused) st_at(gbase(a.D, dcur + s_inG[q]), s8, (int64_t)0);
                     }
+            }
+            const double hc = a.hs * S.inv_c;
+            for (int k = 0; k < a.substeps; ++k) hh_substep(S, a.hs, hc, iin, v, m, h, n);
+            if (active) {
+                // the offset passes through an empty asm, so the compiler
+                // forms the state addresses here instead of holding eight
+                // 64-bit addresses across the substeps
+                uint32_t os = o4;
+                asm volatile("" : "+v"(os));
                 spike = (v0 < 0.0) && (v >= 0.0);
-                split_at(v, a.vh, a.vl, o4);
-                split_at(m, a.mh, a.ml, o4);
-                split_at(h, a.hh, a.hl, o4);
-                split_at(n, a.nh, a.nl, o4);
+                split_at(v, a.vh, a.vl, os);
+                split_at(m, a.mh, a.ml, os);
+                split_at(h, a.hh, a.hl, os);
+                split_at(n, a.nh, a.nl, os);
                 if (fits_fp32(v0) && !fits_fp32(v)) atomicAdd(&a.nan_count[s_inst], 1);
-                if (s_rec) st_at(a.vsum, o8, vs + v);
+                if (s_rec) st_at(a.vsum, 2u * os, vs + v);
             }
         } else if (kIzhOn && s_kind == kIzh) {
             // Izhikevich: v in the V pair, u in the M pair, (a, b, c, d) from
