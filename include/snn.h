@@ -178,7 +178,14 @@ typedef struct {
                                (no propagation kernel: each neuron-update block delivers its
                                own spikes' row chunks with atomics into a double-buffered
                                delivery buffer that the next update adds to G; only for
-                               networks without plastic projections) */
+                               networks without plastic projections), 3 grouped (rows, except
+                               that every non-plastic projection onto at most 1024 neurons,
+                               with at most 60% of the (pre, post) pairs connected and rows
+                               of fewer than 768 synapses on average, is delivered
+                               in groups of 2 to 6 of its spiking rows (about 1536 synapses),
+                               taken in spike-word order: a wavefront sums a group's synapses in
+                               an LDS copy of the post population's conductances and adds
+                               its nonzero entries into G with atomics; prop_block <= 512) */
 } snn_launch;
 
 /* Fill p[0..6] with the Traub-Miles parameters (7.15 uS, 50 mV, 1.43 uS,

@@ -48,7 +48,24 @@ enum { kPoisson = 0, kHH = 1, kIzh = 2 };
 // rows = a work item per chunk of a spiking row, 64-bit atomics into G;
 // tiles = a work item per (projection, post tile, group of active spike
 // words), LDS tile accumulation, partial tiles added into G by a reduction.
-enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2 };
+enum { kModeRows = 0, kModeTiles = 1, kModeFused = 2, kModeGrouped = 3 };
+// grouped = rows, except that every non-plastic projection onto at most
+// kGrpTile post neurons, with at most kGrpDense of its (pre, post) pairs
+// connected and rows of fewer than kGrpSyn / 2 synapses on average, is
+// delivered in groups of its spiking rows (found in order in the pre
+// population's spike words), k rows per group with k = kGrpSyn / (mean row
+// length), at most kGrpRows: a wavefront sums a group's synapses in its own
+// LDS tile of the post population and adds the tile's nonzero entries into G
+// with atomics, a few atomics per post neuron and group instead of one per
+// synapse.  Denser or longer rows already put several synapses in each
+// atomic transaction, and their groups would be long serial walks.
+// kGrpSlots wavefronts per such projection take its groups in turn.  Its
+// row items (still emitted by the neuron update) are skipped.
+constexpr int kGrpTile = 1024;
+constexpr int kGrpRows = 6;
+constexpr int kGrpSyn = 1536;
+constexpr double kGrpDense = 0.6;
+constexpr int kGrpSlots = 16;
 // fused = no propagation kernel: each neuron-update block delivers its own
 // spikes' rows with 64-bit atomics into the delivery buffer D of the next
 // step (double-buffered), which the next update adds to G (networks without
@@ -157,7 +174,7 @@ struct Proj {
     int64_t pull_base;  // first slice of the column-ordered copy (non-plastic), else -1
     int64_t F_base;     // partial flag offset: [tile][group] bytes (1: a partial tile was written)
     int32_t pre_words;  // spike words of the pre population (ceil(n_pre / 64))
-    int32_t pad2_;
+    int32_t grp;        // 1: delivered in row groups in grouped mode
     // STDP
     float a_plus_gmax, a_minus_gmax, g_max, pad_;
     int64_t x_base, y_base;    // trace pool offsets (pre n_pre, post n_post)
@@ -176,7 +193,8 @@ struct StepState {
     uint32_t overflow;   // set if a queue would have overflowed (never expected)
     uint32_t fdone;      // fused mode: buckets of blocks of the running update that finished
     uint32_t npull[2];   // tile mode: populations to pull, per step slot
-    uint32_t pad_[2];
+    uint32_t grp_off[2]; // grouped mode: 1 = the grouped deliveries of S(t-1) in slot t & 1 are already made
+                         // (the host emptied the queues), so the groups skip that slot
 };
 // Largest total of neurons (each population padded to a multiple of 64):
 // byte offsets into the 8-byte per-neuron arrays stay below 2^32.
@@ -235,7 +253,7 @@ struct NeuronArgs {
     int32_t substeps;
     double hs;               // dt / substeps
     StepState *st;
-    int32_t mode;            // kModeRows / kModeTiles / kModeFused
+    int32_t mode;            // kModeRows / kModeTiles / kModeFused (grouped mode runs as rows)
     int64_t *D;              // fused: [2][G pool] deliveries for the next update
     int64_t G_count;
     const int32_t *col_pool;
@@ -296,6 +314,8 @@ struct PropArgs {
     const float4 *pull_w;    // sliced-ELL weights, [packet][64 lanes] x 4 entries
     const uint32_t *pull_d;  // their row deltas, [packet][64 lanes], one byte per entry
     const int32_t *pull_r0;  // [unit][64] lane's row before the unit's first entry
+    const int2 *grp_proj;    // grouped mode: (projection, rows per group) of those delivered in groups
+    int64_t n_grp;           // 0 unless grouped mode
 };
 
 struct LtpArgs {

@@ -7,7 +7,10 @@
 //               propagation work of the next step.  In fused mode the block
 //               instead delivers its own spikes' rows (fused_delivery).
 //  k_propagate_rows  (sparse activity) persistent grid, one wavefront per
-//               chunk of a spiking row; 64-bit atomics into G.
+//               chunk of a spiking row; 64-bit atomics into G.  In grouped
+//               mode wavefronts first take groups of a few spiking rows of
+//               each projection onto a small post population, sum them in an
+//               LDS tile and add its nonzero entries into G.
 //  k_propagate_tiles (dense activity) persistent grid of independent
 //               wavefronts, one per work item = (projection, post tile, group
 //               of active 64-neuron spike words of the pre population; only a
@@ -408,6 +411,7 @@ void k_neuron(NeuronArgs a)
             if (blockIdx.x == 0) {
                 a.st->qcnt[cur ^ 1] = 0;    // consumed by this step's propagation
                 a.st->lcnt[cur ^ 1] = 0;
+                a.st->grp_off[cur] = 0;     // this step's spikes are for the row groups to deliver
                 a.st->t_prop = t + 1;
             }
         }
@@ -707,14 +711,131 @@ __device__ __forceinline__ void visit_items(const PropArgs &a, int prev, uint32_
     }
 }
 
+// Grouped delivery.  Wavefront slot j of grouped projection p takes groups
+// j, j + kGrpSlots, ... of p's spiking rows, a group being p's k consecutive
+// rows in the order of the pre population's step t - 1 spike words.  One pass over the words (64 per round, one per lane) counts the
+// rows; lane r of a group holds its row r, found from the round's inclusive
+// popcount scan (the word whose count passes the row's index) and the set
+// bit of that rank in the word.  A complete group (or the last, partial one)
+// is summed into the wavefront's LDS tile of the post population with LDS
+// atomics, whose nonzero entries then go into G with 64-bit atomics.
+// Integer sums: the bits equal row mode's.
+__device__ __forceinline__ void group_to_global(const PropArgs &a, unsigned long long *tile, int32_t np,
+                                                const int32_t *rp, const int32_t *col, const float *w, double s,
+                                                unsigned long long *G, int32_t row, uint32_t nrows, int32_t n_pre,
+                                                int lane)
+{
+    for (int i = lane; i < np; i += kWave) tile[i] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    int32_t b0 = 0, b1 = 0;
+    if ((uint32_t)lane < nrows && row >= 0 && row < n_pre) {
+        b0 = rp[row];
+        b1 = rp[row + 1];
+    }
+    uint64_t rem = nrows >= (uint32_t)kWave ? ~0ull : ((1ull << nrows) - 1ull);
+    int32_t k = 0, k1 = 0;
+    Batch BA, BB;
+    BatchData DA, DB;
+    auto add = [&](const Batch &B, const BatchData &D) {
+#pragma unroll
+        for (int u = 0; u < kSlots; ++u)
+            if (B.ph[u] >= 0 && B.sk[u] + lane < B.se[u])
+                atomicAdd(tile + D.c[u], (unsigned long long)fix_increment(s, D.g[u]));
+    };
+    if (fill_batch(BA, rem, k, k1, b0, b1)) {
+        load_batch(DA, BA, col, w, 0, lane);
+        for (;;) {
+            const bool more_b = fill_batch(BB, rem, k, k1, b0, b1);
+            if (!more_b) BB = BA;
+            load_batch(DB, BB, col, w, 0, lane);
+            add(BA, DA);
+            if (!more_b) break;
+            const bool more_a = fill_batch(BA, rem, k, k1, b0, b1);
+            if (!more_a) BA = BB;
+            load_batch(DA, BA, col, w, 0, lane);
+            add(BB, DB);
+            if (!more_a) break;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int i = lane; i < np; i += kWave) {
+        const unsigned long long v = tile[i];
+        if (v != 0ull) atomicAdd(G + i, v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ void grouped_wave(const PropArgs &a, int prev, int64_t gslot, int lane,
+                                             unsigned long long *tile)
+{
+    using CProjG = const __attribute__((address_space(4))) Proj;
+    using CSegG = const __attribute__((address_space(4))) Seg;
+    using CI32G = const __attribute__((address_space(4))) int32_t;
+    const CI32G *e = (CI32G *)a.grp_proj + 2 * (gslot / kGrpSlots);   // (projection, rows per group)
+    const int32_t proj = e[0];
+    const uint32_t K = (uint32_t)e[1];
+    const uint32_t j0 = (uint32_t)(gslot % kGrpSlots);
+    CProjG &P = ((CProjG *)a.projs)[proj];
+    const int32_t np = P.n_post, n_pre = P.n_pre, pre_seg = P.pre_seg, pw = P.pre_words, inst = P.inst;
+    const int64_t rp_base = P.rp_base, syn_base = P.syn_base, G_base = P.G_base;
+    if (np <= 0 || np > kGrpTile || pw <= 0 || inst < 0 || inst >= a.n_inst || K < 1 || K > (uint32_t)kGrpRows)
+        return;   // malformed entry
+    const int64_t wbase = ((CSegG *)a.segs)[pre_seg].base / kWave;
+    const uint64_t *wb = a.bits + (int64_t)prev * a.n_waves + wbase;
+    const double sc = (double)a.gscale[inst] * kFixOne;
+    const int32_t *rp = a.rp_pool + rp_base;
+    const int32_t *col = a.col_pool + syn_base;
+    const float *wt = a.w_pool + syn_base;
+    unsigned long long *G = (unsigned long long *)(a.G + G_base);
+    uint32_t q = j0;          // this wavefront's current group
+    uint32_t base = 0;        // spiking rows in the rounds before this one
+    int32_t row = -1;         // lane r < kGrpRows: row r of the current group
+    for (int32_t w0 = 0; w0 < pw; w0 += kWave) {
+        const uint64_t word = w0 + lane < pw ? wb[w0 + lane] : 0ull;
+        const uint32_t pc = (uint32_t)__popcll(word);
+        const uint32_t incl = wave_incl_sum(pc, lane);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+        // rows of the current group that fall in this round, then the group
+        // itself once its last row is in
+        for (;;) {
+            const uint32_t g0 = q * K;
+            if (g0 >= base + tot) break;
+            for (int r = 0; r < (int)K; ++r) {
+                const uint32_t t = g0 + (uint32_t)r;
+                if (t < base || t >= base + tot) continue;   // (uniform)
+                const uint32_t u = t - base;
+                const uint64_t over = __ballot(incl > u);
+                const int L = (int)__builtin_ctzll(over);
+                uint64_t bits = readlane_u64(word, (uint32_t)L);
+                uint32_t n = u - ((uint32_t)__builtin_amdgcn_readlane((int)incl, L) -
+                                  (uint32_t)__builtin_amdgcn_readlane((int)pc, L));
+                for (; n > 0; --n) bits &= bits - 1ull;
+                if (lane == r) row = (w0 + L) * kWave + (int32_t)__builtin_ctzll(bits);
+            }
+            if (g0 + K > base + tot) break;   // the group goes on in the next round
+            group_to_global(a, tile, np, rp, col, wt, sc, G, row, K, n_pre, lane);
+            row = -1;
+            q += (uint32_t)kGrpSlots;
+        }
+        base += tot;
+    }
+    // the last, partial group
+    const uint32_t g0 = q * K;
+    if (g0 < base) group_to_global(a, tile, np, rp, col, wt, sc, G, row, base - g0, n_pre, lane);
+}
+
 // ---------------------------------------------------------------------------
 // CSR propagation, row mode: one wavefront per work item = a chunk of one
 // spiking row; 64-bit atomics add the fixed-point weights into G (+ the
-// depression of plastic rows).  Suited to sparse activity.
+// depression of plastic rows).  Suited to sparse activity.  In grouped mode
+// the first wavefronts deliver the row groups (above) and the grouped
+// projections' row items are skipped.
 // ---------------------------------------------------------------------------
 
+template <bool GRP>
 __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
 {
+    extern __shared__ unsigned long long s_grp[];   // grouped mode: a kGrpTile tile per wavefront
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
     const uint32_t it0 = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -730,7 +851,21 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
     const uint32_t nc = min((uint32_t)a.qcap, prev ? c1 : c0);
     CItem *q = queue + (int64_t)prev * a.qcap;
 
-    visit_items(a, prev, it0, nw, nc, [&](int64_t at) {
+    uint32_t g_it = it0, nw_it = nw;
+    if (GRP && a.n_grp > 0) {
+        const int64_t n_gw = a.n_grp * kGrpSlots;
+        if (a.st->grp_off[prev] == 0)
+            for (int64_t gs = it0; gs < n_gw; gs += nw)
+                grouped_wave(a, prev, gs, lane, s_grp + (threadIdx.x >> 6) * kGrpTile);
+        // with enough wavefronts, the row items go to those past the groups
+        if ((int64_t)nw > 2 * n_gw) {
+            if ((int64_t)it0 < n_gw) nw_it = 0;
+            g_it = it0 - (uint32_t)n_gw;
+            nw_it = nw_it ? nw - (uint32_t)n_gw : 0u;
+        }
+    }
+
+    if (nw_it) visit_items(a, prev, g_it, nw_it, nc, [&](int64_t at) {
         if (at >= a.qcap) return;                     // malformed range
         const int32_t proj = q[at].proj, k0 = q[at].k0, k1 = q[at].k1, inst = (int32_t)q[at].aux;
         if (inst < 0 || inst >= a.n_inst) return;   // malformed item
@@ -738,10 +873,11 @@ __global__ __launch_bounds__(1024) void k_propagate_rows(PropArgs a)
         // together
         CProj &P = projs[proj];
         const int64_t nnz = P.nnz, syn_base = P.syn_base, G_base = P.G_base;
-        const int32_t p_inst = P.inst, stdp = P.stdp;
+        const int32_t p_inst = P.inst, stdp = P.stdp, p_grp = P.grp;
         const float gs = gscale[inst];
-        asm volatile("" ::"s"(nnz), "s"(syn_base), "s"(G_base), "s"(p_inst), "s"(stdp), "s"(gs));
+        asm volatile("" ::"s"(nnz), "s"(syn_base), "s"(G_base), "s"(p_inst), "s"(stdp), "s"(gs), "s"(p_grp));
         if (k0 < 0 || k1 > nnz || k0 > k1 || p_inst != inst) return;   // malformed item
+        if (GRP && p_grp && a.n_grp > 0) return;                         // delivered in row groups
         const double s = (double)gs * kFixOne;
         const int32_t *col = a.col_pool + syn_base;
         float *w = a.w_pool + syn_base;
@@ -1356,7 +1492,16 @@ hipError_t launch_neuron(const NeuronArgs &a, int block, hipStream_t s, hipEvent
 hipError_t launch_propagate(const PropArgs &a, int blocks, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.mode == kModeRows) {
-        SNN_LAUNCH(k_propagate_rows, dim3(blocks), dim3(block), s, e0, e1, a);
+        if (a.n_grp > 0) {
+            // grouped mode: a kGrpTile tile of int64 per wavefront
+            const size_t lds = 8 * (size_t)kGrpTile * (size_t)(block / kWave);
+            if (e0)
+                hipExtLaunchKernelGGL(k_propagate_rows<true>, dim3(blocks), dim3(block), lds, s, e0, e1, 0, a);
+            else
+                hipLaunchKernelGGL(k_propagate_rows<true>, dim3(blocks), dim3(block), lds, s, a);
+        } else {
+            SNN_LAUNCH(k_propagate_rows<false>, dim3(blocks), dim3(block), s, e0, e1, a);
+        }
         return hipGetLastError();
     }
     // the tiled kernel runs kPropWaves wavefronts per block

@@ -185,6 +185,8 @@ struct snn_net {
     uint32_t *d_pull_d;      // their one-byte row deltas, [packet][64]
     int32_t *d_pull_r0;      // [unit][64] each lane's row before the unit's first entry
     int32_t *d_pull_perm;    // each copied weight's position in the weight pool (-1: padding or bridge)
+    int2 *d_grp_proj;        // grouped mode: (projection, rows per group) of those delivered in groups
+    int64_t n_grp;
     int64_t pull_count;      // packets
     uint32_t *pullf;     // arena: [2][n_segs]  populations delivered by pulling
     uint32_t *awcnt;     // arena: [2][n_segs]
@@ -336,7 +338,7 @@ NeuronArgs neuron_args(snn_net *net)
     a.substeps = net->substeps;
     a.hs = net->dt / net->substeps;
     a.st = net->st;
-    a.mode = net->launch.mode;
+    a.mode = net->launch.mode == kModeGrouped ? kModeRows : net->launch.mode;
     a.awcnt = net->awcnt;
     a.scnt = net->scnt;
     a.awl = net->awl;
@@ -361,7 +363,9 @@ NeuronArgs neuron_args(snn_net *net)
 PropArgs prop_args(snn_net *net)
 {
     PropArgs p{};
-    p.mode = net->launch.mode;
+    p.mode = net->launch.mode == kModeGrouped ? kModeRows : net->launch.mode;
+    p.grp_proj = net->d_grp_proj;
+    p.n_grp = net->launch.mode == kModeGrouped ? net->n_grp : 0;
     p.projs = net->d_projs;
     p.segs = net->d_segs;
     p.queue = net->queue;
@@ -1080,6 +1084,23 @@ int snn_create(const snn_config *cfg, snn_net **out)
     }
     net->n_units = (int64_t)units.size();
     net->d_units = (int4 *)dev_alloc(net, sizeof(int4) * std::max<size_t>(units.size(), 1));
+    // grouped mode: every non-plastic projection onto at most kGrpTile neurons,
+    // at most kGrpDense of all (pre, post) pairs connected, whose mean row
+    // length allows two rows or more per group
+    std::vector<int2> grp;
+    for (size_t q = 0; q < net->projs.size(); ++q) {
+        Proj &P = net->projs[q];
+        P.grp = 0;
+        if (P.stdp || P.n_post <= 0 || P.n_post > kGrpTile || P.nnz <= 0 || P.pre_words <= 0 || P.n_pre <= 0)
+            continue;
+        if ((double)P.nnz > kGrpDense * (double)P.n_pre * (double)P.n_post) continue;
+        const int64_t k = std::min<int64_t>(kGrpRows, (int64_t)kGrpSyn * P.n_pre / P.nnz);
+        if (k < 2) continue;
+        P.grp = 1;
+        grp.push_back(make_int2((int)q, (int)k));
+    }
+    net->n_grp = (int64_t)grp.size();
+    net->d_grp_proj = (int2 *)dev_alloc(net, sizeof(int2) * std::max<size_t>(grp.size(), 1));
     net->d_qb_base = (int64_t *)dev_alloc(net, 8 * (size_t)(kQBuckets + 1));
     net->pull_count = pull_total;
     net->n_pull_units = (int64_t)pull_units.size();
@@ -1097,7 +1118,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
     if (!net->d_arena || !net->d_segs || !net->d_projs || !net->d_wave_seg || !net->d_rp || !net->d_col || !net->d_w ||
         !net->d_cp || !net->d_csc_row || !net->d_csc_pos || !net->d_gscale || !net->d_tp || !net->d_partial || !net->d_pflag ||
         !net->d_units || !net->d_pull_units || !net->d_pull_part || !net->d_pull_slices || !net->d_pull_col || !net->d_pull_w ||
-        !net->d_pull_d || !net->d_pull_r0 || !net->d_pull_perm || !net->d_qb_base)
+        !net->d_pull_d || !net->d_pull_r0 || !net->d_pull_perm || !net->d_qb_base || !net->d_grp_proj)
         return bail(fail(SNN_ENOMEM, "device allocation failed"));
     char *A = net->d_arena;
     float **st_ptrs[8] = {&net->vh, &net->vl, &net->mh, &net->ml, &net->hh, &net->hl, &net->nh, &net->nl};
@@ -1148,6 +1169,7 @@ int snn_create(const snn_config *cfg, snn_net **out)
         if ((rc = up(net->d_units, units.data(), sizeof(int4) * units.size()))) return bail(rc);
         if ((rc = up(net->d_pull_units, pull_units.data(), sizeof(PullUnit) * pull_units.size()))) return bail(rc);
         if ((rc = up(net->d_pull_slices, pull_red.data(), sizeof(PullSlice) * pull_red.size()))) return bail(rc);
+        if ((rc = up(net->d_grp_proj, grp.data(), sizeof(int2) * grp.size()))) return bail(rc);
     }
     if ((rc = up(net->d_segs, net->segs.data(), sizeof(Seg) * net->segs.size()))) return bail(rc);
     if ((rc = up(net->d_projs, net->projs.data(), sizeof(Proj) * net->projs.size()))) return bail(rc);
@@ -1608,6 +1630,7 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
     st.npull[slot] = np;
     st.npull[slot ^ 1] = 0;
     st.qcnt[slot] = (uint32_t)items.size();
+    st.grp_off[slot] = 0;   // the groups deliver S(t-1) from its bitmask words
     if (ltp_seg >= 0) {
         const Seg &S = net->segs[ltp_seg];
         const uint32_t n = st.lcnt[slot];
@@ -1633,13 +1656,16 @@ static int rebuild_pending(snn_net *net, int ltp_seg, const uint8_t *ltp_flags)
 
 // Both queue slots empty and no population marked for pulling: fused steps
 // neither fill nor reset them, so a count left from before fused mode must not
-// survive a switch in either direction.
+// survive a switch in either direction.  The row groups of grouped mode,
+// which read the spike words rather than the queue, are told that both slots
+// are done.
 static int clear_queues(snn_net *net)
 {
     int rc;
     StepState st;
     if ((rc = d2h(net, &st, net->st, sizeof st))) return rc;
     st.qcnt[0] = st.qcnt[1] = 0;
+    st.grp_off[0] = st.grp_off[1] = 1;
     st.lcnt[0] = st.lcnt[1] = 0;
     st.npull[0] = st.npull[1] = 0;
     if ((rc = clear_qbuckets(net, -1))) return rc;
@@ -1827,8 +1853,10 @@ int snn_set_launch(snn_net *net, const snn_launch *in)
     if (in->prop_blocks < 1 || in->prop_blocks > 65536) return fail(SNN_EINVAL, "prop_blocks must be in [1, 65536]");
     if (in->chunk < kMinChunk || in->chunk % kWave || in->chunk > (1 << 20))
         return fail(SNN_EINVAL, "chunk must be a multiple of 64 in [64, 2^20]");
-    if (in->mode != kModeRows && in->mode != kModeTiles && in->mode != kModeFused)
-        return fail(SNN_EINVAL, "mode must be 0 (rows), 1 (tiles) or 2 (fused)");
+    if (in->mode != kModeRows && in->mode != kModeTiles && in->mode != kModeFused && in->mode != kModeGrouped)
+        return fail(SNN_EINVAL, "mode must be 0 (rows), 1 (tiles), 2 (fused) or 3 (grouped)");
+    if (in->mode == kModeGrouped && in->prop_block > 512)
+        return fail(SNN_EINVAL, "mode 3 (grouped) needs prop_block <= 512 (an 8 KiB LDS tile per wavefront)");
     if (in->mode == kModeFused && net->plastic)
         return fail(SNN_EINVAL, "mode 2 (fused) needs a network without plastic projections");
     const snn_launch prev = net->launch;
@@ -2334,13 +2362,16 @@ int snn_autotune_internal(snn_net *net, const char *cache)
     int rc = snn_time_steps(net, steps, &best_ms);   // also warms up
     if (rc) return rc;
     if ((rc = snn_time_steps(net, steps, &best_ms))) return rc;
-    const int md[] = {kModeRows, kModeTiles, kModeFused};
+    // modes: rows, tiles, fused (no plastic projections), grouped (some projection to group)
+    int md[4] = {kModeRows, kModeTiles, 0, 0}, n_md = 2;
+    if (!net->plastic) md[n_md++] = kModeFused;
+    if (net->n_grp > 0) md[n_md++] = kModeGrouped;
     const int nb[] = {64, 128, 256, 512, 1024};
     const int pb[] = {256, 512, 1024, 2048, 4096, 8192};
     const int ck[] = {128, 256, 512, 1024, 2048};
     for (int dim = 0; dim < 4; ++dim) {
         const int *vals = dim == 0 ? md : dim == 1 ? nb : dim == 2 ? pb : ck;
-        const int nv = dim == 0 ? (net->plastic ? 2 : 3) : dim == 1 ? 5 : dim == 2 ? 6 : 5;
+        const int nv = dim == 0 ? n_md : dim == 1 ? 5 : dim == 2 ? 6 : 5;
         snn_launch cur_best = best;
         for (int k = 0; k < nv; ++k) {
             snn_launch L = best;

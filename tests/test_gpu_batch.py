@@ -104,14 +104,14 @@ def test_set_gscale_matches_oracle(snn):
 
 
 def test_delivery_modes_agree_on_a_batch(snn):
-    """Rows, tile and fused delivery give the same bits on a batch of uneven
-    instances (many segments and projections), also after g_scale and weight
-    changes with spikes pending."""
+    """Rows, tile, fused and grouped delivery give the same bits on a batch of
+    uneven instances (many segments and projections), also after g_scale and
+    weight changes with spikes pending."""
     import torch
     say("case: delivery modes on a batch of 6 instances")
     spec = netgen.make_config(4, n_instances=6, scale=0.1)
     nets = []
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         n = snn.Network(spec)
         n.set_launch(mode=mode)
         n.step(90)
@@ -313,6 +313,32 @@ def test_full_size_pull_delivery_bitwise(snn):
             assert np.array_equal(a.conductance(k, q), b.conductance(k, q)), (k, q)
     for k in pick:
         assert float(np.abs(a.conductance(k, 0)).sum()) > 0.0 and float(np.abs(a.conductance(k, 1)).sum()) > 0.0
+    a.close()
+    b.close()
+
+
+def test_full_size_grouped_delivery_bitwise(snn):
+    """Workload 4 at its full size in grouped mode (its 512 projections onto
+    at most 1024 neurons delivered in row groups) against row mode: 300 live
+    steps after a 300-step pre-roll leave every instance's spike counts,
+    voltages and conductances bit for bit the same."""
+    spec = netgen.make_config(4)
+    say("case: workload 4 full size, grouped vs rows over 300 live steps")
+    nets = []
+    for mode in (3, 0):
+        net = snn.Network(spec)
+        net.set_launch(mode=0, prop_blocks=4096)
+        net.step(300)
+        net.set_launch(mode=mode, prop_blocks=4096)
+        net.step(300)
+        nets.append(net)
+    a, b = nets
+    for k, inst in enumerate(spec["instances"]):
+        for p in range(len(inst["pops"])):
+            assert np.array_equal(a.spikes(k, p), b.spikes(k, p)), (k, p)
+        assert np.array_equal(a.state(k, 2, snn.V), b.state(k, 2, snn.V)), k
+        for q in range(len(inst["projs"])):
+            assert np.array_equal(a.conductance(k, q), b.conductance(k, q)), (k, q)
     a.close()
     b.close()
 

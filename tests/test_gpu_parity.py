@@ -56,11 +56,13 @@ def test_poisson_raster_bitwise(snn):
     net.close()
 
 
+@pytest.mark.parametrize("mode", [0, 3])
 @pytest.mark.parametrize("seed", range(6))
-def test_propagation_bitwise_integer_weights(snn, seed):
+def test_propagation_bitwise_integer_weights(snn, seed, mode):
     """G after one step equals the rounded dense product d * (W^T s) on the
-    2^-40 uS grid, bit for bit (integer g makes every order exact)."""
-    say(f"case: propagation seed {seed}")
+    2^-40 uS grid, bit for bit (integer g makes every order exact); by rows
+    and in row groups (every projection here is delivered in groups)."""
+    say(f"case: propagation seed {seed}, mode {mode}")
     spec = netgen.random_tiny(seed, integer_g=True, max_n=200, p=0.4)
     inst = spec["instances"][0]
     rng = np.random.default_rng(100 + seed)
@@ -69,6 +71,7 @@ def test_propagation_bitwise_integer_weights(snn, seed):
     if seed == 4:
         flags = {p: np.zeros_like(f) for p, f in flags.items()}
     net = snn.Network(spec)
+    net.set_launch(mode=mode)
     orc = O.OracleNet(inst)
     for p, f in flags.items():
         net.set_last_spikes(0, p, f)
@@ -81,6 +84,45 @@ def test_propagation_bitwise_integer_weights(snn, seed):
         g_orc = np.rint(orc.G(q) * FIX)
         assert np.array_equal(g_gpu, g_orc), q
     net.close()
+
+
+@pytest.mark.parametrize("frac", [0.0005, 0.02, 0.3, 1.0])
+def test_grouped_delivery_bitwise(snn, frac):
+    """Grouped mode with a pre population of 5000 neurons (79 spike words, two
+    rounds of the word scan, so groups straddle rounds): projections onto
+    1000 and 64 neurons are delivered in row groups, one onto 3000 stays with
+    rows; G after one step equals the oracle's bit for bit, at sparse and
+    dense activity, in several launch shapes (one block taking every group
+    slot in turn, one wavefront per block, eight, the row items split off)."""
+    say(f"case: grouped delivery, 5000 pre neurons, {frac:.2%} spiking")
+    rng = np.random.default_rng(37)
+    n_pre, sizes = 5000, (1000, 3000, 64)
+    pops = [dict(name="A", kind="poisson", n=n_pre, rate_hz=0.0, i_ext=0.0)] + \
+        [dict(name=f"P{k}", kind="hh", n=m, rate_hz=0.0, i_ext=0.0) for k, m in enumerate(sizes)]
+    projs = []
+    for k, m in enumerate(sizes):
+        mask = rng.random((n_pre, m)) < (0.05 if m > 64 else 0.3)
+        rp = np.concatenate([[0], np.cumsum(mask.sum(1))]).astype(np.int32)
+        ci = np.nonzero(mask)[1].astype(np.int32)
+        g = rng.integers(0, 4, ci.size).astype(np.float32)
+        projs.append(dict(pre=0, post=k + 1, row_ptr=rp, col_idx=ci, g=g, e_rev=0.0, tau=1.0, stdp=None))
+    inst = dict(g_scale=1.0, seed=5, pops=pops, projs=projs)
+    spec = dict(dt=0.1, substeps=3, instances=[inst])
+    f = (rng.random(n_pre) < frac).astype(np.uint8)
+    f[4999] = 1   # the last neuron of the last word
+    orc = O.OracleNet(inst)
+    orc.set_last_spikes(0, f)
+    orc.step(1)
+    ref = [np.rint(orc.G(q) * FIX) for q in range(len(projs))]
+    for shape in (dict(), dict(prop_blocks=1), dict(prop_block=64, prop_blocks=7), dict(prop_block=512),
+                  dict(prop_blocks=8192)):
+        net = snn.Network(spec)
+        net.set_launch(mode=3, **shape)
+        net.set_last_spikes(0, 0, f)
+        net.step(1)
+        for q in range(len(projs)):
+            assert np.array_equal(net.conductance(0, q) * FIX, ref[q]), (shape, q)
+        net.close()
 
 
 def _upstroke_state(n, spiking):
@@ -626,6 +668,45 @@ def test_fused_mode_agrees_bitwise_through_switches(snn, workload, scale):
     _same_network_state(ref, fus, spec)
     ref.close()
     fus.close()
+
+
+@pytest.mark.parametrize("workload,scale", [(1, 0.5), (2, 0.25)])
+def test_grouped_mode_agrees_bitwise_through_switches(snn, workload, scale):
+    """Mode 3 (small projections delivered in row groups through LDS tiles)
+    gives the same bits as row mode, also across switches to and from every
+    other mode with work pending, with odd step counts and several launch
+    shapes."""
+    say(f"case: grouped mode, workload {workload} at scale {scale}")
+    spec = netgen.make_config(workload, scale=scale)
+    ref = snn.Network(spec)
+    grp = snn.Network(spec)
+    grp.set_launch(mode=3)
+    plan = [(77, dict(mode=0)), (51, dict(mode=3, prop_blocks=1)), (33, dict(mode=2)),
+            (41, dict(mode=3, prop_block=64, chunk=64)), (29, dict(mode=1)), (64, dict(mode=3, prop_block=512)),
+            (35, dict(mode=3, neuron_block=1024, prop_blocks=8192))]
+    for i, (n, shape) in enumerate(plan):
+        ref.step(n)
+        grp.step(n)
+        say(f"  phase {i}: {n} steps in mode {grp.launch['mode']}, then {shape}")
+        _same_network_state(ref, grp, spec)
+        grp.set_launch(**shape)
+    ref.step(70)
+    grp.step(70)
+    _same_network_state(ref, grp, spec)
+    ref.close()
+    grp.close()
+
+
+def test_grouped_mode_rejects_wide_blocks(snn):
+    """Grouped mode keeps an 8 KiB LDS tile per wavefront, so blocks of more
+    than 512 threads are refused (the launch is left as it was)."""
+    spec = netgen.make_config(1, scale=0.5)
+    net = snn.Network(spec)
+    with pytest.raises(snn.SNNError):
+        net.set_launch(mode=3, prop_block=1024)
+    net.set_launch(mode=3, prop_block=512)
+    net.step(5)
+    net.close()
 
 
 def test_fused_mode_last_spikes_and_rejection(snn):
