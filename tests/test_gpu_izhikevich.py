@@ -175,9 +175,9 @@ def test_izhikevich_batch_in_every_delivery_mode(snn):
     spike counts equal the oracle's after 600 steps."""
     T = 600
     spec = netgen.izhikevich_calibration_config([100, 300], [0.3, 1.0, 3.0], n_exc=400, n_inh=100, steps=T)
-    say(f"case: batch of {len(spec['instances'])} Izhikevich networks, {T} steps, delivery modes 0/1/2")
+    say(f"case: batch of {len(spec['instances'])} Izhikevich networks, {T} steps, delivery modes 0/1/2/3")
     res = []
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         net = snn.Network(spec)
         net.set_launch(mode=mode)
         net.step(T)
