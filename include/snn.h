@@ -299,7 +299,8 @@ int snn_get_weights(snn_net *net, int32_t inst, int32_t proj, float *out);
 int snn_memory_bytes(const snn_net *net, int64_t *per_proj_bytes);
 
 /* Current / new launch shape; snn_set_launch validates the ranges above
- * (SNN_EINVAL, also for mode 2 on a network with plastic projections).  A
+ * (SNN_EINVAL, also for mode 2 on a network with plastic projections and for
+ * mode 3 with prop_block above 512; the launch is then left as it was).  A
  * change of mode converts the work pending for the next step (delivers it
  * now, or folds fused deliveries into G); results are unchanged.
  * Synchronises when the mode changes. */
